@@ -1,0 +1,75 @@
+"""RBF kernel and the Nystrom method (Sec. 6.1.1, Sec. 6.4).
+
+rbf: K[i, j] = exp(-||x_i - y_j||^2 / (2 sigma^2)).  Reading: the printed
+formula of Sec. 6.1.1 puts sigma^{-2} in the denominator, while the rbf
+listing divides by sigma^2 after halving the squared distance; the listing's
+kernel is used.  The squared distance is formed from the differences
+directly (the listing's expanded form cancels badly in low precision).
+
+Nystrom (Sec. 6.4 and its listing): S = c sorted uniform indices drawn
+without replacement; C = K[:, S]; W = C[S, :]; W = U Lam U^T;
+keep the top k = ceil(0.8 c) eigenpairs; L = C U_k Lam_k^{-1/2} so that
+K ~ L L^T = C W_k^+ C^T.  Reading: the footnote writes Lam^{-1}; only the
+listing's Lam^{-1/2} gives L L^T = C W_k^+ C^T.
+
+Gaussian variant: C = K Omega with Omega (n x c) i.i.d. N(0, 1) and
+W = Omega^T C = Omega^T K Omega (the W = S^T K S form of Sec. 6.4 with a
+projection in place of the selection).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import rng
+
+
+def rbf(X1, X2, sigma: float):
+    X1 = np.asarray(X1, dtype=np.float64)
+    X2 = np.asarray(X2, dtype=np.float64)
+    D2 = ((X1[:, None, :] - X2[None, :, :]) ** 2).sum(axis=2)
+    return np.exp(-D2 / (2.0 * sigma * sigma))
+
+
+def default_rank(c: int) -> int:
+    return int(math.ceil(0.8 * c))
+
+
+def sample(n: int, c: int, seed: int):
+    return rng.sample_indices(n, c, rng.TAG_NYSTROM_SAMPLE, seed)
+
+
+def _factor(C, W, k):
+    lam, U = np.linalg.eigh(W)
+    order = np.argsort(lam)[::-1]
+    lam = lam[order]
+    U = U[:, order]
+    L = C @ (U[:, :k] / np.sqrt(lam[:k])[None, :])
+    return L, lam
+
+
+def nystrom(X, sigma: float, c: int, seed: int, k=None):
+    """Column-sampling Nystrom; returns (L (n x k), S, C, W, eigenvalues)."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    k = default_rank(c) if k is None else int(k)
+    S = sample(n, c, seed)
+    C = rbf(X, X[S], sigma)
+    W = C[S, :]
+    L, lam = _factor(C, W, k)
+    return L, S, C, W, lam
+
+
+def nystrom_gaussian(X, sigma: float, c: int, seed: int, k=None, fp64=True):
+    """Gaussian-projection variant; returns (L, Omega, C, W, eigenvalues)."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    k = default_rank(c) if k is None else int(k)
+    Om = rng.gaussian_matrix(n, c, rng.TAG_GAUSS_NYSTROM, seed, fp64)
+    K = rbf(X, X, sigma)
+    C = K @ Om
+    W = Om.T @ C
+    L, lam = _factor(C, W, k)
+    return L, Om, C, W, lam
