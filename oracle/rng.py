@@ -13,7 +13,7 @@ Generator
     Weyl key increments 0x9E3779B9 / 0xBB67AE85.  Key = (lo32(seed),
     hi32(seed)); counter = (lo32(i), hi32(i), tag, j).
 
-Per-row word (CountSketch, SRHT signs)
+Per-row word (CountSketch)
     word(i) = philox((i >> 2), tag, 0)[i & 3]  -- one 32-bit word per row.
 
 CountSketch (Alg. 3.1: a uniform bucket l in [s] and a uniform sign g)
@@ -21,7 +21,8 @@ CountSketch (Alg. 3.1: a uniform bucket l in [s] and a uniform sign g)
     g_i = +1 if word(i) is even else -1
 
 SRHT diagonal D (Sec. 3.2.2: entries uniform on {+1,-1})
-    d_i = +1 if word(i) (tag SRHT) is even else -1
+    d_i = -1 if bit (i mod 128) of philox((i >> 7), TAG_SRHT, 0) is set
+    (bit b in word b >> 5 at position b & 31), else +1
 
 Sampling without replacement (SRHT row sampling, Sec. 3.2.2; uniform column
 selection, Sec. 3.3.1 and Sec. 6.4)
@@ -121,9 +122,19 @@ def countsketch_hash_sign(m: int, s: int, seed: int):
 
 
 def srht_signs(m: int, seed: int):
-    """Diagonal of D (Sec. 3.2.2): uniform signs over the m real rows."""
-    w = row_words(np.arange(m, dtype=np.uint64), TAG_SRHT_SIGN, seed)
-    return np.where((w & np.uint64(1)) == 0, 1, -1).astype(np.int64)
+    """Diagonal of D (Sec. 3.2.2): uniform signs over the m real rows.
+
+    d_i is bit (i mod 128) of the 128-bit Philox block at counter
+    (i div 128, TAG_SRHT_SIGN, 0); bit b sits in word b div 32 at position
+    b mod 32; a set bit means -1.
+    """
+    i = np.arange(m, dtype=np.uint64)
+    lo, hi = _split64(i >> np.uint64(7))
+    w = philox4x32_10(lo, hi, TAG_SRHT_SIGN, 0, seed)
+    bit = i & np.uint64(127)
+    word = np.choose((bit >> np.uint64(5)).astype(np.int64), w)
+    b = (word >> (bit & np.uint64(31))) & np.uint64(1)
+    return np.where(b == 0, 1, -1).astype(np.int64)
 
 
 def ceil_log2(n: int) -> int:
