@@ -1,0 +1,166 @@
+/*
+ * rmm.h -- C ABI of the MI355X (gfx950) randomized sketching library.
+ *
+ * Operations follow the problem statements of S. Wang, "A Practical Guide to
+ * Randomized Matrix Computations with MATLAB Implementations"
+ * (arXiv:1505.07570):
+ *   - sketching C = S^T A                     (Ch. 3, Sec. 3.2; row form of eq. 4.2)
+ *   - randomized k-SVD with subspace iteration (Alg. 5.2, power step of Alg. 5.1)
+ *   - sketch-and-solve least squares          (eq. 4.2, Sec. 4.2)
+ *   - exact least squares x* = A^+ b           (Sec. 4.1), the "plain" comparator
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  Layout     Matrices are column-major (BLAS convention): element (i, j) of
+ *             an r x c matrix X with leading dimension ldx >= max(1, r) is
+ *             X[i + j * ldx].
+ *  Memory     Every pointer argument named A, b, C, U, V, sigma, x, resid,
+ *             status, out is DEVICE memory owned by the caller.  The library
+ *             never allocates or frees device memory inside a call: scratch
+ *             space is the caller-owned workspace registered with
+ *             rmm_set_workspace, sized with the matching *_workspace query.
+ *  Streams    All work is enqueued on the stream set by rmm_set_stream
+ *             (default: the null stream) and is asynchronous with respect to
+ *             the host; no call synchronizes the device.
+ *  Errors     Every call returns RMM_OK (0) or a negative rmm_status.
+ *             Argument errors are detected on the host before anything is
+ *             enqueued.  Numerical conditions found on the device (rank
+ *             deficiency, breakdown of the Gram-based orthonormalization,
+ *             Jacobi sweeps exhausted) are OR-ed into the int32 status word
+ *             passed by the caller (RMM_STATUS_* flags), which is set to 0
+ *             at the start of the call.
+ *  Randomness Every random quantity is a pure function of (seed, stream tag,
+ *             index) through Philox4x32-10 (Salmon et al., SC'11); results
+ *             are bitwise reproducible run to run for the same arguments.
+ *  Threads    A handle holds a stream, a workspace and cached device
+ *             properties; use one handle per host thread.
+ */
+#ifndef RMM_H
+#define RMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmm_ctx* rmm_handle;
+
+typedef enum { RMM_F32 = 0, RMM_F64 = 1 } rmm_dtype;
+
+/* Sketch families of Sec. 3.2. */
+typedef enum {
+  RMM_GAUSSIAN = 0,    /* S = G / sqrt(s), G i.i.d. N(0,1)            (Sec. 3.2.1) */
+  RMM_SRHT = 1,        /* S = s^{-1/2} D H_N P, zero padding to N = 2^ceil(log2 m)
+                          (Sec. 3.2.2)                                             */
+  RMM_COUNTSKETCH = 2  /* one +-1 per row of S, uniform bucket       (Sec. 3.2.3, Alg. 3.1) */
+} rmm_sketch_kind;
+
+/* Operand precision of the pass-over-A GEMMs of rmm_rsvd. */
+typedef enum { RMM_PREC_NATIVE = 0, RMM_PREC_BF16 = 1, RMM_PREC_FP8 = 2 } rmm_precision;
+
+typedef enum {
+  RMM_OK = 0,
+  RMM_ERR_INVALID_ARG = -1,        /* null pointer, bad size or leading dimension */
+  RMM_ERR_WORKSPACE_TOO_SMALL = -2,
+  RMM_ERR_HIP = -3,                /* a HIP runtime call failed */
+  RMM_ERR_UNSUPPORTED = -4         /* valid but unsupported combination */
+} rmm_status;
+
+/* device-side status flags */
+#define RMM_STATUS_RANK_DEFICIENT 1  /* sketched LSR: min|R_jj| <= 10 s eps max|R_jj| */
+#define RMM_STATUS_QR_FALLBACK 2     /* Gram matrix numerically singular: eigen-based
+                                        orthonormalization dropped directions */
+#define RMM_STATUS_NOT_CONVERGED 4   /* Jacobi sweep limit reached */
+
+/* ---- handle ------------------------------------------------------------ */
+
+/* Creates a handle bound to HIP device `device`.  Allocates host memory only. */
+int rmm_create(rmm_handle* h, int device);
+int rmm_destroy(rmm_handle h);
+/* Sets the hipStream_t (passed as void*) on which later calls enqueue work. */
+int rmm_set_stream(rmm_handle h, void* hip_stream);
+/* Registers caller-owned device scratch memory (256-byte aligned). */
+int rmm_set_workspace(rmm_handle h, void* dptr, size_t bytes);
+/* Human-readable name of an rmm_status code. */
+const char* rmm_strerror(int code);
+/* Number of compute units of the handle's device. */
+int rmm_device_cus(rmm_handle h, int* cus);
+
+/* ---- sketching (Ch. 3) ----------------------------------------------------
+ * C = S^T [A | b]: A is m x n (lda >= m), b an optional extra column of
+ * length m (NULL for none).  C is s x n' with n' = n + (b != NULL), ldc >= s.
+ * The extra column is sketched with the same S (the joint sketch of [A, b]
+ * used by InexactLSR, Sec. 4.2.1).  S is m x s:
+ *   GAUSSIAN     S[i, r] = Omega[i, r] / sqrt(s), Omega from stream tag 4
+ *   SRHT         S[i, r] = d_i H[i, idx_r] / sqrt(s); H Sylvester-ordered
+ *                (H[i, r] = (-1)^popcount(i & r)); idx = sorted sample of s
+ *                distinct rows of [0, N); requires s <= N
+ *   COUNTSKETCH  S[i, h_i] = g_i, zero elsewhere; no scaling
+ * m = 0 yields C = 0.  Requires n >= 0, s >= 1. */
+int rmm_sketch_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,
+                         int64_t m, int64_t n_total, int64_t s, size_t* bytes);
+int rmm_sketch(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m,
+               int64_t n, const void* A, int64_t lda, const void* b, int64_t s,
+               uint64_t seed, void* C, int64_t ldc);
+
+/* ---- randomized k-SVD (Alg. 5.2 with the subspace iteration of Alg. 5.1) --
+ * A (m x n) ~ U diag(sigma) V^T with U m x k (ldu >= m), sigma k entries,
+ * V n x k (ldv >= n), all in dtype dt.  l = k + p <= min(m, n); q >= 0 is the
+ * number of A A^T applications, the basis being re-orthonormalized after
+ * every product.  Singular values are descending; each u_i has its
+ * largest-magnitude entry positive.  prec selects the operand precision of
+ * the passes over A (RMM_PREC_NATIVE: dt itself; BF16/FP8 need dt = RMM_F32
+ * and accumulate in FP32); orthonormalization and the small SVD are FP64.
+ * status: device int32, see RMM_STATUS_*. */
+int rmm_rsvd_workspace(rmm_handle h, rmm_dtype dt, rmm_precision prec,
+                       int64_t m, int64_t n, int64_t k, int64_t p, size_t* bytes);
+int rmm_rsvd(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m,
+             int64_t n, const void* A, int64_t lda, int64_t k, int64_t p,
+             int64_t q, uint64_t seed, void* U, int64_t ldu, void* sigma,
+             void* V, int64_t ldv, int32_t* status);
+
+/* ---- least squares (Ch. 4) --------------------------------------------------
+ * Sketch-and-solve (eq. 4.2): x~ = argmin ||S^T (A x - b)||_2 with one S of
+ * the given kind applied to [A | b] (A m x d, lda >= m; b length m; d <= s).
+ * The s x (d+1) sketch is promoted to FP64 and solved by CholeskyQR2;
+ * x (d doubles) and, if resid != NULL, resid = ||A x~ - b||_2 (one double)
+ * are written in FP64.  status: RMM_STATUS_RANK_DEFICIENT when the sketched
+ * system is numerically rank deficient. */
+int rmm_lsr_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,
+                      int64_t m, int64_t d, int64_t s, size_t* bytes);
+int rmm_sketched_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,
+                     int64_t m, int64_t d, const void* A, int64_t lda,
+                     const void* b, int64_t s, uint64_t seed, double* x,
+                     double* resid, int32_t* status);
+/* Exact solution x* = A^+ b (Sec. 4.1) by FP64 CholeskyQR2 of A itself: the
+ * "plain" comparator. Same argument conventions as rmm_sketched_lsr. */
+int rmm_plain_lsr_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d,
+                            size_t* bytes);
+int rmm_plain_lsr(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d,
+                  const void* A, int64_t lda, const void* b, double* x,
+                  double* resid, int32_t* status);
+
+/* ---- random quantities (test hooks; Sec. 3.2, Alg. 3.1) ------------------- */
+/* CountSketch buckets h_i in [0, s) for rows 0..m-1 (int32, device). */
+int rmm_sketch_hashes(rmm_handle h, int64_t m, int64_t s, uint64_t seed,
+                      int32_t* out);
+/* Row signs (+1 / -1, int8, device) of CountSketch (kind = RMM_COUNTSKETCH)
+ * or of the SRHT diagonal D (kind = RMM_SRHT). */
+int rmm_sketch_signs(rmm_handle h, rmm_sketch_kind kind, int64_t m,
+                     uint64_t seed, int8_t* out);
+/* SRHT sample: s sorted distinct indices of [0, N), N = 2^ceil(log2 m),
+ * int64, device.  Requires 1 <= s <= min(N, 8192). */
+int rmm_srht_indices(rmm_handle h, int64_t m, int64_t s, uint64_t seed,
+                     int64_t* out);
+/* Gaussian matrix Omega (rows x cols, ld >= rows) of stream `stream`
+ * (0: sketch, 1: rsvd, 2: Nystrom) in dtype dt. */
+int rmm_gaussian(rmm_handle h, rmm_dtype dt, int stream, int64_t rows,
+                 int64_t cols, uint64_t seed, void* out, int64_t ld);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMM_H */

@@ -119,8 +119,11 @@ def sketch_matrix(kind: int, m: int, s: int, seed: int, fp64: bool = True,
     if kind == SRHT:
         return srht_matrix(m, s, seed, cols)
     if kind == COUNTSKETCH:
-        S = countsketch_matrix(m, s, seed)
-        return S if cols is None else S[:, np.asarray(cols)]
+        if cols is None:
+            return countsketch_matrix(m, s, seed)
+        h, g = rng.countsketch_hash_sign(m, s, seed)
+        cols = np.asarray(cols)
+        return np.where(h[:, None] == cols[None, :], g[:, None], 0).astype(np.float64)
     raise ValueError("unknown sketch kind")
 
 

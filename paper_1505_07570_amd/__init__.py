@@ -1,0 +1,289 @@
+"""Python binding of librmm (randomized sketching on MI355X / gfx950).
+
+Argument marshalling only: every operation runs in the HIP kernels of
+``librmm.so``; PyTorch provides device memory and the current stream.  The
+binding fails loudly when the library has not been built.
+
+Matrices are torch tensors on the GPU in column-major layout
+(``stride(0) == 1``), e.g. ``torch.empty(n, m, device="cuda").t()``; use
+:func:`colmajor` to convert.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "librmm.so")
+
+GAUSSIAN, SRHT, COUNTSKETCH = 0, 1, 2
+KINDS = {"gaussian": GAUSSIAN, "srht": SRHT, "countsketch": COUNTSKETCH}
+PREC_NATIVE, PREC_BF16, PREC_FP8 = 0, 1, 2
+F32, F64 = 0, 1
+
+STATUS_RANK_DEFICIENT = 1
+STATUS_QR_FALLBACK = 2
+STATUS_NOT_CONVERGED = 4
+
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int
+
+
+class RmmError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {_strerror(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded librmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_1505_07570_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "rmm_create": [ctypes.POINTER(_vp), _i32],
+            "rmm_destroy": [_vp],
+            "rmm_set_stream": [_vp, _vp],
+            "rmm_set_workspace": [_vp, _vp, ctypes.c_size_t],
+            "rmm_device_cus": [_vp, ctypes.POINTER(_i32)],
+            "rmm_sketch_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_sketch": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _i64],
+            "rmm_rsvd_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_rsvd": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _i64, _i64, _i64, _u64,
+                         _vp, _i64, _vp, _vp, _i64, _vp],
+            "rmm_lsr_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_sketched_lsr": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _vp, _vp],
+            "rmm_plain_lsr_workspace": [_vp, _i32, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_plain_lsr": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
+            "rmm_sketch_hashes": [_vp, _i64, _i64, _u64, _vp],
+            "rmm_sketch_signs": [_vp, _i32, _i64, _u64, _vp],
+            "rmm_srht_indices": [_vp, _i64, _i64, _u64, _vp],
+            "rmm_gaussian": [_vp, _i32, _i32, _i64, _i64, _u64, _vp, _i64],
+        }
+        for name, args in sig.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.argtypes = args
+                f.restype = _i32
+        L.rmm_strerror.argtypes = [_i32]
+        L.rmm_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().rmm_strerror(code).decode()
+    except Exception:  # pragma: no cover - library missing
+        return "error"
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise RmmError(code, what)
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _kind(kind) -> int:
+    if isinstance(kind, str):
+        return KINDS[kind.lower()]
+    return int(kind)
+
+
+def colmajor(x: torch.Tensor) -> torch.Tensor:
+    """Column-major copy (or the tensor itself if it already is one)."""
+    if x.dim() == 1:
+        return x.contiguous()
+    if x.stride(0) == 1 and x.stride(1) >= max(1, x.shape[0]):
+        return x
+    return x.t().contiguous().t()
+
+
+def _ld(x: torch.Tensor) -> int:
+    if x.dim() == 1:
+        return max(1, x.shape[0])
+    if x.stride(0) != 1 and x.shape[0] > 1:
+        raise ValueError("matrix must be column-major (stride(0) == 1)")
+    return max(1, x.stride(1), x.shape[0])
+
+
+def _ptr(x):
+    return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+class Handle:
+    """A library handle bound to one device, its stream and a workspace."""
+
+    def __init__(self, device=None):
+        device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self.device = device
+        h = ctypes.c_void_p()
+        _check(lib().rmm_create(ctypes.byref(h), device.index or 0), "rmm_create")
+        self._h = h
+        self._ws = None
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().rmm_destroy(self._h)
+        except Exception:
+            pass
+
+    @property
+    def cus(self) -> int:
+        v = ctypes.c_int()
+        _check(lib().rmm_device_cus(self._h, ctypes.byref(v)), "rmm_device_cus")
+        return v.value
+
+    def _prepare(self, nbytes: int):
+        """Bind the current torch stream and a workspace of >= nbytes."""
+        stream = torch.cuda.current_stream(self.device)
+        _check(lib().rmm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "rmm_set_stream")
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        _check(lib().rmm_set_workspace(self._h, _ptr(self._ws), self._ws.numel()),
+               "rmm_set_workspace")
+
+    def reserve(self, nbytes: int):
+        self._prepare(nbytes)
+
+    # ---- sketching -------------------------------------------------------
+    def sketch_workspace(self, dtype, kind, m, ncols, s) -> int:
+        out = ctypes.c_size_t()
+        dt = F32 if dtype == torch.float32 else F64
+        _check(lib().rmm_sketch_workspace(self._h, dt, _kind(kind), m, ncols, s, ctypes.byref(out)),
+               "rmm_sketch_workspace")
+        return out.value
+
+    def sketch(self, A: torch.Tensor, s: int, kind, seed: int, b: torch.Tensor = None,
+               out: torch.Tensor = None) -> torch.Tensor:
+        """C = S^T [A | b] (s x n'), column-major, same dtype as A."""
+        m, n = A.shape
+        ncols = n + (1 if b is not None else 0)
+        if out is None:
+            out = torch.empty(ncols, s, dtype=A.dtype, device=A.device).t()
+        ws = self.sketch_workspace(A.dtype, kind, m, ncols, s)
+        self._prepare(ws)
+        _check(lib().rmm_sketch(self._h, _dt(A), _kind(kind), m, n, _ptr(A), _ld(A), _ptr(b), s,
+                                seed, _ptr(out), _ld(out)), "rmm_sketch")
+        return out
+
+    # ---- randomized SVD ----------------------------------------------------
+    def rsvd(self, A: torch.Tensor, k: int, p: int, q: int, seed: int, prec: int = PREC_NATIVE):
+        m, n = A.shape
+        dt = _dt(A)
+        U = torch.empty(k, m, dtype=A.dtype, device=A.device).t()
+        V = torch.empty(k, n, dtype=A.dtype, device=A.device).t()
+        sig = torch.empty(k, dtype=A.dtype, device=A.device)
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_rsvd_workspace(self._h, dt, prec, m, n, k, p, ctypes.byref(ws)),
+               "rmm_rsvd_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_rsvd(self._h, dt, prec, m, n, _ptr(A), _ld(A), k, p, q, seed, _ptr(U),
+                              _ld(U), _ptr(sig), _ptr(V), _ld(V), _ptr(status)), "rmm_rsvd")
+        return U, sig, V, status
+
+    # ---- least squares -------------------------------------------------------
+    def sketched_lsr(self, A: torch.Tensor, b: torch.Tensor, s: int, kind, seed: int,
+                     residual: bool = True):
+        m, d = A.shape
+        dt = _dt(A)
+        x = torch.empty(d, dtype=torch.float64, device=A.device)
+        res = torch.empty(1, dtype=torch.float64, device=A.device) if residual else None
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_lsr_workspace(self._h, dt, _kind(kind), m, d, s, ctypes.byref(ws)),
+               "rmm_lsr_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_sketched_lsr(self._h, dt, _kind(kind), m, d, _ptr(A), _ld(A), _ptr(b), s,
+                                      seed, _ptr(x), _ptr(res), _ptr(status)), "rmm_sketched_lsr")
+        return x, res, status
+
+    def plain_lsr(self, A: torch.Tensor, b: torch.Tensor, residual: bool = True):
+        m, d = A.shape
+        dt = _dt(A)
+        x = torch.empty(d, dtype=torch.float64, device=A.device)
+        res = torch.empty(1, dtype=torch.float64, device=A.device) if residual else None
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_plain_lsr_workspace(self._h, dt, m, d, ctypes.byref(ws)),
+               "rmm_plain_lsr_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_plain_lsr(self._h, dt, m, d, _ptr(A), _ld(A), _ptr(b), _ptr(x), _ptr(res),
+                                   _ptr(status)), "rmm_plain_lsr")
+        return x, res, status
+
+    # ---- random quantities ---------------------------------------------------
+    def sketch_hashes(self, m: int, s: int, seed: int) -> torch.Tensor:
+        out = torch.empty(max(m, 1), dtype=torch.int32, device=self.device)[:m]
+        self._prepare(0)
+        _check(lib().rmm_sketch_hashes(self._h, m, s, seed, _ptr(out)), "rmm_sketch_hashes")
+        return out
+
+    def sketch_signs(self, kind, m: int, seed: int) -> torch.Tensor:
+        out = torch.empty(max(m, 1), dtype=torch.int8, device=self.device)[:m]
+        self._prepare(0)
+        _check(lib().rmm_sketch_signs(self._h, _kind(kind), m, seed, _ptr(out)), "rmm_sketch_signs")
+        return out
+
+    def srht_indices(self, m: int, s: int, seed: int) -> torch.Tensor:
+        out = torch.empty(s, dtype=torch.int64, device=self.device)
+        self._prepare(0)
+        _check(lib().rmm_srht_indices(self._h, m, s, seed, _ptr(out)), "rmm_srht_indices")
+        return out
+
+    def gaussian(self, rows: int, cols: int, seed: int, stream: int = 0,
+                 dtype=torch.float64) -> torch.Tensor:
+        out = torch.empty(max(cols, 1), max(rows, 1), dtype=dtype, device=self.device).t()[:rows, :cols]
+        self._prepare(0)
+        _check(lib().rmm_gaussian(self._h, F32 if dtype == torch.float32 else F64, stream, rows,
+                                  cols, seed, _ptr(out), max(1, rows)), "rmm_gaussian")
+        return out
+
+
+_default = {}
+
+
+def handle(device=None) -> Handle:
+    """Per-device default handle."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    key = dev.index or 0
+    if key not in _default:
+        _default[key] = Handle(dev)
+    return _default[key]
+
+
+def sketch(A, s, kind, seed, b=None):
+    return handle(A.device).sketch(A, s, kind, seed, b)
+
+
+def rsvd(A, k, p, q, seed, prec=PREC_NATIVE):
+    return handle(A.device).rsvd(A, k, p, q, seed, prec)
+
+
+def sketched_lsr(A, b, s, kind, seed, residual=True):
+    return handle(A.device).sketched_lsr(A, b, s, kind, seed, residual)
+
+
+def plain_lsr(A, b, residual=True):
+    return handle(A.device).plain_lsr(A, b, residual)

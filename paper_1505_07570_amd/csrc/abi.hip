@@ -1,0 +1,157 @@
+// C ABI: argument validation, workspace carving and dispatch.
+#include <math.h>
+#include <new>
+
+#include "common.hpp"
+#include "ops.hpp"
+#include "rng.hpp"
+
+using namespace rmm;
+
+namespace {
+
+bool bad_ld(int64_t ld, int64_t rows) { return ld < (rows > 1 ? rows : 1); }
+
+// the sketch kernels index columns as int and rows as int64
+bool sketch_dims_ok(int64_t m, int64_t n, int64_t s) {
+  return m >= 0 && n >= 0 && s >= 1 && n < (1ll << 30) && s < (1ll << 30);
+}
+
+template <typename T>
+size_t sketch_ws(const rmm_ctx* h, rmm_sketch_kind kind, int64_t m, int ncols, int64_t s) {
+  switch (kind) {
+    case RMM_COUNTSKETCH: return countsketch_workspace<T>(h, m, ncols, s);
+    case RMM_SRHT: return srht_workspace<T>(h, m, ncols, s);
+    default: return gauss_sketch_workspace<T>(h, m, ncols, s);
+  }
+}
+
+template <typename T>
+int sketch_dispatch(rmm_ctx* h, rmm_sketch_kind kind, int64_t m, int n, const T* A, int64_t lda,
+                    const T* b, int64_t s, uint64_t seed, T* C, int64_t ldc, Carver& ws) {
+  switch (kind) {
+    case RMM_COUNTSKETCH: return countsketch_run<T>(h, m, n, A, lda, b, s, seed, C, ldc, ws);
+    case RMM_SRHT: return srht_run<T>(h, m, n, A, lda, b, s, seed, C, ldc, ws);
+    case RMM_GAUSSIAN: return gauss_sketch_run<T>(h, m, n, A, lda, b, s, seed, C, ldc, ws);
+  }
+  return RMM_ERR_INVALID_ARG;
+}
+
+bool kind_ok(rmm_sketch_kind k) {
+  return k == RMM_GAUSSIAN || k == RMM_SRHT || k == RMM_COUNTSKETCH;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmm_create(rmm_handle* h, int device) {
+  if (!h) return RMM_ERR_INVALID_ARG;
+  *h = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+    return RMM_ERR_INVALID_ARG;
+  rmm_ctx* c = new (std::nothrow) rmm_ctx();
+  if (!c) return RMM_ERR_HIP;
+  c->device = device;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0)
+    c->cus = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
+      v > 0)
+    c->lds_bytes = (size_t)v;
+  *h = c;
+  return RMM_OK;
+}
+
+int rmm_destroy(rmm_handle h) {
+  delete h;
+  return RMM_OK;
+}
+
+int rmm_set_stream(rmm_handle h, void* stream) {
+  if (!h) return RMM_ERR_INVALID_ARG;
+  h->stream = reinterpret_cast<hipStream_t>(stream);
+  return RMM_OK;
+}
+
+int rmm_set_workspace(rmm_handle h, void* dptr, size_t bytes) {
+  if (!h || (bytes > 0 && !dptr) || ((uintptr_t)dptr % kAlign) != 0) return RMM_ERR_INVALID_ARG;
+  h->ws = reinterpret_cast<char*>(dptr);
+  h->ws_bytes = bytes;
+  return RMM_OK;
+}
+
+int rmm_device_cus(rmm_handle h, int* cus) {
+  if (!h || !cus) return RMM_ERR_INVALID_ARG;
+  *cus = h->cus;
+  return RMM_OK;
+}
+
+const char* rmm_strerror(int code) {
+  switch (code) {
+    case RMM_OK: return "ok";
+    case RMM_ERR_INVALID_ARG: return "invalid argument";
+    case RMM_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case RMM_ERR_HIP: return "HIP runtime error";
+    case RMM_ERR_UNSUPPORTED: return "unsupported combination";
+  }
+  return "unknown error";
+}
+
+int rmm_sketch_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m,
+                         int64_t n_total, int64_t s, size_t* bytes) {
+  if (!h || !bytes || !dt_ok(dt) || !kind_ok(kind) || !sketch_dims_ok(m, n_total, s))
+    return RMM_ERR_INVALID_ARG;
+  *bytes = dt == RMM_F32 ? sketch_ws<float>(h, kind, m, (int)n_total, s)
+                         : sketch_ws<double>(h, kind, m, (int)n_total, s);
+  return RMM_OK;
+}
+
+int rmm_sketch(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m, int64_t n,
+               const void* A, int64_t lda, const void* b, int64_t s, uint64_t seed, void* C,
+               int64_t ldc) {
+  if (!h || !dt_ok(dt) || !kind_ok(kind) || !sketch_dims_ok(m, n + 1, s)) return RMM_ERR_INVALID_ARG;
+  if ((n > 0 && m > 0 && !A) || !C || bad_ld(lda, m) || bad_ld(ldc, s)) return RMM_ERR_INVALID_ARG;
+  if (kind == RMM_SRHT) {
+    const int k = ceil_log2((uint64_t)(m > 0 ? m : 1));
+    if (s > (1ll << k)) return RMM_ERR_INVALID_ARG;
+  }
+  Carver ws(h->ws, h->ws_bytes);
+  if (dt == RMM_F32)
+    return sketch_dispatch<float>(h, kind, m, (int)n, (const float*)A, lda, (const float*)b, s,
+                                  seed, (float*)C, ldc, ws);
+  return sketch_dispatch<double>(h, kind, m, (int)n, (const double*)A, lda, (const double*)b, s,
+                                 seed, (double*)C, ldc, ws);
+}
+
+int rmm_sketch_hashes(rmm_handle h, int64_t m, int64_t s, uint64_t seed, int32_t* out) {
+  if (!h || m < 0 || s < 1 || s >= (1ll << 31) || (m > 0 && !out)) return RMM_ERR_INVALID_ARG;
+  return launch_cs_hashes(h, m, s, seed, out);
+}
+
+int rmm_sketch_signs(rmm_handle h, rmm_sketch_kind kind, int64_t m, uint64_t seed, int8_t* out) {
+  if (!h || m < 0 || (m > 0 && !out) || (kind != RMM_COUNTSKETCH && kind != RMM_SRHT))
+    return RMM_ERR_INVALID_ARG;
+  return launch_signs(h, (int)kind, m, seed, out);
+}
+
+int rmm_srht_indices(rmm_handle h, int64_t m, int64_t s, uint64_t seed, int64_t* out) {
+  if (!h || m < 0 || !out) return RMM_ERR_INVALID_ARG;
+  const int k = ceil_log2((uint64_t)(m > 0 ? m : 1));
+  if (s < 1 || s > (1ll << k)) return RMM_ERR_INVALID_ARG;
+  if (s > 8192 || k > 32) return RMM_ERR_UNSUPPORTED;
+  return launch_sample_indices_i64(h, 1ull << k, k, s, TAG_SRHT_SAMPLE, seed, out);
+}
+
+int rmm_gaussian(rmm_handle h, rmm_dtype dt, int stream, int64_t rows, int64_t cols, uint64_t seed,
+                 void* out, int64_t ld) {
+  static const uint32_t tags[3] = {TAG_GAUSS_SKETCH, TAG_GAUSS_RSVD, TAG_GAUSS_NYSTROM};
+  if (!h || !dt_ok(dt) || stream < 0 || stream > 2 || rows < 0 || cols < 0 ||
+      cols >= (1ll << 32) || bad_ld(ld, rows) || (rows * cols > 0 && !out))
+    return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32) return launch_gaussian<float>(h, tags[stream], rows, cols, seed, (float*)out, ld);
+  return launch_gaussian<double>(h, tags[stream], rows, cols, seed, (double*)out, ld);
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rmm.h"
+
+struct rmm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int cus = 256;
+  size_t lds_bytes = 65536;  // usable LDS per workgroup
+};
+
+namespace rmm {
+
+constexpr size_t kAlign = 256;
+
+// Bump allocator over the caller's workspace.  The size queries run the
+// same carving sequence with a null base, so a query and the call that
+// follows always agree on the layout.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  size_t cap;
+  Carver(char* b, size_t c) : base(b), cap(c) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  bool fits() const { return off <= cap; }
+};
+
+inline int hip_status(hipError_t e) { return e == hipSuccess ? RMM_OK : RMM_ERR_HIP; }
+
+// Check the launch that was just enqueued.
+inline int launch_status() { return hip_status(hipGetLastError()); }
+
+#define RMM_TRY(expr)               \
+  do {                              \
+    int rmm_rc_ = (expr);           \
+    if (rmm_rc_ != RMM_OK) return rmm_rc_; \
+  } while (0)
+
+#define RMM_HIP(expr)                           \
+  do {                                          \
+    if ((expr) != hipSuccess) return RMM_ERR_HIP; \
+  } while (0)
+
+inline bool dt_ok(rmm_dtype dt) { return dt == RMM_F32 || dt == RMM_F64; }
+inline size_t dt_size(rmm_dtype dt) { return dt == RMM_F64 ? 8 : 4; }
+
+// ---- column-panel streaming plan ---------------------------------------------
+//
+// The sketch kernels stream A as (column panel, row chunk) work units.  A
+// panel is a run of at most `width` consecutive columns; units are ordered
+// panel-major and split into G contiguous, equally sized ranges, one per
+// workgroup (or per wave).  A worker flushes its accumulators whenever its
+// panel changes, so each panel receives partial results from a contiguous
+// run of workers; partial slot = worker + panel is unique.
+struct PanelPlan {
+  int64_t m;        // rows of A
+  int64_t nchunks;  // row chunks
+  int64_t chunk;    // rows per chunk
+  int64_t units;    // P * BT * nchunks
+  int ncols;        // columns including the optional b column
+  int P;            // column panels
+  int width;        // max columns per panel
+  int BT;           // bucket tiles (CountSketch only; 1 otherwise)
+  int ST;           // buckets per tile
+  int s;            // sketch size
+  int G;            // workers
+  int slot_elems;   // elements per partial slot = width * ST
+};
+
+__host__ __device__ __forceinline__ int64_t plan_col0(const PanelPlan& p, int panel) {
+  return (int64_t)panel * p.ncols / p.P;
+}
+__host__ __device__ __forceinline__ int64_t plan_start(const PanelPlan& p, int64_t w) {
+  return w * p.units / p.G;
+}
+// Worker whose range holds unit u.
+__host__ __device__ __forceinline__ int64_t plan_worker(const PanelPlan& p, int64_t u) {
+  return ((u + 1) * p.G - 1) / p.units;
+}
+
+PanelPlan make_plan(int64_t m, int ncols, int width, int s, int ST, int64_t chunk, int G);
+inline int64_t plan_slots(const PanelPlan& p) { return (int64_t)p.G + (int64_t)p.P * p.BT; }
+
+// Fixed-order reduction of partial slots into C (scaled), see reduce.hip.
+template <typename T>
+int launch_panel_reduce(const PanelPlan& plan, const T* partials, double scale, T* C,
+                        int64_t ldc, hipStream_t st);
+
+// Zero an s x n column-major block of C.
+template <typename T>
+int launch_fill_zero(T* C, int64_t rows, int64_t cols, int64_t ldc, hipStream_t st);
+
+}  // namespace rmm

@@ -1,0 +1,226 @@
+// CountSketch C = S^T A (Sec. 3.2.3, Alg. 3.1, streaming fashion).
+//
+// S has one nonzero per row: row i of A is added, with sign g_i, into row
+// h_i of C.  One pass over A; no scaling.
+//
+// Kernel layout (one workgroup of WAVES waves per column panel x row-chunk
+// range, see PanelPlan):
+//  * wave w owns column (panel start + w) and a private LDS accumulator of
+//    ST buckets, so every LDS add to a bucket comes from one wave in program
+//    order: the per-block sums are reproducible run to run;
+//  * the CountSketch words of a chunk's rows are generated once per chunk
+//    by the whole workgroup (one Philox block per 4 rows) into an LDS table
+//    shared by the WAVES columns;
+//  * A is streamed with 16-byte loads, 4 consecutive rows per lane, issued
+//    before the hash generation so the loads are in flight meanwhile;
+//  * at a panel change the accumulators are flushed to a partial slot and a
+//    fixed-order reduction (reduce.hip) sums the slots into C.
+#include "common.hpp"
+#include "rng.hpp"
+
+namespace rmm {
+
+template <typename T, bool VEC>
+__device__ __forceinline__ void load4(const T* __restrict__ col, int64_t row, int64_t m,
+                                      T v[4]) {
+  if (VEC && row + 3 < m) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 x = *reinterpret_cast<const float4*>(col + row);
+      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+    } else {
+      const double2 x = *reinterpret_cast<const double2*>(col + row);
+      const double2 y = *reinterpret_cast<const double2*>(col + row + 2);
+      v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (row + e < m) ? col[row + e] : T(0);
+  }
+}
+
+template <typename T, int WAVES, int UNROLL, bool VEC>
+__global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
+    uint64_t seed, T* __restrict__ partials) {
+  constexpr int CH = 256 * UNROLL;  // rows per chunk
+  constexpr int NT = WAVES * 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* acc = reinterpret_cast<T*>(smem);
+  uint32_t* hbuf = reinterpret_cast<uint32_t*>(smem + (size_t)WAVES * plan.ST * sizeof(T));
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t blk = blockIdx.x;
+  const int64_t u0 = plan_start(plan, blk);
+  const int64_t u1 = plan_start(plan, blk + 1);
+  const uint32_t s = (uint32_t)plan.s;
+  const int ST = plan.ST;
+  T* my_acc = acc + (size_t)wave * ST;
+
+  int64_t cur_vp = -1;
+  int buf = 0;
+  for (int64_t u = u0; u < u1; ++u) {
+    const int64_t vp = u / plan.nchunks;
+    const int64_t c = u - vp * plan.nchunks;
+    const int panel = (int)(vp / plan.BT);
+    const int bt = (int)(vp - (int64_t)panel * plan.BT);
+    if (vp != cur_vp) {
+      if (cur_vp >= 0) {
+        __syncthreads();
+        T* dst = partials + (blk + cur_vp) * plan.slot_elems;
+        for (int i = tid; i < WAVES * ST; i += NT) dst[i] = acc[i];
+      }
+      __syncthreads();
+      for (int i = tid; i < WAVES * ST; i += NT) acc[i] = T(0);
+      cur_vp = vp;
+    }
+    const int64_t r0 = c * CH;
+    const int64_t j = plan_col0(plan, panel) + wave;
+    const bool active = j < plan_col0(plan, panel + 1);
+    const T* col = (j < n) ? A + j * lda : bcol;
+
+    // 1. loads in flight
+    T v[UNROLL][4];
+    if (active) {
+#pragma unroll
+      for (int k = 0; k < UNROLL; ++k) load4<T, VEC>(col, r0 + 256 * k + 4 * lane, plan.m, v[k]);
+    }
+    // 2. CountSketch words of this chunk, packed as bucket | sign << 31
+    uint32_t* hb = hbuf + buf * CH;
+#pragma unroll
+    for (int q = tid; q < CH / 4; q += NT) {
+      const Words4 w = philox_at((uint64_t)(r0 >> 2) + q, TAG_COUNTSKETCH, 0, seed);
+      uint4 pk;
+      pk.x = cs_bucket(w.w[0], s) | (w.w[0] << 31);
+      pk.y = cs_bucket(w.w[1], s) | (w.w[1] << 31);
+      pk.z = cs_bucket(w.w[2], s) | (w.w[2] << 31);
+      pk.w = cs_bucket(w.w[3], s) | (w.w[3] << 31);
+      *reinterpret_cast<uint4*>(hb + 4 * q) = pk;
+    }
+    __syncthreads();
+    // 3. signed scatter-add into this wave's buckets
+    if (active) {
+      const uint32_t tile0 = (uint32_t)bt * (uint32_t)ST;
+#pragma unroll
+      for (int k = 0; k < UNROLL; ++k) {
+        const int off = 256 * k + 4 * lane;
+        const uint4 pk = *reinterpret_cast<const uint4*>(hb + off);
+        const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (r0 + off + e < plan.m) {
+            const uint32_t bucket = (pw[e] & 0x7FFFFFFFu) - tile0;
+            if (bucket < (uint32_t)ST) {
+              const T x = (pw[e] >> 31) ? -v[k][e] : v[k][e];
+              atomicAdd(my_acc + bucket, x);
+            }
+          }
+        }
+      }
+    }
+    buf ^= 1;
+  }
+  if (cur_vp >= 0) {
+    __syncthreads();
+    T* dst = partials + (blk + cur_vp) * plan.slot_elems;
+    for (int i = tid; i < WAVES * ST; i += NT) dst[i] = acc[i];
+  }
+}
+
+namespace {
+
+constexpr size_t kAccBudget = 128 * 1024;  // LDS bytes for the bucket accumulators
+
+template <typename T>
+int pick_unroll() {
+  return sizeof(T) == 4 ? 8 : 4;
+}
+
+template <typename T>
+void cs_shape(const rmm_ctx* h, int64_t m, int ncols, int s, int* waves, int* ST,
+              PanelPlan* plan) {
+  int st = s;
+  const int max_st = (int)(kAccBudget / sizeof(T));
+  if (st > max_st) st = max_st;
+  int w = (int)(kAccBudget / ((size_t)st * sizeof(T)));
+  if (w > 8) w = 8;
+  int pw = 1;
+  while (pw * 2 <= w) pw *= 2;
+  while (pw > 1 && pw / 2 >= ncols) pw /= 2;
+  *waves = pw;
+  *ST = st;
+  const int unroll = pick_unroll<T>();
+  const size_t lds = (size_t)pw * st * sizeof(T) + 2 * 256 * unroll * 4;
+  int per_cu = (int)(160 * 1024 / lds);
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 8) per_cu = 8;
+  *plan = make_plan(m, ncols, pw, s, st, 256 * unroll, h->cus * per_cu);
+}
+
+template <typename T, int WAVES, bool VEC>
+int launch_cs(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
+              const PanelPlan& plan, uint64_t seed, T* partials) {
+  constexpr int UNROLL = sizeof(T) == 4 ? 8 : 4;
+  const size_t lds = (size_t)WAVES * plan.ST * sizeof(T) + 2 * 256 * UNROLL * 4;
+  auto kern = countsketch_kernel<T, WAVES, UNROLL, VEC>;
+  RMM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+  hipLaunchKernelGGL(kern, dim3(plan.G), dim3(WAVES * 64), lds, h->stream, A, lda, b, n, plan,
+                     seed, partials);
+  return launch_status();
+}
+
+}  // namespace
+
+template <typename T>
+size_t countsketch_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s) {
+  int waves, ST;
+  PanelPlan plan;
+  cs_shape<T>(h, m, ncols, (int)s, &waves, &ST, &plan);
+  Carver c(nullptr, 0);
+  c.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
+  return c.off;
+}
+
+template <typename T>
+int countsketch_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b,
+                    int64_t s, uint64_t seed, T* C, int64_t ldc, Carver& ws) {
+  const int ncols = n + (b ? 1 : 0);
+  if (ncols == 0) return RMM_OK;
+  if (m == 0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
+  int waves, ST;
+  PanelPlan plan;
+  cs_shape<T>(h, m, ncols, (int)s, &waves, &ST, &plan);
+  T* partials = ws.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) &&
+                   (b == nullptr || (uintptr_t)b % 16 == 0);
+  int rc;
+#define RMM_CS_CASE(W)                                                          \
+  case W:                                                                       \
+    rc = vec ? launch_cs<T, W, true>(h, A, lda, b, n, plan, seed, partials)     \
+             : launch_cs<T, W, false>(h, A, lda, b, n, plan, seed, partials);   \
+    break;
+  switch (waves) {
+    RMM_CS_CASE(1)
+    RMM_CS_CASE(2)
+    RMM_CS_CASE(4)
+    RMM_CS_CASE(8)
+    default:
+      return RMM_ERR_UNSUPPORTED;
+  }
+#undef RMM_CS_CASE
+  RMM_TRY(rc);
+  return launch_panel_reduce<T>(plan, partials, 1.0, C, ldc, h->stream);
+}
+
+template size_t countsketch_workspace<float>(const rmm_ctx*, int64_t, int, int64_t);
+template size_t countsketch_workspace<double>(const rmm_ctx*, int64_t, int, int64_t);
+template int countsketch_run<float>(rmm_ctx*, int64_t, int, const float*, int64_t, const float*,
+                                    int64_t, uint64_t, float*, int64_t, Carver&);
+template int countsketch_run<double>(rmm_ctx*, int64_t, int, const double*, int64_t,
+                                     const double*, int64_t, uint64_t, double*, int64_t,
+                                     Carver&);
+
+}  // namespace rmm

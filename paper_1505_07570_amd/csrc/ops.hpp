@@ -1,0 +1,36 @@
+// Internal entry points of the kernels, called by the C ABI layer.
+#pragma once
+
+#include "common.hpp"
+
+namespace rmm {
+
+template <typename T>
+size_t countsketch_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s);
+template <typename T>
+int countsketch_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b,
+                    int64_t s, uint64_t seed, T* C, int64_t ldc, Carver& ws);
+
+template <typename T>
+size_t srht_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s);
+template <typename T>
+int srht_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b, int64_t s,
+             uint64_t seed, T* C, int64_t ldc, Carver& ws);
+
+template <typename T>
+size_t gauss_sketch_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s);
+template <typename T>
+int gauss_sketch_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b,
+                     int64_t s, uint64_t seed, T* C, int64_t ldc, Carver& ws);
+
+int launch_sample_indices_u32(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
+                              uint32_t tag, uint64_t seed, uint32_t* out);
+int launch_sample_indices_i64(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
+                              uint32_t tag, uint64_t seed, int64_t* out);
+int launch_cs_hashes(const rmm_ctx* h, int64_t m, int64_t s, uint64_t seed, int32_t* out);
+int launch_signs(const rmm_ctx* h, int kind, int64_t m, uint64_t seed, int8_t* out);
+template <typename T>
+int launch_gaussian(const rmm_ctx* h, uint32_t tag, int64_t rows, int64_t cols, uint64_t seed,
+                    T* out, int64_t ld);
+
+}  // namespace rmm

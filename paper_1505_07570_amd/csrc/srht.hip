@@ -1,0 +1,282 @@
+// SRHT sketch C = s^{-1/2} (H_N D [A; 0])[idx, :]  (Sec. 3.2.2).
+//
+// Random signs D on the m real rows, zero padding to N = 2^ceil(log2 m),
+// the Sylvester-ordered Walsh-Hadamard transform along the rows, and the s
+// sampled rows idx (sorted, drawn without replacement), scaled by 1/sqrt(s).
+//
+// Only s of the N transformed rows are needed, so the transform is split
+// with the Kronecker structure of the Sylvester recursion: with L = 4096 and
+// row index i = i_hi L + i_lo,
+//     H_N[r, i] = H_{N/L}[r_hi, i_hi] * H_L[r_lo, i_lo],
+//     (H_N x)[r] = sum_{i_hi} (-1)^popcount(r_hi & i_hi) (H_L x_{i_hi})[r_lo].
+// Each wave owns one column and a run of L-row chunks: it loads the chunk
+// (16-byte loads, 4 rows per lane), applies D, runs the 12-stage butterfly
+// network in registers with one LDS transpose, stores z = H_L x_chunk to its
+// LDS region, and adds +-z[r_lo] into register accumulators for the samples
+// it owns.  N < L is handled by zero padding to L: (H_L [x; 0])[r] equals
+// (H_N x)[r] for r < N.  Per-wave partial sums are reduced in fixed order.
+#include "common.hpp"
+#include "rng.hpp"
+
+namespace rmm {
+
+namespace {
+
+constexpr int kLogL = 12;
+constexpr int kL = 1 << kLogL;  // 4096 rows per chunk, 64 values per lane
+
+// LDS word address of row r inside a wave's chunk buffer.  XOR-ing row bits
+// 8..10 into bits 2..4 makes both the 16-byte stores of the load layout and
+// the strided 4-byte loads of the transposed layout bank-conflict free.
+__device__ __forceinline__ uint32_t swz(uint32_t r) { return r ^ (((r >> 8) & 7u) << 2); }
+
+template <typename T>
+__device__ __forceinline__ T flip(T x, uint32_t bit);
+template <>
+__device__ __forceinline__ float flip<float>(float x, uint32_t bit) {
+  // adding bit << 31 toggles the IEEE sign bit when bit is 0 or 1
+  return __uint_as_float(__float_as_uint(x) + (bit << 31));
+}
+template <>
+__device__ __forceinline__ double flip<double>(double x, uint32_t bit) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x) + ((uint64_t)bit << 63);
+  return __longlong_as_double((long long)u);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ __forceinline__ void bfly(T& a, T& b) {
+  const T x = a + b;
+  const T y = a - b;
+  a = x;
+  b = y;
+}
+
+template <typename T, int SPL, bool VEC>
+__global__ __launch_bounds__(64) void srht_kernel(const T* __restrict__ A, int64_t lda,
+                                                  const T* __restrict__ bcol, int n,
+                                                  PanelPlan plan, const uint32_t* __restrict__ idx,
+                                                  uint64_t seed, T* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* buf = reinterpret_cast<T*>(smem);                          // kL values
+  uint32_t* sgn = reinterpret_cast<uint32_t*>(smem + kL * sizeof(T));  // 32 x 4 words
+  const int lane = threadIdx.x;
+  const int64_t wk = blockIdx.x;  // this wave's worker id
+  const int64_t u0 = plan_start(plan, wk);
+  const int64_t u1 = plan_start(plan, wk + 1);
+  const int s = plan.s;
+
+  // owned samples t = lane + 64 k: packed (r_hi << SH) | LDS byte address of z[r_lo]
+  constexpr uint32_t SH = sizeof(T) == 4 ? 14 : 15;
+  constexpr uint32_t AMASK = (1u << SH) - 1u;
+  uint32_t pk[SPL];
+  T acc[SPL];
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    const int t = lane + 64 * k;
+    const uint32_t r = t < s ? idx[t] : 0u;
+    pk[k] = ((r >> kLogL) << SH) | (swz(r & (kL - 1)) * (uint32_t)sizeof(T));
+    acc[k] = T(0);
+  }
+  // lane-constant parts of the swizzled addresses (swz only touches bits 2..4)
+  const uint32_t a = lane & 3u, bq = (uint32_t)lane >> 2;
+  uint32_t woff[8], roff[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    woff[i] = 4u * ((uint32_t)lane ^ (uint32_t)i);              // + 256 k, k & 7 == i
+    roff[i] = a + 256u * bq + 4u * ((uint32_t)i ^ (bq & 7u));   // + 32 (i >> 3)
+  }
+  int64_t cur_panel = -1;
+  for (int64_t u = u0; u < u1; ++u) {
+    const int64_t panel = u / plan.nchunks;
+    const int64_t c = u - panel * plan.nchunks;
+    if (panel != cur_panel) {
+      if (cur_panel >= 0) {
+        T* dst = partials + (wk + cur_panel) * plan.slot_elems;
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+          const int t = lane + 64 * k;
+          if (t < s) dst[t] = acc[k];
+          acc[k] = T(0);
+        }
+      }
+      cur_panel = panel;
+    }
+    const int64_t j = panel;  // one column per panel
+    const T* col = (j < n) ? A + j * lda : bcol;
+    const int64_t r0 = c * kL;
+
+    // 1. load: lane holds rows r0 + 256 k + 4 lane + e in x[4k + e]
+    T x[64];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int64_t row = r0 + 256 * k + 4 * lane;
+      if (VEC && row + 3 < plan.m) {
+        if constexpr (sizeof(T) == 4) {
+          const float4 q = *reinterpret_cast<const float4*>(col + row);
+          x[4 * k] = q.x; x[4 * k + 1] = q.y; x[4 * k + 2] = q.z; x[4 * k + 3] = q.w;
+        } else {
+          const double2 q0 = *reinterpret_cast<const double2*>(col + row);
+          const double2 q1 = *reinterpret_cast<const double2*>(col + row + 2);
+          x[4 * k] = q0.x; x[4 * k + 1] = q0.y; x[4 * k + 2] = q1.x; x[4 * k + 3] = q1.y;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[4 * k + e] = (row + e < plan.m) ? col[row + e] : T(0);
+      }
+    }
+    // 2. signs: 32 Philox blocks of 128 rows cover the chunk
+    if (lane < 32) {
+      const Words4 w = philox_at((uint64_t)(r0 >> 7) + lane, TAG_SRHT_SIGN, 0, seed);
+      *reinterpret_cast<uint4*>(sgn + 4 * lane) = make_uint4(w.w[0], w.w[1], w.w[2], w.w[3]);
+    }
+    wave_lds_sync();
+    {
+      const int wsel = (lane & 31) >> 3;
+      const uint32_t sh = 4u * (lane & 7);
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t word = sgn[4 * (2 * k + (lane >> 5)) + wsel] >> sh;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[4 * k + e] = flip<T>(x[4 * k + e], (word >> e) & 1u);
+      }
+    }
+    // 3. butterflies on row bits 0,1 (e) and 8..11 (k): register index bits 0..5
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+#pragma unroll
+      for (int i = 0; i < 64; ++i)
+        if (!(i & (1 << b))) bfly(x[i], x[i | (1 << b)]);
+    }
+    // 4. transpose through LDS: afterwards lane (a | b' << 2) holds rows
+    //    a + 4 i + 256 b' in x[i], i = 0..63
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      T* p = buf + 256 * k + woff[k & 7];
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(x[4 * k], x[4 * k + 1], x[4 * k + 2], x[4 * k + 3]);
+      } else {
+        *reinterpret_cast<double2*>(p) = make_double2(x[4 * k], x[4 * k + 1]);
+        *reinterpret_cast<double2*>(p + 2) = make_double2(x[4 * k + 2], x[4 * k + 3]);
+      }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < 64; ++i) x[i] = buf[roff[i & 7] + 32 * (i >> 3)];
+    // 5. butterflies on row bits 2..7
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+#pragma unroll
+      for (int i = 0; i < 64; ++i)
+        if (!(i & (1 << b))) bfly(x[i], x[i | (1 << b)]);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < 64; ++i) buf[roff[i & 7] + 32 * (i >> 3)] = x[i];
+    wave_lds_sync();
+    // 6. combine: acc[t] += (-1)^popcount(r_hi & c) z[r_lo]
+    const uint32_t cmask = (uint32_t)c << SH;
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+      const T z = *reinterpret_cast<const T*>(smem + (pk[k] & AMASK));
+      const uint32_t par = __builtin_popcount(pk[k] & cmask) & 1u;
+      acc[k] += flip<T>(z, par);
+    }
+    wave_lds_sync();
+  }
+  if (cur_panel >= 0) {
+    T* dst = partials + (wk + cur_panel) * plan.slot_elems;
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+      const int t = lane + 64 * k;
+      if (t < s) dst[t] = acc[k];
+    }
+  }
+}
+
+template <typename T>
+size_t srht_lds() {
+  return (size_t)kL * sizeof(T) + 512;
+}
+
+PanelPlan srht_plan(const rmm_ctx* h, int64_t m, int ncols, int s, size_t tsize) {
+  const size_t lds = (size_t)kL * tsize + 512;
+  int per_cu = (int)(h->lds_bytes / lds);
+  if (per_cu > 8) per_cu = 8;
+  if (per_cu < 1) per_cu = 1;
+  return make_plan(m, ncols, 1, s, s, kL, h->cus * per_cu);
+}
+
+template <typename T, int SPL, bool VEC>
+int launch_srht(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
+                const PanelPlan& plan, const uint32_t* idx, uint64_t seed, T* partials) {
+  auto kern = srht_kernel<T, SPL, VEC>;
+  const size_t lds = srht_lds<T>();
+  RMM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+  hipLaunchKernelGGL(kern, dim3(plan.G), dim3(64), lds, h->stream, A, lda, b, n, plan, idx, seed,
+                     partials);
+  return launch_status();
+}
+
+}  // namespace
+
+int launch_sample_indices_u32(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
+                              uint32_t tag, uint64_t seed, uint32_t* out);
+
+template <typename T>
+size_t srht_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s) {
+  const PanelPlan plan = srht_plan(h, m, ncols, (int)s, sizeof(T));
+  Carver c(nullptr, 0);
+  c.take<uint32_t>((size_t)s);
+  c.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
+  return c.off;
+}
+
+template <typename T>
+int srht_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b, int64_t s,
+             uint64_t seed, T* C, int64_t ldc, Carver& ws) {
+  const int ncols = n + (b ? 1 : 0);
+  if (ncols == 0) return RMM_OK;
+  const int k = ceil_log2((uint64_t)(m > 0 ? m : 1));
+  if (s > (1ll << k) || s > 8192) return s > (1ll << k) ? RMM_ERR_INVALID_ARG : RMM_ERR_UNSUPPORTED;
+  if (k > 29) return RMM_ERR_UNSUPPORTED;  // r_hi must fit the packed sample field
+  if (m == 0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
+  const PanelPlan plan = srht_plan(h, m, ncols, (int)s, sizeof(T));
+  uint32_t* idx = ws.take<uint32_t>((size_t)s);
+  T* partials = ws.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  RMM_TRY(launch_sample_indices_u32(h, 1ull << k, k, s, TAG_SRHT_SAMPLE, seed, idx));
+  const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) &&
+                   (b == nullptr || (uintptr_t)b % 16 == 0);
+  int rc;
+#define RMM_SRHT_CASE(SPL)                                                                 \
+  rc = vec ? launch_srht<T, SPL, true>(h, A, lda, b, n, plan, idx, seed, partials)         \
+           : launch_srht<T, SPL, false>(h, A, lda, b, n, plan, idx, seed, partials);
+  if (s <= 256) {
+    RMM_SRHT_CASE(4)
+  } else if (s <= 1024) {
+    RMM_SRHT_CASE(16)
+  } else if (s <= 4096) {
+    RMM_SRHT_CASE(64)
+  } else {
+    RMM_SRHT_CASE(128)
+  }
+#undef RMM_SRHT_CASE
+  RMM_TRY(rc);
+  return launch_panel_reduce<T>(plan, partials, 1.0 / sqrt((double)s), C, ldc, h->stream);
+}
+
+template size_t srht_workspace<float>(const rmm_ctx*, int64_t, int, int64_t);
+template size_t srht_workspace<double>(const rmm_ctx*, int64_t, int, int64_t);
+template int srht_run<float>(rmm_ctx*, int64_t, int, const float*, int64_t, const float*,
+                             int64_t, uint64_t, float*, int64_t, Carver&);
+template int srht_run<double>(rmm_ctx*, int64_t, int, const double*, int64_t, const double*,
+                              int64_t, uint64_t, double*, int64_t, Carver&);
+
+}  // namespace rmm
