@@ -177,6 +177,7 @@ class Handle:
     def sketch(self, A: torch.Tensor, s: int, kind, seed: int, b: torch.Tensor = None,
                out: torch.Tensor = None) -> torch.Tensor:
         """C = S^T [A | b] (s x n'), column-major, same dtype as A."""
+        A = colmajor(A)
         m, n = A.shape
         ncols = n + (1 if b is not None else 0)
         if out is None:
@@ -189,6 +190,7 @@ class Handle:
 
     # ---- randomized SVD ----------------------------------------------------
     def rsvd(self, A: torch.Tensor, k: int, p: int, q: int, seed: int, prec: int = PREC_NATIVE):
+        A = colmajor(A)
         m, n = A.shape
         dt = _dt(A)
         U = torch.empty(k, m, dtype=A.dtype, device=A.device).t()
@@ -206,6 +208,7 @@ class Handle:
     # ---- least squares -------------------------------------------------------
     def sketched_lsr(self, A: torch.Tensor, b: torch.Tensor, s: int, kind, seed: int,
                      residual: bool = True):
+        A = colmajor(A)
         m, d = A.shape
         dt = _dt(A)
         x = torch.empty(d, dtype=torch.float64, device=A.device)
@@ -220,6 +223,7 @@ class Handle:
         return x, res, status
 
     def plain_lsr(self, A: torch.Tensor, b: torch.Tensor, residual: bool = True):
+        A = colmajor(A)
         m, d = A.shape
         dt = _dt(A)
         x = torch.empty(d, dtype=torch.float64, device=A.device)

@@ -1,0 +1,306 @@
+// Dense building blocks of the drivers: MFMA GEMMs with split-K, and the
+// elementwise / GEMV helpers around them.
+//
+// gemm: C = alpha * op(A) * op(B), column-major, op = identity or transpose.
+//  * workgroup tile BM x BN, 4 waves in a 2 x 2 grid, 16x16x4 MFMA in fp32 or
+//    fp64 (the compute type TC); inputs of either precision are converted
+//    to TC when they are staged into LDS;
+//  * the K dimension is split over gridDim.z; each split writes a partial
+//    tile and a fixed-order reduction adds them in fp64 and converts to the
+//    output type, so results do not depend on scheduling.
+#include "common.hpp"
+#include "dense.hpp"
+
+namespace rmm {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename TC>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  using acc = floatx4;
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of D held in register v by lane group g = lane >> 4
+  static __device__ __forceinline__ int row(int g, int v) { return 4 * g + v; }
+};
+template <>
+struct Mfma<double> {
+  using acc = doublex4;
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
+};
+
+constexpr int kBK = 16;
+
+// op(X)[i, k] for a column-major X: X[i + k*ld] or, transposed, X[k + i*ld]
+template <typename T, bool TR>
+__device__ __forceinline__ T opget(const T* __restrict__ X, int64_t ld, int64_t i, int64_t k) {
+  return TR ? X[k + i * ld] : X[i + k * ld];
+}
+
+template <typename TAI, typename TBI, typename TC, bool TA, bool TB, int BM, int BN>
+__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int64_t K, const TAI* __restrict__ A,
+                                                   int64_t lda, const TBI* __restrict__ B, int64_t ldb,
+                                                   TC* __restrict__ P, int64_t kchunk) {
+  using F = Mfma<TC>;
+  using acc_t = typename F::acc;
+  constexpr int WM = BM / 2, WN = BN / 2;  // wave tile
+  constexpr int TM = WM / 16, TN = WN / 16;
+  __shared__ TC As[kBK][BM + 1];
+  __shared__ TC Bs[kBK][BN + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+  int64_t k1 = k0 + kchunk;
+  if (k1 > K) k1 = K;
+  acc_t acc[TM][TN];
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  const int g = lane >> 4, c16 = lane & 15;
+  for (int64_t kb = k0; kb < k1; kb += kBK) {
+    // stage op(A)[m0 .. m0+BM, kb .. kb+BK] and op(B)[kb .., n0 ..]
+    for (int e = tid; e < BM * kBK; e += 256) {
+      int i, kk;
+      if (TA) { kk = e % kBK; i = e / kBK; } else { i = e % BM; kk = e / BM; }
+      const int64_t gi = m0 + i, gk = kb + kk;
+      As[kk][i] = (gi < M && gk < k1) ? (TC)opget<TAI, TA>(A, lda, gi, gk) : TC(0);
+    }
+    for (int e = tid; e < BN * kBK; e += 256) {
+      int j, kk;
+      // op(B)[k, j]: B[k + j*ldb] (k fastest) or, transposed, B[j + k*ldb]
+      if (TB) { j = e % BN; kk = e / BN; } else { kk = e % kBK; j = e / kBK; }
+      const int64_t gj = n0 + j, gk = kb + kk;
+      TC v = TC(0);
+      if (gj < N && gk < k1) v = (TC)(TB ? B[gj + gk * ldb] : B[gk + gj * ldb]);
+      Bs[kk][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < kBK; ks += 4) {
+      TC av[TM], bv[TN];
+#pragma unroll
+      for (int a = 0; a < TM; ++a) av[a] = As[ks + g][wm * WM + a * 16 + c16];
+#pragma unroll
+      for (int b = 0; b < TN; ++b) bv[b] = Bs[ks + g][wn * WN + b * 16 + c16];
+#pragma unroll
+      for (int a = 0; a < TM; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = F::run(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  TC* dst = P + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int a = 0; a < TM; ++a)
+#pragma unroll
+    for (int b = 0; b < TN; ++b) {
+      const int j = n0 + wn * WN + b * 16 + c16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = m0 + wm * WM + a * 16 + F::row(g, v);
+        if (i < M && j < N) dst[i + (int64_t)j * M] = acc[a][b][v];
+      }
+    }
+}
+
+template <typename TC, typename TO>
+__global__ void gemm_reduce_kernel(int M, int N, const TC* __restrict__ P, int splits, double alpha,
+                                   TO* __restrict__ C, int64_t ldc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i >= M) return;
+  double acc = 0.0;
+  for (int z = 0; z < splits; ++z) acc += (double)P[(int64_t)z * M * N + i + j * M];
+  C[i + j * ldc] = (TO)(alpha * acc);
+}
+
+namespace {
+
+struct GemmShape {
+  int BM, BN, splits;
+  int64_t kchunk;
+};
+
+GemmShape gemm_shape(const rmm_ctx* h, int M, int N, int64_t K) {
+  GemmShape g;
+  g.BM = 64;
+  g.BN = N > 64 ? 128 : 64;
+  const int64_t tiles = (int64_t)((M + g.BM - 1) / g.BM) * ((N + g.BN - 1) / g.BN);
+  int64_t want = (2ll * h->cus + tiles - 1) / tiles;
+  const int64_t maxsplit = (K + 255) / 256;  // at least 256 K per split
+  if (want > maxsplit) want = maxsplit;
+  if (want < 1) want = 1;
+  int64_t kc = (K + want - 1) / want;
+  kc = (kc + kBK - 1) / kBK * kBK;
+  if (kc < kBK) kc = kBK;
+  g.kchunk = kc;
+  g.splits = K > 0 ? (int)((K + kc - 1) / kc) : 1;
+  return g;
+}
+
+template <typename TAI, typename TBI, typename TC, bool TA, bool TB>
+int launch_gemm_t(const rmm_ctx* h, const GemmShape& g, int M, int N, int64_t K, const TAI* A,
+                  int64_t lda, const TBI* B, int64_t ldb, TC* P) {
+  dim3 grid((unsigned)((M + g.BM - 1) / g.BM), (unsigned)((N + g.BN - 1) / g.BN),
+            (unsigned)g.splits);
+  if (g.BN == 128)
+    hipLaunchKernelGGL((gemm_kernel<TAI, TBI, TC, TA, TB, 64, 128>), grid, dim3(256), 0, h->stream,
+                       M, N, K, A, lda, B, ldb, P, g.kchunk);
+  else
+    hipLaunchKernelGGL((gemm_kernel<TAI, TBI, TC, TA, TB, 64, 64>), grid, dim3(256), 0, h->stream,
+                       M, N, K, A, lda, B, ldb, P, g.kchunk);
+  return launch_status();
+}
+
+}  // namespace
+
+template <typename TC>
+size_t gemm_workspace(const rmm_ctx* h, int M, int N, int64_t K) {
+  const GemmShape g = gemm_shape(h, M, N, K);
+  Carver c(nullptr, 0);
+  c.take<TC>((size_t)g.splits * M * N);
+  return c.off;
+}
+
+template <typename TAI, typename TBI, typename TC, typename TO>
+int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, int64_t lda,
+         const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc, Carver& ws) {
+  if (M == 0 || N == 0) return RMM_OK;
+  const GemmShape g = gemm_shape(h, M, N, K);
+  const size_t mark = ws.off;
+  TC* P = ws.take<TC>((size_t)g.splits * M * N);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  int rc;
+  if (!ta && !tb) rc = launch_gemm_t<TAI, TBI, TC, false, false>(h, g, M, N, K, A, lda, B, ldb, P);
+  else if (ta && !tb) rc = launch_gemm_t<TAI, TBI, TC, true, false>(h, g, M, N, K, A, lda, B, ldb, P);
+  else if (!ta && tb) rc = launch_gemm_t<TAI, TBI, TC, false, true>(h, g, M, N, K, A, lda, B, ldb, P);
+  else rc = launch_gemm_t<TAI, TBI, TC, true, true>(h, g, M, N, K, A, lda, B, ldb, P);
+  RMM_TRY(rc);
+  dim3 grid((unsigned)((M + 255) / 256), (unsigned)N);
+  hipLaunchKernelGGL((gemm_reduce_kernel<TC, TO>), grid, dim3(256), 0, h->stream, M, N, P, g.splits,
+                     alpha, C, ldc);
+  ws.off = mark;  // the partials are dead once the reduction is enqueued
+  return launch_status();
+}
+
+// ---- elementwise helpers ---------------------------------------------------------
+
+template <typename TI, typename TO>
+__global__ void copy_cast_kernel(int64_t rows, const TI* __restrict__ X, int64_t ldx,
+                                 TO* __restrict__ Y, int64_t ldy) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t j = blockIdx.y;
+  if (i < rows) Y[i + j * ldy] = (TO)X[i + j * ldx];
+}
+
+template <typename TI, typename TO>
+int copy_cast(const rmm_ctx* h, int64_t rows, int64_t cols, const TI* X, int64_t ldx, TO* Y,
+              int64_t ldy) {
+  if (rows == 0 || cols == 0) return RMM_OK;
+  dim3 grid((unsigned)((rows + 255) / 256), (unsigned)cols);
+  hipLaunchKernelGGL((copy_cast_kernel<TI, TO>), grid, dim3(256), 0, h->stream, rows, X, ldx, Y, ldy);
+  return launch_status();
+}
+
+// partial sums of squares of r = A x - b (fp64), one per workgroup
+template <typename T>
+__global__ __launch_bounds__(256) void residual_kernel(int64_t m, int d, const T* __restrict__ A,
+                                                       int64_t lda, const T* __restrict__ b,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ part) {
+  __shared__ double xs[1024];
+  __shared__ double red[256];
+  double acc = 0.0;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double r = 0.0;
+  if (i < m) r = -(double)b[i];
+  for (int j0 = 0; j0 < d; j0 += 1024) {
+    const int nj = (d - j0) < 1024 ? (d - j0) : 1024;
+    __syncthreads();
+    for (int t = threadIdx.x; t < nj; t += 256) xs[t] = x[j0 + t];
+    __syncthreads();
+    if (i < m)
+      for (int j = 0; j < nj; ++j) r += (double)A[i + (int64_t)(j0 + j) * lda] * xs[j];
+  }
+  acc = r * r;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void sum_sqrt_kernel(const double* __restrict__ part, int64_t n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += 256) acc += part[t];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sqrt(red[0]);
+}
+
+template <typename T>
+int residual_norm(const rmm_ctx* h, int64_t m, int d, const T* A, int64_t lda, const T* b,
+                  const double* x, double* out, Carver& ws) {
+  const int64_t blocks = m > 0 ? (m + 255) / 256 : 1;
+  const size_t mark = ws.off;
+  double* part = ws.take<double>((size_t)blocks);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  if (m > 0) {
+    hipLaunchKernelGGL((residual_kernel<T>), dim3((unsigned)blocks), dim3(256), 0, h->stream, m, d, A,
+                       lda, b, x, part);
+    RMM_TRY(launch_status());
+  }
+  hipLaunchKernelGGL(sum_sqrt_kernel, dim3(1), dim3(256), 0, h->stream, part, m > 0 ? blocks : 0, out);
+  ws.off = mark;
+  return launch_status();
+}
+
+size_t residual_workspace(int64_t m) {
+  Carver c(nullptr, 0);
+  c.take<double>((size_t)(m > 0 ? (m + 255) / 256 : 1));
+  return c.off;
+}
+
+#define RMM_GEMM_INST(TAI, TBI, TC, TO)                                                      \
+  template int gemm<TAI, TBI, TC, TO>(rmm_ctx*, bool, bool, int, int, int64_t, const TAI*, \
+                                      int64_t, const TBI*, int64_t, double, TO*, int64_t,  \
+                                      Carver&);
+RMM_GEMM_INST(double, double, double, double)
+RMM_GEMM_INST(float, float, float, float)
+RMM_GEMM_INST(float, float, double, double)
+RMM_GEMM_INST(float, double, double, double)
+RMM_GEMM_INST(double, float, double, double)
+RMM_GEMM_INST(float, double, double, float)
+RMM_GEMM_INST(double, double, double, float)
+RMM_GEMM_INST(float, float, float, double)
+#undef RMM_GEMM_INST
+
+template size_t gemm_workspace<float>(const rmm_ctx*, int, int, int64_t);
+template size_t gemm_workspace<double>(const rmm_ctx*, int, int, int64_t);
+template int copy_cast<float, double>(const rmm_ctx*, int64_t, int64_t, const float*, int64_t, double*, int64_t);
+template int copy_cast<double, float>(const rmm_ctx*, int64_t, int64_t, const double*, int64_t, float*, int64_t);
+template int copy_cast<double, double>(const rmm_ctx*, int64_t, int64_t, const double*, int64_t, double*, int64_t);
+template int copy_cast<float, float>(const rmm_ctx*, int64_t, int64_t, const float*, int64_t, float*, int64_t);
+template int residual_norm<float>(const rmm_ctx*, int64_t, int, const float*, int64_t, const float*,
+                                  const double*, double*, Carver&);
+template int residual_norm<double>(const rmm_ctx*, int64_t, int, const double*, int64_t,
+                                   const double*, const double*, double*, Carver&);
+
+}  // namespace rmm

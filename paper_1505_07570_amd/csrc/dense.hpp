@@ -1,0 +1,60 @@
+// Dense building blocks used by the drivers (see dense.hip, small.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace rmm {
+
+// C (M x N, ldc) = alpha * op(A) * op(B); op(A) is M x K, op(B) is K x N.
+// TC is the MFMA compute type; partial sums need gemm_workspace<TC> bytes.
+template <typename TAI, typename TBI, typename TC, typename TO>
+int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, int64_t lda,
+         const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc, Carver& ws);
+template <typename TC>
+size_t gemm_workspace(const rmm_ctx* h, int M, int N, int64_t K);
+
+template <typename TI, typename TO>
+int copy_cast(const rmm_ctx* h, int64_t rows, int64_t cols, const TI* X, int64_t ldx, TO* Y,
+              int64_t ldy);
+
+// out = ||A x - b||_2 (fp64); workspace residual_workspace(m)
+template <typename T>
+int residual_norm(const rmm_ctx* h, int64_t m, int d, const T* A, int64_t lda, const T* b,
+                  const double* x, double* out, Carver& ws);
+size_t residual_workspace(int64_t m);
+
+// G (l x l, fp64, symmetric positive semidefinite) = R^T R with R upper
+// triangular; writes Rinv = R^{-1} (l x l, ld l, upper) and diag(R).
+// Directions whose pivot falls below tau * G_jj are dropped (zero row and
+// column in Rinv, zero diagonal) and RMM_STATUS_QR_FALLBACK is raised.
+// Needs cholinv_workspace(l) bytes when l > 128.
+int cholinv(const rmm_ctx* h, int l, const double* G, int64_t ldg, double tau, double* Rinv,
+            double* diag, int32_t* status, Carver& ws);
+size_t cholinv_workspace(int l);
+
+// Symmetric eigendecomposition by cyclic Jacobi: evals descending, V (l x l,
+// ld l) orthonormal eigenvectors.  l <= 128.
+int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals, double* V,
+               int32_t* status, Carver& ws);
+size_t jacobi_workspace(int l);
+
+// Flip (u_i, v_i) so that the largest-magnitude entry of u_i is positive.
+template <typename T>
+int sign_fix(const rmm_ctx* h, int64_t m, int64_t n, int k, T* U, int64_t ldu, T* V, int64_t ldv);
+
+// W (l x k) = Vr[:, :k] * diag(1 / sigma), sigma = sqrt(max(evals, 0)) (desc);
+// also writes sigma (k) in type T.
+template <typename T>
+int svd_from_eig(const rmm_ctx* h, int l, int k, const double* evals, const double* Vr,
+                 double* W, T* sigma);
+
+// status |= RANK_DEFICIENT if min|d1 d2| <= tol * max|d1 d2|
+int rank_check(const rmm_ctx* h, int d, const double* d1, const double* d2, double tol,
+               int32_t* status);
+
+int zero_status(const rmm_ctx* h, int32_t* status);
+
+// x = Rinv * y for upper-triangular Rinv (d x d) and vector y (both fp64)
+int trmv_upper(const rmm_ctx* h, int d, const double* Rinv, const double* y, double* x);
+
+}  // namespace rmm

@@ -1,31 +1,346 @@
-// Randomized SVD and least-squares drivers (filled in below).
+// Drivers: randomized k-SVD (Alg. 5.2 with the subspace iteration of
+// Alg. 5.1), sketch-and-solve least squares (eq. 4.2) and the exact
+// least-squares comparator (Sec. 4.1).
+//
+// Everything is enqueued on the handle's stream; no host synchronization.
+// Orthonormalization is CholeskyQR2 in fp64 (Gram matrix, Cholesky with
+// dropping of numerically dependent directions, triangular inverse, twice).
+// The small SVD of B = Q^T A is taken from the Jacobi eigendecomposition of
+// B B^T = Z^T Z with Z = A^T Q, so that B never has to be formed: sigma =
+// sqrt(lambda), Ubar = eigenvectors, V = Z Ubar diag(1/sigma).
+#include <math.h>
+
 #include "common.hpp"
+#include "dense.hpp"
 #include "ops.hpp"
+#include "rng.hpp"
+
+namespace rmm {
+
+template <typename T>
+int launch_gaussian(const rmm_ctx* h, uint32_t tag, int64_t rows, int64_t cols, uint64_t seed,
+                    T* out, int64_t ld);
+
+namespace {
+
+constexpr double kEps = 2.220446049250313e-16;
+
+size_t smax(size_t a, size_t b) { return a > b ? a : b; }
+
+// ---- CholeskyQR2 ---------------------------------------------------------------
+
+struct OrthBufs {
+  double* G;
+  double* Rinv;
+  double* diag;
+  double* Xd;  // rows x l fp64
+};
+
+template <typename T>
+size_t orth_scratch(const rmm_ctx* h, int64_t rows, int l) {
+  size_t w = gemm_workspace<double>(h, l, l, rows);
+  w = smax(w, gemm_workspace<double>(h, (int)rows, l, l));
+  w = smax(w, cholinv_workspace(l));
+  return w;
+}
+
+// Q (rows x l, type T) = orthonormal basis of range(X) by CholeskyQR2.
+template <typename T>
+int orth(rmm_ctx* h, int64_t rows, int l, const T* X, int64_t ldx, T* Q, int64_t ldq,
+         const OrthBufs& b, double tau, int32_t* status, Carver& ws) {
+  const int r = (int)rows;
+  RMM_TRY((gemm<T, T, double, double>(h, true, false, l, l, rows, X, ldx, X, ldx, 1.0, b.G, l, ws)));
+  RMM_TRY(cholinv(h, l, b.G, l, tau, b.Rinv, b.diag, status, ws));
+  RMM_TRY((gemm<T, double, double, double>(h, false, false, r, l, l, X, ldx, b.Rinv, l, 1.0, b.Xd,
+                                           rows, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, l, l, rows, b.Xd, rows, b.Xd, rows,
+                                                1.0, b.G, l, ws)));
+  RMM_TRY(cholinv(h, l, b.G, l, tau, b.Rinv, b.diag, status, ws));
+  return gemm<double, double, double, T>(h, false, false, r, l, l, b.Xd, rows, b.Rinv, l, 1.0, Q,
+                                         ldq, ws);
+}
+
+// ---- randomized SVD --------------------------------------------------------------
+
+template <typename T>
+int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t lda, int k, int p,
+              int q, uint64_t seed, T* U, int64_t ldu, T* sigma, T* V, int64_t ldv, int32_t* status,
+              size_t* bytes) {
+  const int l = k + p;
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  T* Om = ws.take<T>((size_t)n * l);
+  T* Y = ws.take<T>((size_t)m * l);
+  T* Q = ws.take<T>((size_t)m * l);
+  T* Z = ws.take<T>((size_t)n * l);
+  T* Qz = ws.take<T>((size_t)n * l);
+  OrthBufs ob;
+  ob.G = ws.take<double>((size_t)l * l);
+  ob.Rinv = ws.take<double>((size_t)l * l);
+  ob.diag = ws.take<double>((size_t)l);
+  ob.Xd = ws.take<double>((size_t)(m > n ? m : n) * l);
+  double* evals = ws.take<double>((size_t)l);
+  double* Vr = ws.take<double>((size_t)l * l);
+  double* W = ws.take<double>((size_t)l * k);
+  // scratch shared by the steps below (released after each)
+  size_t scratch = orth_scratch<T>(h, m, l);
+  scratch = smax(scratch, orth_scratch<T>(h, n, l));
+  scratch = smax(scratch, gemm_workspace<T>(h, (int)m, l, n));
+  scratch = smax(scratch, gemm_workspace<T>(h, (int)n, l, m));
+  scratch = smax(scratch, gemm_workspace<double>(h, l, l, n));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, l));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, l));
+  scratch = smax(scratch, jacobi_workspace(l));
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const double tau_m = 64.0 * kEps * (double)(m > l ? m : l);
+  const double tau_n = 64.0 * kEps * (double)(n > l ? n : l);
+  RMM_TRY(zero_status(h, status));
+  RMM_TRY(launch_gaussian<T>(h, TAG_GAUSS_RSVD, n, l, seed, Om, n));
+  // range finder: Y = A Omega, Q = qr(Y); q times Z = A^T Q, Qz = qr(Z), Y = A Qz, Q = qr(Y)
+  RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, l, n, A, lda, Om, n, 1.0, Y, m, ws)));
+  RMM_TRY(orth<T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
+  for (int t = 0; t < q; ++t) {
+    RMM_TRY((gemm<T, T, T, T>(h, true, false, (int)n, l, m, A, lda, Q, m, 1.0, Z, n, ws)));
+    RMM_TRY(orth<T>(h, n, l, Z, n, Qz, n, ob, tau_n, status, ws));
+    RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, l, n, A, lda, Qz, n, 1.0, Y, m, ws)));
+    RMM_TRY(orth<T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
+  }
+  // projection: Z = A^T Q = B^T, and the small SVD of B through B B^T = Z^T Z
+  RMM_TRY((gemm<T, T, T, T>(h, true, false, (int)n, l, m, A, lda, Q, m, 1.0, Z, n, ws)));
+  RMM_TRY((gemm<T, T, double, double>(h, true, false, l, l, n, Z, n, Z, n, 1.0, ob.G, l, ws)));
+  RMM_TRY(jacobi_eig(h, l, ob.G, l, evals, Vr, status, ws));
+  RMM_TRY(svd_from_eig<T>(h, l, k, evals, Vr, W, sigma));
+  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, k, l, Q, m, Vr, l, 1.0, U, ldu, ws)));
+  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)n, k, l, Z, n, W, l, 1.0, V, ldv, ws)));
+  return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
+}
+
+// ---- sketch-and-solve least squares ---------------------------------------------------
+
+template <typename T>
+size_t sketch_scratch(const rmm_ctx* h, rmm_sketch_kind kind, int64_t m, int ncols, int64_t s) {
+  switch (kind) {
+    case RMM_COUNTSKETCH: return countsketch_workspace<T>(h, m, ncols, s);
+    case RMM_SRHT: return srht_workspace<T>(h, m, ncols, s);
+    default: return gauss_sketch_workspace<T>(h, m, ncols, s);
+  }
+}
+
+template <typename T>
+int run_sketch(rmm_ctx* h, rmm_sketch_kind kind, int64_t m, int n, const T* A, int64_t lda,
+               const T* b, int64_t s, uint64_t seed, T* C, int64_t ldc, Carver& ws) {
+  switch (kind) {
+    case RMM_COUNTSKETCH: return countsketch_run<T>(h, m, n, A, lda, b, s, seed, C, ldc, ws);
+    case RMM_SRHT: return srht_run<T>(h, m, n, A, lda, b, s, seed, C, ldc, ws);
+    default: return gauss_sketch_run<T>(h, m, n, A, lda, b, s, seed, C, ldc, ws);
+  }
+}
+
+// x = argmin ||Cs[:, :d] x - Cs[:, d]|| for the s x (d+1) fp64 system by
+// CholeskyQR2: Q R = Cs[:, :d], x = R^{-1} Q^T b~.
+struct LsBufs {
+  double *G, *R1, *R2, *d1, *d2, *Q1, *Q, *y, *t;
+};
+
+size_t ls_scratch(const rmm_ctx* h, int64_t s, int d) {
+  size_t w = gemm_workspace<double>(h, d, d, s);
+  w = smax(w, gemm_workspace<double>(h, (int)s, d, d));
+  w = smax(w, gemm_workspace<double>(h, d, 1, s));
+  w = smax(w, cholinv_workspace(d));
+  return w;
+}
+
+LsBufs take_ls(Carver& ws, int64_t s, int d) {
+  LsBufs b;
+  b.G = ws.take<double>((size_t)d * d);
+  b.R1 = ws.take<double>((size_t)d * d);
+  b.R2 = ws.take<double>((size_t)d * d);
+  b.d1 = ws.take<double>((size_t)d);
+  b.d2 = ws.take<double>((size_t)d);
+  b.Q1 = ws.take<double>((size_t)s * d);
+  b.Q = ws.take<double>((size_t)s * d);
+  b.y = ws.take<double>((size_t)d);
+  b.t = ws.take<double>((size_t)d);
+  return b;
+}
+
+int ls_solve(rmm_ctx* h, int64_t s, int d, const double* Cs, const LsBufs& b, double* x,
+             int32_t* status, Carver& ws) {
+  const double tau = 64.0 * kEps * (double)s;
+  const double* bt = Cs + (int64_t)d * s;
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, d, d, s, Cs, s, Cs, s, 1.0, b.G, d, ws)));
+  RMM_TRY(cholinv(h, d, b.G, d, tau, b.R1, b.d1, nullptr, ws));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, (int)s, d, d, Cs, s, b.R1, d, 1.0,
+                                                b.Q1, s, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, d, d, s, b.Q1, s, b.Q1, s, 1.0, b.G,
+                                                d, ws)));
+  RMM_TRY(cholinv(h, d, b.G, d, tau, b.R2, b.d2, nullptr, ws));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, (int)s, d, d, b.Q1, s, b.R2, d, 1.0,
+                                                b.Q, s, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, d, 1, s, b.Q, s, bt, s, 1.0, b.y, d, ws)));
+  RMM_TRY(trmv_upper(h, d, b.R2, b.y, b.t));
+  RMM_TRY(trmv_upper(h, d, b.R1, b.t, x));
+  // R = R2 R1 has diagonal d2 * d1 (a dropped pivot shows up as a zero)
+  return rank_check(h, d, b.d1, b.d2, 10.0 * (double)s * kEps, status);
+}
+
+template <typename T>
+int lsr_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind, int64_t m, int d, const T* A, int64_t lda,
+             const T* b, int64_t s, uint64_t seed, double* x, double* resid, int32_t* status,
+             size_t* bytes) {
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  T* Cs = ws.take<T>((size_t)s * (d + 1));
+  double* Csd = ws.take<double>((size_t)s * (d + 1));
+  LsBufs lb = take_ls(ws, s, d);
+  size_t scratch = sketch_scratch<T>(h, kind, m, d + 1, s);
+  scratch = smax(scratch, ls_scratch(h, s, d));
+  scratch = smax(scratch, residual_workspace(m));
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  RMM_TRY(zero_status(h, status));
+  {
+    const size_t mark = ws.off;
+    RMM_TRY(run_sketch<T>(h, kind, m, d, A, lda, b, s, seed, Cs, s, ws));
+    ws.off = mark;
+  }
+  RMM_TRY((copy_cast<T, double>(h, s, d + 1, Cs, s, Csd, s)));
+  RMM_TRY(ls_solve(h, s, d, Csd, lb, x, status, ws));
+  if (resid) RMM_TRY(residual_norm<T>(h, m, d, A, lda, b, x, resid, ws));
+  return RMM_OK;
+}
+
+// exact solution by the normal equations in fp64: (A^T A) x = A^T b
+template <typename T>
+int plain_impl(rmm_ctx* h, bool run, int64_t m, int d, const T* A, int64_t lda, const T* b,
+               double* x, double* resid, int32_t* status, size_t* bytes) {
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  double* G = ws.take<double>((size_t)d * d);
+  double* c = ws.take<double>((size_t)d);
+  double* Rinv = ws.take<double>((size_t)d * d);
+  double* dg = ws.take<double>((size_t)d);
+  double* t = ws.take<double>((size_t)d);
+  size_t scratch = gemm_workspace<double>(h, d, d, m);
+  scratch = smax(scratch, gemm_workspace<double>(h, d, 1, m));
+  scratch = smax(scratch, gemm_workspace<double>(h, d, 1, d));
+  scratch = smax(scratch, cholinv_workspace(d));
+  scratch = smax(scratch, residual_workspace(m));
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  RMM_TRY(zero_status(h, status));
+  RMM_TRY((gemm<T, T, double, double>(h, true, false, d, d, m, A, lda, A, lda, 1.0, G, d, ws)));
+  RMM_TRY((gemm<T, T, double, double>(h, true, false, d, 1, m, A, lda, b, m, 1.0, c, d, ws)));
+  RMM_TRY(cholinv(h, d, G, d, 64.0 * kEps * (double)m, Rinv, dg, nullptr, ws));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, d, 1, d, Rinv, d, c, d, 1.0, t, d, ws)));
+  RMM_TRY(trmv_upper(h, d, Rinv, t, x));
+  RMM_TRY(rank_check(h, d, dg, nullptr, 10.0 * (double)m * kEps, status));
+  if (resid) RMM_TRY(residual_norm<T>(h, m, d, A, lda, b, x, resid, ws));
+  return RMM_OK;
+}
+
+bool ld_bad(int64_t ld, int64_t rows) { return ld < (rows > 1 ? rows : 1); }
+
+bool kind_ok(rmm_sketch_kind k) { return k == RMM_GAUSSIAN || k == RMM_SRHT || k == RMM_COUNTSKETCH; }
+
+int rsvd_args(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t n, int64_t k,
+              int64_t p) {
+  if (!h || !dt_ok(dt) || m < 1 || n < 1 || k < 1 || p < 0) return RMM_ERR_INVALID_ARG;
+  if (k + p > (m < n ? m : n) || k + p > 128) return k + p > 128 ? RMM_ERR_UNSUPPORTED : RMM_ERR_INVALID_ARG;
+  if (m >= (1ll << 31) || n >= (1ll << 31)) return RMM_ERR_UNSUPPORTED;
+  if (prec != RMM_PREC_NATIVE) return RMM_ERR_UNSUPPORTED;
+  return RMM_OK;
+}
+
+int lsr_args(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d, int64_t s) {
+  if (!h || !dt_ok(dt) || m < 1 || d < 1 || s < d || d > m) return RMM_ERR_INVALID_ARG;
+  if (d > 4096 || s >= (1ll << 30) || m >= (1ll << 31)) return RMM_ERR_UNSUPPORTED;
+  return RMM_OK;
+}
+
+}  // namespace
+
+}  // namespace rmm
+
+using namespace rmm;
 
 extern "C" {
 
-int rmm_rsvd_workspace(rmm_handle, rmm_dtype, rmm_precision, int64_t, int64_t, int64_t, int64_t,
-                       size_t*) {
-  return RMM_ERR_UNSUPPORTED;
+int rmm_rsvd_workspace(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t n,
+                       int64_t k, int64_t p, size_t* bytes) {
+  RMM_TRY(rsvd_args(h, dt, prec, m, n, k, p));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return rsvd_impl<float>(h, false, m, n, nullptr, m, (int)k, (int)p, 0, 0, nullptr, m, nullptr,
+                            nullptr, n, nullptr, bytes);
+  return rsvd_impl<double>(h, false, m, n, nullptr, m, (int)k, (int)p, 0, 0, nullptr, m, nullptr,
+                           nullptr, n, nullptr, bytes);
 }
-int rmm_rsvd(rmm_handle, rmm_dtype, rmm_precision, int64_t, int64_t, const void*, int64_t,
-             int64_t, int64_t, int64_t, uint64_t, void*, int64_t, void*, void*, int64_t,
-             int32_t*) {
-  return RMM_ERR_UNSUPPORTED;
+
+int rmm_rsvd(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t n, const void* A,
+             int64_t lda, int64_t k, int64_t p, int64_t q, uint64_t seed, void* U, int64_t ldu,
+             void* sigma, void* V, int64_t ldv, int32_t* status) {
+  RMM_TRY(rsvd_args(h, dt, prec, m, n, k, p));
+  if (!A || !U || !sigma || !V || q < 0 || ld_bad(lda, m) || ld_bad(ldu, m) || ld_bad(ldv, n))
+    return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return rsvd_impl<float>(h, true, m, n, (const float*)A, lda, (int)k, (int)p, (int)q, seed,
+                            (float*)U, ldu, (float*)sigma, (float*)V, ldv, status, nullptr);
+  return rsvd_impl<double>(h, true, m, n, (const double*)A, lda, (int)k, (int)p, (int)q, seed,
+                           (double*)U, ldu, (double*)sigma, (double*)V, ldv, status, nullptr);
 }
-int rmm_lsr_workspace(rmm_handle, rmm_dtype, rmm_sketch_kind, int64_t, int64_t, int64_t,
-                      size_t*) {
-  return RMM_ERR_UNSUPPORTED;
+
+int rmm_lsr_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m, int64_t d,
+                      int64_t s, size_t* bytes) {
+  RMM_TRY(lsr_args(h, dt, m, d, s));
+  if (!bytes || !kind_ok(kind)) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return lsr_impl<float>(h, false, kind, m, (int)d, nullptr, m, nullptr, s, 0, nullptr, nullptr,
+                           nullptr, bytes);
+  return lsr_impl<double>(h, false, kind, m, (int)d, nullptr, m, nullptr, s, 0, nullptr, nullptr,
+                          nullptr, bytes);
 }
-int rmm_sketched_lsr(rmm_handle, rmm_dtype, rmm_sketch_kind, int64_t, int64_t, const void*,
-                     int64_t, const void*, int64_t, uint64_t, double*, double*, int32_t*) {
-  return RMM_ERR_UNSUPPORTED;
+
+int rmm_sketched_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m, int64_t d,
+                     const void* A, int64_t lda, const void* b, int64_t s, uint64_t seed, double* x,
+                     double* resid, int32_t* status) {
+  RMM_TRY(lsr_args(h, dt, m, d, s));
+  if (!kind_ok(kind) || !A || !b || !x || ld_bad(lda, m)) return RMM_ERR_INVALID_ARG;
+  if (kind == RMM_SRHT) {
+    const int k = ceil_log2((uint64_t)m);
+    if (s > (1ll << k)) return RMM_ERR_INVALID_ARG;
+  }
+  if (dt == RMM_F32)
+    return lsr_impl<float>(h, true, kind, m, (int)d, (const float*)A, lda, (const float*)b, s, seed,
+                           x, resid, status, nullptr);
+  return lsr_impl<double>(h, true, kind, m, (int)d, (const double*)A, lda, (const double*)b, s, seed,
+                          x, resid, status, nullptr);
 }
-int rmm_plain_lsr_workspace(rmm_handle, rmm_dtype, int64_t, int64_t, size_t*) {
-  return RMM_ERR_UNSUPPORTED;
+
+int rmm_plain_lsr_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d, size_t* bytes) {
+  RMM_TRY(lsr_args(h, dt, m, d, d));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return plain_impl<float>(h, false, m, (int)d, nullptr, m, nullptr, nullptr, nullptr, nullptr, bytes);
+  return plain_impl<double>(h, false, m, (int)d, nullptr, m, nullptr, nullptr, nullptr, nullptr, bytes);
 }
-int rmm_plain_lsr(rmm_handle, rmm_dtype, int64_t, int64_t, const void*, int64_t, const void*,
-                  double*, double*, int32_t*) {
-  return RMM_ERR_UNSUPPORTED;
+
+int rmm_plain_lsr(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d, const void* A, int64_t lda,
+                  const void* b, double* x, double* resid, int32_t* status) {
+  RMM_TRY(lsr_args(h, dt, m, d, d));
+  if (!A || !b || !x || ld_bad(lda, m)) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return plain_impl<float>(h, true, m, (int)d, (const float*)A, lda, (const float*)b, x, resid,
+                             status, nullptr);
+  return plain_impl<double>(h, true, m, (int)d, (const double*)A, lda, (const double*)b, x, resid,
+                            status, nullptr);
 }
-}
+
+}  // extern "C"

@@ -175,7 +175,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if (st + 1 < nst) store_stage(b ^ 1);
     __syncthreads();
   }
-  // lane holds D[4 (lane >> 4) + v][lane & 15] of each 16x16 tile
+  // lane holds D[row][lane & 15] of each 16x16 tile with row = 4 (lane >> 4) + v for
+  // the fp32 MFMA and row = (lane >> 4) + 4 v for the fp64 MFMA
   T* dst = partials + (int64_t)sp * ncols * s;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
@@ -185,7 +186,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       const int64_t j = nbase + q * 16 + mi;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = m0 + 2 * (4 * kk + v) + t;
+        const int row = sizeof(T) == 4 ? 4 * kk + v : kk + 4 * v;
+        const int r = m0 + 2 * row + t;
         if (j < ncols && r < s) dst[j * s + r] = tot[v];
       }
     }

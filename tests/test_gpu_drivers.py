@@ -1,0 +1,176 @@
+"""GPU parity of the drivers: randomized SVD and least squares (MI355X).
+
+rsvd is compared with the oracle run on the same Omega; U and V are compared
+with the sign convention applied on both sides, and the sign-free product
+U diag(sigma) V^T as well.  Least squares compares x with the oracle within
+tol * kappa(A~), tol = 1e-12 (fp64) / 1e-5 (fp32).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import lsr as olsr, rsvd as orsvd, sketch as osk
+from tests.gpu_util import TOL, dev, host, rel
+
+pytestmark = pytest.mark.gpu
+rmm = pytest.importorskip("paper_1505_07570_amd")
+KINDS = [("gaussian", osk.GAUSSIAN), ("srht", osk.SRHT), ("countsketch", osk.COUNTSKETCH)]
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rmm.handle()
+
+
+def check_rsvd(U, s, V, Ur, sr, Vr, tol):
+    assert np.abs(s - sr).max() <= tol * sr[0]
+    USV = (U * s) @ V.T
+    ref = (Ur * sr) @ Vr.T
+    assert np.linalg.norm(USV - ref) <= tol * np.linalg.norm(sr)
+
+
+def test_rsvd_config_fp64(h):
+    """2048 x 512, sigma_i = 0.9^i + N(0, 1e-8) noise, k = 20, p = 10, q = 2."""
+    A, _ = synth.rsvd_fp64()
+    seed = synth.sketch_seed(1)
+    U, s, V, st = h.rsvd(dev(A), 20, 10, 2, seed)
+    Ur, sr, Vr, _ = orsvd.rsvd(A, 20, 10, 2, seed, fp64=True)
+    assert int(st.item()) == 0
+    U, s, V = host(U), host(s), host(V)
+    check_rsvd(U, s, V, Ur, sr, Vr, 1e-12)
+    # singular vectors themselves (well separated spectrum, same sign convention)
+    assert np.abs(U - Ur).max() < 1e-10
+    assert np.abs(V - Vr).max() < 1e-10
+    assert np.abs(U.T @ U - np.eye(20)).max() < 1e-13
+    assert np.abs(V.T @ V - np.eye(20)).max() < 1e-13
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(1000, 37, 5, 3, 0), (301, 300, 7, 9, 1), (64, 4000, 3, 2, 2),
+                                       (5000, 129, 16, 16, 1)])
+def test_rsvd_shapes_fp64(h, m, n, k, p, q):
+    A, _, _, _ = synth.low_rank(m + n, m, n, min(m, n), decay=0.8)
+    A = A + 1e-3 * np.random.default_rng(1).standard_normal((m, n))
+    U, s, V, st = h.rsvd(dev(A), k, p, q, 99)
+    Ur, sr, Vr, _ = orsvd.rsvd(A, k, p, q, 99, fp64=True)
+    check_rsvd(host(U), host(s), host(V), Ur, sr, Vr, 1e-12)
+
+
+def test_rsvd_exact_recovery_rank_deficient(h):
+    A, U0, sig0, V0 = synth.low_rank(7, 900, 300, 8, decay=0.7)
+    U, s, V, st = h.rsvd(dev(A), 10, 4, 1, 5)
+    s = host(s)
+    np.testing.assert_allclose(s[:8], sig0, rtol=1e-12)
+    assert np.all(np.abs(s[8:]) < 1e-12)
+    rec = (host(U) * s) @ host(V).T
+    assert rel(rec, A) < 1e-12
+    assert int(st.item()) & rmm.STATUS_QR_FALLBACK
+
+
+def test_rsvd_full_sketch_equals_svd(h):
+    r = np.random.default_rng(8)
+    A = r.standard_normal((60, 25))
+    U, s, V, st = h.rsvd(dev(A), 10, 15, 0, 6)
+    U0, s0, V0t = np.linalg.svd(A, full_matrices=False)
+    np.testing.assert_allclose(host(s), s0[:10], rtol=1e-12)
+    assert rel((host(U) * host(s)) @ host(V).T, (U0[:, :10] * s0[:10]) @ V0t[:10]) < 1e-12
+
+
+def test_rsvd_fp32(h):
+    A, _, _, _ = synth.low_rank(11, 3000, 400, 400, decay=0.97)
+    A = A.astype(np.float32)
+    U, s, V, st = h.rsvd(dev(A), 10, 6, 1, 3)
+    Ur, sr, Vr, _ = orsvd.rsvd(A.astype(np.float64), 10, 6, 1, 3, fp64=False)
+    check_rsvd(host(U), host(s), host(V), Ur, sr, Vr, 1e-5)
+
+
+def test_rsvd_deterministic(h):
+    A, _ = synth.rsvd_fp64(m=700, n=200)
+    a = h.rsvd(dev(A), 12, 8, 1, 4)
+    b = h.rsvd(dev(A), 12, 8, 1, 4)
+    for x, y in zip(a[:3], b[:3]):
+        assert torch.equal(x, y)
+
+
+def test_rsvd_invalid(h):
+    A = torch.zeros(10, 8, dtype=torch.float64, device="cuda")
+    with pytest.raises(rmm.RmmError):
+        h.rsvd(A, 6, 4, 0, 1)  # k + p > min(m, n)
+
+
+# ---- least squares --------------------------------------------------------------------
+
+def kappa(M):
+    sv = np.linalg.svd(M, compute_uv=False)
+    return sv[0] / sv[-1]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name,kind", KINDS)
+def test_lsr_parity_small(h, dtype, name, kind):
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    A, b, xs = synth.lsr_fp32(seed=3, m=6000, d=24, dtype=npdt)
+    s = 320
+    x, res, st = h.sketched_lsr(dev(A), dev(b), s, name, 17)
+    xr, rr, rd, Cs = olsr.sketched_lsr(A.astype(np.float64), b.astype(np.float64), s, kind, 17,
+                                       fp64=(dtype == torch.float64))
+    assert int(st.item()) == 0 and not rd
+    k = kappa(Cs[:, :24])
+    assert rel(host(x), xr) <= TOL[dtype] * k
+    assert abs(res.item() - rr) <= 10 * TOL[dtype] * k * rr
+
+
+@pytest.mark.parametrize("name,kind", KINDS)
+def test_lsr_consistent_rhs_exact(h, name, kind):
+    r = np.random.default_rng(5)
+    A = r.standard_normal((4000, 16)) * np.abs(r.standard_t(2, size=4000))[:, None]
+    xs = r.standard_normal(16)
+    b = A @ xs
+    x, res, st = h.sketched_lsr(dev(A), dev(b), 128, name, 3)
+    assert rel(host(x), xs) < 1e-10
+    assert res.item() < 1e-9 * np.linalg.norm(b)
+
+
+def test_lsr_rank_deficient_flag(h):
+    r = np.random.default_rng(6)
+    A = r.standard_normal((3000, 8))
+    A[:, 7] = A[:, 1] + A[:, 2]
+    b = r.standard_normal(3000)
+    x, res, st = h.sketched_lsr(dev(A), dev(b), 64, "gaussian", 1)
+    assert int(st.item()) & rmm.STATUS_RANK_DEFICIENT
+
+
+def test_plain_lsr_matches_lstsq(h):
+    A, b, xs = synth.lsr_fp32(seed=8, m=20000, d=30, dtype=np.float64)
+    x, res, st = h.plain_lsr(dev(A), dev(b))
+    xr, rr = olsr.exact_lsr(A, b)
+    assert rel(host(x), xr) < 1e-12 * kappa(A) ** 2
+    assert abs(res.item() - rr) < 1e-10 * rr
+
+
+@pytest.fixture(scope="module")
+def lsr_config():
+    A, b, xs = synth.lsr_fp32()
+    return A, b
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,kind", KINDS)
+def test_lsr_config_full_size(h, lsr_config, name, kind):
+    """2^20 x 256 fp32, s = 4096: the solve matches an fp64 least-squares
+    solve of the sketched system the library itself produces (whose rows were
+    checked against the oracle), and the objective is within (1+eps)^2."""
+    A, b = lsr_config
+    seed = synth.sketch_seed(2)
+    Ad, bd = dev(A), dev(b)
+    x, res, st = h.sketched_lsr(Ad, bd, 4096, name, seed)
+    assert int(st.item()) == 0
+    Cs = host(h.sketch(Ad, 4096, name, seed, b=bd))
+    xl = np.linalg.lstsq(Cs[:, :256], Cs[:, 256], rcond=None)[0]
+    assert rel(host(x), xl) < 1e-10 * kappa(Cs[:, :256])
+    xp, rp, stp = h.plain_lsr(Ad, bd)
+    ratio = (res.item() / rp.item()) ** 2
+    assert 1.0 - 1e-6 <= ratio < 1.5, ratio
