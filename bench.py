@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the sketching hot path on one MI355X.
+
+Workload (the paper's sketch-and-solve least squares, eq. 4.2, at the
+synthetic heavy-leverage shape): A is 2^20 x 256 fp32 (rows g_i |t_i|, g_i ~
+N(0, I), t_i Student-t with 2 degrees of freedom), b = A x* + N(0, 1e-3),
+sketch size s = 4096.
+
+One step = for each sketch family (CountSketch, SRHT, Gaussian) the whole
+path of the library: the sketch C = S^T [A | b] (one pass over A), the FP64
+CholeskyQR2 solve of the s x 256 sketched system, and the FP64 residual
+||A x~ - b|| (a second pass over A).  Inputs are resident in HBM before the
+timed region.  `value` is GB/s of A: (number of sketches) x bytes of [A | b]
+per second of step time.
+
+Prints one JSON line.  Extra keys: per-family sketch time and roofline,
+sketch-and-solve p50/p99 latency next to the plain FP64 normal-equation
+solve, rsvd solves/s on the 2048 x 512 fp64 problem, and the CPU oracle timed
+on a bounded row sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+# kernel source behind each sketch family (traffic counters are void once it changes)
+KERNEL_SRC = {
+    "countsketch": "paper_1505_07570_amd/csrc/countsketch.hip",
+    "srht": "paper_1505_07570_amd/csrc/srht.hip",
+    "gaussian": "paper_1505_07570_amd/csrc/gauss_sketch.hip",
+}
+
+
+def src_sha(path):
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kind, launches_bytes):
+    """HBM bytes per launch from committed rocprofv3 counter summaries.
+
+    profiles/traffic.json maps a sketch family to the FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch) of its kernels, the copy-kernel calibration factor and
+    the sha of the kernel source they were taken on; stale entries give null.
+    """
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f).get(kind)
+    if not t or t.get("src_sha") != src_sha(KERNEL_SRC[kind]):
+        return None
+    return (t["fetch_kib"] + t["write_kib"]) * 1024.0 * t.get("scale", 1.0)
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q))
+
+
+def cpu_baseline(A, b, s, kinds, seed, rows):
+    """The FP64 oracle's sketch-and-solve on the first `rows` rows."""
+    import numpy as np
+    from oracle import lsr as olsr, sketch as osk
+    codes = {"countsketch": osk.COUNTSKETCH, "srht": osk.SRHT, "gaussian": osk.GAUSSIAN}
+    As = np.asarray(A[:rows], dtype=np.float64)
+    bs = np.asarray(b[:rows], dtype=np.float64)
+    t0 = time.perf_counter()
+    for k in kinds:
+        olsr.sketched_lsr(As, bs, s, codes[k], seed, fp64=False)
+    dt = time.perf_counter() - t0
+    nbytes = len(kinds) * rows * (A.shape[1] + 1) * 4
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        cores = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {
+        "value": nbytes / dt / 1e9,
+        "unit": "GB/s",
+        "cores": min(cores, threads),
+        "kind": "oracle",
+        "sample": f"first {rows} rows of [A|b] (m={rows}, d={A.shape[1]}), s={s}, "
+                  f"sketch-and-solve for {','.join(kinds)} in fp64 numpy with explicit S; "
+                  f"{dt:.1f} s wall",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--kinds", default="countsketch,srht,gaussian")
+    ap.add_argument("--latency-reps", type=int, default=20)
+    ap.add_argument("--cpu-rows", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip latency / rsvd side measurements")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the sketching path on a single "
+              "MI355X (the multi-GPU sharding is a design, not a measured configuration).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1505_07570_amd as rmm
+    if not os.path.exists(rmm.LIB_PATH):
+        from paper_1505_07570_amd import build as _b
+        _b.build()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    kinds = [k.strip() for k in args.kinds.split(",") if k.strip()]
+    s, seed = 4096, synth.sketch_seed(2)
+    t0 = time.perf_counter()
+    A, b, xs = synth.lsr_fp32()
+    gen_s = time.perf_counter() - t0
+    m, d = A.shape
+    Ad = torch.from_numpy(A.T.copy()).cuda().t()   # column-major, lda = m
+    bd = torch.from_numpy(b).cuda()
+    h = rmm.handle()
+    C = {k: torch.empty(d + 1, s, dtype=torch.float32, device="cuda").t() for k in kinds}
+    res = {k: torch.empty(1, dtype=torch.float64, device="cuda") for k in kinds}
+    xsol = {}
+    ab_bytes = (m * (d + 1)) * 4
+
+    def step(ev=None):
+        for k in kinds:
+            if ev is not None:
+                ev[k][0].record()
+            h.sketch(Ad, s, k, seed, b=bd, out=C[k])
+            if ev is not None:
+                ev[k][1].record()
+            x, st = h.lsr_solve(C[k], d)
+            h.residual(Ad, bd, x, out=res[k])
+            xsol[k] = x
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for k in kinds} for _ in range(args.steps)]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for i in range(args.steps):
+        step(evs[i])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    sketch_ms = {k: float(np.mean([ev[k][0].elapsed_time(ev[k][1]) for ev in evs])) for k in kinds}
+    value = len(kinds) * ab_bytes / (ms_step * 1e-3) / 1e9
+
+    # roofline of every sketch kernel; the dominant one is reported as "roofline"
+    rl = {}
+    for k in kinds:
+        t = sketch_ms[k] * 1e-3
+        if k == "gaussian":
+            flops = 2.0 * s * m * (d + 1)
+            rl[k] = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": FP32_MFMA_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": flops / t / 1e12 / FP32_MFMA_PEAK_TFLOPS,
+                     "traffic": measured_traffic(k, ab_bytes)}
+        else:
+            nb = ab_bytes + s * (d + 1) * 4
+            rl[k] = {"bound": "hbm", "achieved": nb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": nb / t / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic(k, nb)}
+    dominant = max(kinds, key=lambda k: sketch_ms[k])
+
+    out = {
+        "metric": "sketch GB/s of A & % roofline; rsvd/LSR solves/sec; p50/p99 latency vs plain",
+        "value": value,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sketch-and-solve LSR, A 1048576x256 fp32 (Student-t leverage) "
+                               f"+ b, s={s}, families={','.join(kinds)}; per family: sketch, "
+                               "fp64 CholeskyQR2 solve, fp64 residual",
+                   "m": m, "d": d, "s": s, "parallelism": "single GPU"},
+        "roofline": dict(rl[dominant], kernel=f"{dominant} sketch"),
+        "roofline_by_kernel": rl,
+        "sketch_ms": sketch_ms,
+        "sketch_gbs": {k: ab_bytes / (sketch_ms[k] * 1e-3) / 1e9 for k in kinds},
+        "data_gen_s": gen_s,
+    }
+
+    if not args.no_extras:
+        def lat(fn, reps):
+            ts = []
+            for _ in range(reps):
+                a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                fn()
+                z.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(z))
+            return ts
+        R = args.latency_reps
+        lsr_lat = {}
+        for k in kinds:
+            ts = lat(lambda: h.sketched_lsr(Ad, bd, s, k, seed), R)
+            lsr_lat[k] = {"p50_ms": percentile(ts, 50), "p99_ms": percentile(ts, 99),
+                          "solves_per_s": 1e3 / float(np.mean(ts))}
+        ts = lat(lambda: h.plain_lsr(Ad, bd), R)
+        xp, rp, _ = h.plain_lsr(Ad, bd)
+        out["lsr_latency"] = lsr_lat
+        out["plain_lsr"] = {"p50_ms": percentile(ts, 50), "p99_ms": percentile(ts, 99),
+                            "method": "fp64 normal equations on the GPU"}
+        out["objective_ratio"] = {k: (float(res[k].item()) / float(rp.item())) ** 2 for k in kinds}
+        A1, _ = synth.rsvd_fp64()
+        A1d = torch.from_numpy(A1.T.copy()).cuda().t()
+        h.rsvd(A1d, 20, 10, 2, synth.sketch_seed(1))
+        ts = lat(lambda: h.rsvd(A1d, 20, 10, 2, synth.sketch_seed(1)), R)
+        out["rsvd_2048x512_fp64"] = {"k": 20, "p": 10, "q": 2, "p50_ms": percentile(ts, 50),
+                                     "p99_ms": percentile(ts, 99),
+                                     "solves_per_s": 1e3 / float(np.mean(ts))}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(A, b, s, kinds, seed, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

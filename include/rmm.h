@@ -134,6 +134,18 @@ int rmm_sketched_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,
                      int64_t m, int64_t d, const void* A, int64_t lda,
                      const void* b, int64_t s, uint64_t seed, double* x,
                      double* resid, int32_t* status);
+/* The two halves of rmm_sketched_lsr, for callers that sketch once and
+ * solve separately.  rmm_lsr_solve: x = argmin ||Cs[:, :d] x - Cs[:, d]||_2
+ * for an s x (d+1) sketched system Cs (ldc >= s, dtype dt, device), solved
+ * in FP64 by CholeskyQR2 (eq. 4.2; the backslash of InexactLSR, Sec. 4.2.1);
+ * status as for rmm_sketched_lsr.  rmm_residual: resid = ||A x - b||_2 in
+ * FP64 (one pass over A; x is d doubles on the device). */
+int rmm_lsr_solve_workspace(rmm_handle h, int64_t s, int64_t d, size_t* bytes);
+int rmm_lsr_solve(rmm_handle h, rmm_dtype dt, int64_t s, int64_t d, const void* Cs,
+                  int64_t ldc, double* x, int32_t* status);
+int rmm_residual_workspace(rmm_handle h, int64_t m, size_t* bytes);
+int rmm_residual(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d, const void* A,
+                 int64_t lda, const void* b, const double* x, double* resid);
 /* Exact solution x* = A^+ b (Sec. 4.1) by FP64 CholeskyQR2 of A itself: the
  * "plain" comparator. Same argument conventions as rmm_sketched_lsr. */
 int rmm_plain_lsr_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d,

@@ -67,6 +67,10 @@ def lib():
             "rmm_sketched_lsr": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _vp, _vp],
             "rmm_plain_lsr_workspace": [_vp, _i32, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_plain_lsr": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
+            "rmm_lsr_solve_workspace": [_vp, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_lsr_solve": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp],
+            "rmm_residual_workspace": [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_residual": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp],
             "rmm_sketch_hashes": [_vp, _i64, _i64, _u64, _vp],
             "rmm_sketch_signs": [_vp, _i32, _i64, _u64, _vp],
             "rmm_srht_indices": [_vp, _i64, _i64, _u64, _vp],
@@ -221,6 +225,30 @@ class Handle:
         _check(lib().rmm_sketched_lsr(self._h, dt, _kind(kind), m, d, _ptr(A), _ld(A), _ptr(b), s,
                                       seed, _ptr(x), _ptr(res), _ptr(status)), "rmm_sketched_lsr")
         return x, res, status
+
+    def lsr_solve(self, Cs: torch.Tensor, d: int):
+        """x = argmin ||Cs[:, :d] x - Cs[:, d]|| for a sketched system Cs."""
+        s = Cs.shape[0]
+        x = torch.empty(d, dtype=torch.float64, device=Cs.device)
+        status = torch.zeros(1, dtype=torch.int32, device=Cs.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_lsr_solve_workspace(self._h, s, d, ctypes.byref(ws)), "rmm_lsr_solve_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_lsr_solve(self._h, _dt(Cs), s, d, _ptr(Cs), _ld(Cs), _ptr(x), _ptr(status)),
+               "rmm_lsr_solve")
+        return x, status
+
+    def residual(self, A: torch.Tensor, b: torch.Tensor, x: torch.Tensor, out: torch.Tensor = None):
+        """||A x - b||_2 in fp64 (x: fp64 device vector)."""
+        A = colmajor(A)
+        m, d = A.shape
+        out = torch.empty(1, dtype=torch.float64, device=A.device) if out is None else out
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_residual_workspace(self._h, m, ctypes.byref(ws)), "rmm_residual_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_residual(self._h, _dt(A), m, d, _ptr(A), _ld(A), _ptr(b), _ptr(x), _ptr(out)),
+               "rmm_residual")
+        return out
 
     def plain_lsr(self, A: torch.Tensor, b: torch.Tensor, residual: bool = True):
         A = colmajor(A)

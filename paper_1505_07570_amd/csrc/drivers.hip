@@ -324,6 +324,46 @@ int rmm_sketched_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m
                           x, resid, status, nullptr);
 }
 
+int rmm_lsr_solve_workspace(rmm_handle h, int64_t s, int64_t d, size_t* bytes) {
+  if (!h || !bytes || d < 1 || s < d || d > 4096 || s >= (1ll << 30)) return RMM_ERR_INVALID_ARG;
+  Carver ws(nullptr, 0);
+  ws.take<double>((size_t)s * (d + 1));
+  take_ls(ws, s, d);
+  *bytes = ws.off + ls_scratch(h, s, d) + 8 * kAlign;
+  return RMM_OK;
+}
+
+int rmm_lsr_solve(rmm_handle h, rmm_dtype dt, int64_t s, int64_t d, const void* Cs, int64_t ldc,
+                  double* x, int32_t* status) {
+  if (!h || !dt_ok(dt) || !Cs || !x || d < 1 || s < d || ld_bad(ldc, s)) return RMM_ERR_INVALID_ARG;
+  if (d > 4096 || s >= (1ll << 30)) return RMM_ERR_UNSUPPORTED;
+  Carver ws(h->ws, h->ws_bytes);
+  double* Csd = ws.take<double>((size_t)s * (d + 1));
+  LsBufs lb = take_ls(ws, s, d);
+  if (ws.off + ls_scratch(h, s, d) + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  RMM_TRY(zero_status(h, status));
+  if (dt == RMM_F32) RMM_TRY((copy_cast<float, double>(h, s, d + 1, (const float*)Cs, ldc, Csd, s)));
+  else RMM_TRY((copy_cast<double, double>(h, s, d + 1, (const double*)Cs, ldc, Csd, s)));
+  return ls_solve(h, s, (int)d, Csd, lb, x, status, ws);
+}
+
+int rmm_residual_workspace(rmm_handle h, int64_t m, size_t* bytes) {
+  if (!h || !bytes || m < 0) return RMM_ERR_INVALID_ARG;
+  *bytes = residual_workspace(m) + kAlign;
+  return RMM_OK;
+}
+
+int rmm_residual(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d, const void* A, int64_t lda,
+                 const void* b, const double* x, double* resid) {
+  if (!h || !dt_ok(dt) || m < 0 || d < 1 || !b || !x || !resid || (m > 0 && !A) || ld_bad(lda, m))
+    return RMM_ERR_INVALID_ARG;
+  if (d > (1 << 30) || m >= (1ll << 40)) return RMM_ERR_UNSUPPORTED;
+  Carver ws(h->ws, h->ws_bytes);
+  if (dt == RMM_F32)
+    return residual_norm<float>(h, m, (int)d, (const float*)A, lda, (const float*)b, x, resid, ws);
+  return residual_norm<double>(h, m, (int)d, (const double*)A, lda, (const double*)b, x, resid, ws);
+}
+
 int rmm_plain_lsr_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d, size_t* bytes) {
   RMM_TRY(lsr_args(h, dt, m, d, d));
   if (!bytes) return RMM_ERR_INVALID_ARG;
