@@ -20,22 +20,15 @@
 
 namespace rmm {
 
-template <typename T, bool VEC>
-__device__ __forceinline__ void load4(const T* __restrict__ col, int64_t row, int64_t m,
-                                      T v[4]) {
-  if (VEC && row + 3 < m) {
-    if constexpr (sizeof(T) == 4) {
-      const float4 x = *reinterpret_cast<const float4*>(col + row);
-      v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-    } else {
-      const double2 x = *reinterpret_cast<const double2*>(col + row);
-      const double2 y = *reinterpret_cast<const double2*>(col + row + 2);
-      v[0] = x.x; v[1] = x.y; v[2] = y.x; v[3] = y.y;
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) v[e] = (row + e < m) ? col[row + e] : T(0);
-  }
+template <typename T>
+__device__ __forceinline__ T apply_sign(T v, uint32_t packed);
+template <>
+__device__ __forceinline__ float apply_sign<float>(float v, uint32_t packed) {
+  return __uint_as_float(__float_as_uint(v) ^ (packed & 0x80000000u));
+}
+template <>
+__device__ __forceinline__ double apply_sign<double>(double v, uint32_t packed) {
+  return (packed >> 31) ? -v : v;
 }
 
 template <typename T, int WAVES, int UNROLL, bool VEC>
@@ -58,6 +51,43 @@ __global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
   const int ST = plan.ST;
   T* my_acc = acc + (size_t)wave * ST;
 
+  // this wave's column for unit u (nullptr when the panel is narrower)
+  auto column = [&](int64_t u) -> const T* {
+    const int panel = (int)(u / plan.nchunks / plan.BT);
+    const int64_t j = plan_col0(plan, panel) + wave;
+    if (j >= plan_col0(plan, panel + 1)) return nullptr;
+    return j < n ? A + j * lda : bcol;
+  };
+  auto load_unit = [&](int64_t u, T v[UNROLL][4]) {
+    const T* col = column(u);
+    const int64_t r0 = (u % plan.nchunks) * CH;
+    if (col == nullptr) return;
+    if (VEC && r0 + CH <= plan.m) {
+#pragma unroll
+      for (int k = 0; k < UNROLL; ++k) {
+        const T* p = col + r0 + 256 * k + 4 * lane;
+        if constexpr (sizeof(T) == 4) {
+          const float4 x = *reinterpret_cast<const float4*>(p);
+          v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
+        } else {
+          const double2 x = *reinterpret_cast<const double2*>(p);
+          const double2 y = *reinterpret_cast<const double2*>(p + 2);
+          v[k][0] = x.x; v[k][1] = x.y; v[k][2] = y.x; v[k][3] = y.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < UNROLL; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = r0 + 256 * k + 4 * lane + e;
+          v[k][e] = row < plan.m ? col[row] : T(0);
+        }
+    }
+  };
+
+  T v[UNROLL][4], vn[UNROLL][4];
+  if (u0 < u1) load_unit(u0, v);
   int64_t cur_vp = -1;
   int buf = 0;
   for (int64_t u = u0; u < u1; ++u) {
@@ -76,17 +106,8 @@ __global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
       cur_vp = vp;
     }
     const int64_t r0 = c * CH;
-    const int64_t j = plan_col0(plan, panel) + wave;
-    const bool active = j < plan_col0(plan, panel + 1);
-    const T* col = (j < n) ? A + j * lda : bcol;
-
-    // 1. loads in flight
-    T v[UNROLL][4];
-    if (active) {
-#pragma unroll
-      for (int k = 0; k < UNROLL; ++k) load4<T, VEC>(col, r0 + 256 * k + 4 * lane, plan.m, v[k]);
-    }
-    // 2. CountSketch words of this chunk, packed as bucket | sign << 31
+    const bool active = column(u) != nullptr;
+    // CountSketch words of this chunk, packed as bucket | sign << 31
     uint32_t* hb = hbuf + buf * CH;
 #pragma unroll
     for (int q = tid; q < CH / 4; q += NT) {
@@ -99,26 +120,39 @@ __global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
       *reinterpret_cast<uint4*>(hb + 4 * q) = pk;
     }
     __syncthreads();
-    // 3. signed scatter-add into this wave's buckets
+    // next unit's loads go out before this unit's scatter-adds
+    if (u + 1 < u1) load_unit(u + 1, vn);
     if (active) {
-      const uint32_t tile0 = (uint32_t)bt * (uint32_t)ST;
+      const bool fast = (r0 + CH <= plan.m) && (plan.BT == 1);
+      if (fast) {
 #pragma unroll
-      for (int k = 0; k < UNROLL; ++k) {
-        const int off = 256 * k + 4 * lane;
-        const uint4 pk = *reinterpret_cast<const uint4*>(hb + off);
-        const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
+        for (int k = 0; k < UNROLL; ++k) {
+          const uint4 pk = *reinterpret_cast<const uint4*>(hb + 256 * k + 4 * lane);
+          atomicAdd(my_acc + (pk.x & 0x7FFFFFFFu), apply_sign<T>(v[k][0], pk.x));
+          atomicAdd(my_acc + (pk.y & 0x7FFFFFFFu), apply_sign<T>(v[k][1], pk.y));
+          atomicAdd(my_acc + (pk.z & 0x7FFFFFFFu), apply_sign<T>(v[k][2], pk.z));
+          atomicAdd(my_acc + (pk.w & 0x7FFFFFFFu), apply_sign<T>(v[k][3], pk.w));
+        }
+      } else {
+        const uint32_t tile0 = (uint32_t)bt * (uint32_t)ST;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          if (r0 + off + e < plan.m) {
+        for (int k = 0; k < UNROLL; ++k) {
+          const int off = 256 * k + 4 * lane;
+          const uint4 pk = *reinterpret_cast<const uint4*>(hb + off);
+          const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
             const uint32_t bucket = (pw[e] & 0x7FFFFFFFu) - tile0;
-            if (bucket < (uint32_t)ST) {
-              const T x = (pw[e] >> 31) ? -v[k][e] : v[k][e];
-              atomicAdd(my_acc + bucket, x);
-            }
+            if (r0 + off + e < plan.m && bucket < (uint32_t)ST)
+              atomicAdd(my_acc + bucket, apply_sign<T>(v[k][e], pw[e]));
           }
         }
       }
     }
+#pragma unroll
+    for (int k = 0; k < UNROLL; ++k)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[k][e] = vn[k][e];
     buf ^= 1;
   }
   if (cur_vp >= 0) {

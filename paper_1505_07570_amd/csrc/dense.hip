@@ -115,13 +115,15 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int64_t K, cons
 
 template <typename TC, typename TO>
 __global__ void gemm_reduce_kernel(int M, int N, const TC* __restrict__ P, int splits, double alpha,
-                                   TO* __restrict__ C, int64_t ldc) {
+                                   double beta, TO* __restrict__ C, int64_t ldc) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (i >= M) return;
   double acc = 0.0;
   for (int z = 0; z < splits; ++z) acc += (double)P[(int64_t)z * M * N + i + j * M];
-  C[i + j * ldc] = (TO)(alpha * acc);
+  double v = alpha * acc;
+  if (beta != 0.0) v += beta * (double)C[i + j * ldc];
+  C[i + j * ldc] = (TO)v;
 }
 
 namespace {
@@ -174,7 +176,7 @@ size_t gemm_workspace(const rmm_ctx* h, int M, int N, int64_t K) {
 
 template <typename TAI, typename TBI, typename TC, typename TO>
 int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, int64_t lda,
-         const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc, Carver& ws) {
+         const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc, Carver& ws, double beta) {
   if (M == 0 || N == 0) return RMM_OK;
   const GemmShape g = gemm_shape(h, M, N, K);
   const size_t mark = ws.off;
@@ -188,7 +190,7 @@ int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, in
   RMM_TRY(rc);
   dim3 grid((unsigned)((M + 255) / 256), (unsigned)N);
   hipLaunchKernelGGL((gemm_reduce_kernel<TC, TO>), grid, dim3(256), 0, h->stream, M, N, P, g.splits,
-                     alpha, C, ldc);
+                     alpha, beta, C, ldc);
   ws.off = mark;  // the partials are dead once the reduction is enqueued
   return launch_status();
 }
@@ -281,7 +283,7 @@ size_t residual_workspace(int64_t m) {
 #define RMM_GEMM_INST(TAI, TBI, TC, TO)                                                      \
   template int gemm<TAI, TBI, TC, TO>(rmm_ctx*, bool, bool, int, int, int64_t, const TAI*, \
                                       int64_t, const TBI*, int64_t, double, TO*, int64_t,  \
-                                      Carver&);
+                                      Carver&, double);
 RMM_GEMM_INST(double, double, double, double)
 RMM_GEMM_INST(float, float, float, float)
 RMM_GEMM_INST(float, float, double, double)

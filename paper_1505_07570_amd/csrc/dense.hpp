@@ -7,9 +7,11 @@ namespace rmm {
 
 // C (M x N, ldc) = alpha * op(A) * op(B); op(A) is M x K, op(B) is K x N.
 // TC is the MFMA compute type; partial sums need gemm_workspace<TC> bytes.
+// With beta != 0 the result is alpha * op(A) op(B) + beta * C.
 template <typename TAI, typename TBI, typename TC, typename TO>
 int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, int64_t lda,
-         const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc, Carver& ws);
+         const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc, Carver& ws,
+         double beta = 0.0);
 template <typename TC>
 size_t gemm_workspace(const rmm_ctx* h, int M, int N, int64_t K);
 
@@ -27,10 +29,11 @@ size_t residual_workspace(int64_t m);
 // triangular; writes Rinv = R^{-1} (l x l, ld l, upper) and diag(R).
 // Directions whose pivot falls below tau * G_jj are dropped (zero row and
 // column in Rinv, zero diagonal) and RMM_STATUS_QR_FALLBACK is raised.
-// Needs cholinv_workspace(l) bytes when l > 128.
-int cholinv(const rmm_ctx* h, int l, const double* G, int64_t ldg, double tau, double* Rinv,
+// Above 128 the factorization recurses on 2 x 2 blocks (needs
+// cholinv_workspace(h, l) bytes).
+int cholinv(rmm_ctx* h, int l, const double* G, int64_t ldg, double tau, double* Rinv,
             double* diag, int32_t* status, Carver& ws);
-size_t cholinv_workspace(int l);
+size_t cholinv_workspace(const rmm_ctx* h, int l);
 
 // Symmetric eigendecomposition by cyclic Jacobi: evals descending, V (l x l,
 // ld l) orthonormal eigenvectors.  l <= 128.

@@ -40,7 +40,7 @@ template <typename T>
 size_t orth_scratch(const rmm_ctx* h, int64_t rows, int l) {
   size_t w = gemm_workspace<double>(h, l, l, rows);
   w = smax(w, gemm_workspace<double>(h, (int)rows, l, l));
-  w = smax(w, cholinv_workspace(l));
+  w = smax(w, cholinv_workspace(h, l));
   return w;
 }
 
@@ -149,7 +149,7 @@ size_t ls_scratch(const rmm_ctx* h, int64_t s, int d) {
   size_t w = gemm_workspace<double>(h, d, d, s);
   w = smax(w, gemm_workspace<double>(h, (int)s, d, d));
   w = smax(w, gemm_workspace<double>(h, d, 1, s));
-  w = smax(w, cholinv_workspace(d));
+  w = smax(w, cholinv_workspace(h, d));
   return w;
 }
 
@@ -228,7 +228,7 @@ int plain_impl(rmm_ctx* h, bool run, int64_t m, int d, const T* A, int64_t lda, 
   size_t scratch = gemm_workspace<double>(h, d, d, m);
   scratch = smax(scratch, gemm_workspace<double>(h, d, 1, m));
   scratch = smax(scratch, gemm_workspace<double>(h, d, 1, d));
-  scratch = smax(scratch, cholinv_workspace(d));
+  scratch = smax(scratch, cholinv_workspace(h, d));
   scratch = smax(scratch, residual_workspace(m));
   if (!run) {
     *bytes = ws.off + scratch + 8 * kAlign;

@@ -1,21 +1,22 @@
 // Gaussian-projection sketch C = (Omega / sqrt(s))^T A  (Sec. 3.2.1).
 //
 // A GEMM with the long dimension m as its reduction:  C (s x n') =
-// Omega^T (s x m) * A (m x n').  Omega is never stored: each wave generates
-// the entries its MFMA operand needs in registers from the counter-based
-// generator, so the only HBM traffic is one read of A and the split-K
-// partials.
+// Omega^T (s x m) * A (m x n').  Omega is never stored in HBM: every stage
+// of KS rows, the workgroup generates the KS x 128 block of Omega it needs
+// from the counter-based generator (one Philox block -> four fp32 normals,
+// or two fp64 normals) straight into LDS, so the only HBM traffic is one
+// read of A and the split-K partials.
 //
 // Tiling (gfx950, 16x16x4 MFMA, fp32 or fp64):
-//  * workgroup = 4 waves = 128 sketch rows x (16 NT) columns x one K range;
-//  * wave w covers 32 sketch rows as two 16-row MFMA tiles; MFMA row mi of
-//    tile t is sketch row m0 + 2 mi + t, so one Box-Muller pair of the
-//    generator (the cos / sin entries of columns 2j, 2j+1) feeds both tiles;
-//  * A is staged through a double-buffered LDS tile stored column-major
-//    with a padded stride that keeps the MFMA operand reads conflict free;
-//  * fp32 partial sums are folded into a second accumulator set every
-//    4096 rows, so no fp32 running sum spans more than 1024 MFMA steps;
-//  * the K ranges are reduced in a fixed order in fp64.
+//  * workgroup = 4 waves = 128 sketch rows x (16 NT) columns x one K range
+//    of at most 16384 rows (fp32), so no fp32 running sum spans more than
+//    4096 MFMA steps; the K ranges are reduced in a fixed order in fp64;
+//  * wave w covers sketch rows 32 w .. 32 w + 31 of the block as two 16-row
+//    MFMA tiles against all NT column tiles;
+//  * A and Omega are staged through double-buffered LDS tiles: while the
+//    MFMAs consume stage t, the loads of stage t+1 are in flight and its
+//    Omega block is generated; two workgroups share a CU so that one
+//    group's generator work overlaps the other's MFMAs.
 #include "common.hpp"
 #include "rng.hpp"
 
@@ -28,14 +29,16 @@ template <typename T>
 struct GaussCfg;
 template <>
 struct GaussCfg<float> {
-  static constexpr int KS = 32;   // rows per LDS stage
-  static constexpr int LDT = 34;  // padded stride (elements) of a tile column
+  static constexpr int KS = 16;   // rows per LDS stage
+  static constexpr int LDT = 18;  // padded stride (elements) of a staged A column
+  static constexpr int64_t KMAX = 16384;
   using acc_t = floatx4;
 };
 template <>
 struct GaussCfg<double> {
   static constexpr int KS = 16;
   static constexpr int LDT = 17;
+  static constexpr int64_t KMAX = 1 << 20;
   using acc_t = doublex4;
 };
 
@@ -45,30 +48,12 @@ __device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c) {
 __device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// row of the 16x16 result held in register v by lane group g = lane >> 4
+__device__ __forceinline__ int mfma_row(float, int g, int v) { return 4 * g + v; }
+__device__ __forceinline__ int mfma_row(double, int g, int v) { return g + 4 * v; }
 
-// Omega[i, r] and Omega[i, r + 1] for even r (one Box-Muller pair).
-__device__ __forceinline__ void omega_pair(uint64_t i, uint32_t r, uint32_t tag, uint64_t seed,
-                                           float& z0, float& z1) {
-  const Words4 b = philox_at(i, tag, r >> 2, seed);
-  const bool second = (r >> 1) & 1u;
-  const uint32_t wu = second ? b.w[2] : b.w[0];
-  const uint32_t wv = second ? b.w[3] : b.w[1];
-  const float u = (float)((wu >> 8) + 1u) * 0x1p-24f;
-  const float v = (float)(wv >> 8) * 0x1p-24f;
-  const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));
-  z0 = rad * __builtin_amdgcn_cosf(v);
-  z1 = rad * __builtin_amdgcn_sinf(v);
-}
-__device__ __forceinline__ void omega_pair(uint64_t i, uint32_t r, uint32_t tag, uint64_t seed,
-                                           double& z0, double& z1) {
-  double z[2];
-  gauss2_f64(i, r >> 1, tag, seed, z);
-  z0 = z[0];
-  z1 = z[1];
-}
-
-template <typename T, int NT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void gauss_sketch_kernel(
+template <typename T, int NT, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gauss_sketch_kernel(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, int ncols,
     int64_t m, int s, int64_t kchunk, uint32_t tag, uint64_t seed, T* __restrict__ partials) {
   using Cfg = GaussCfg<T>;
@@ -76,37 +61,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   constexpr int KS = Cfg::KS;
   constexpr int LDT = Cfg::LDT;
   constexpr int NCOL = NT * 16;              // columns of the tile
-  constexpr int GROUPS = NCOL * (KS / 4);    // 4-row groups per stage
+  constexpr int GROUPS = NCOL * (KS / 4);    // 4-row groups of A per stage
   constexpr int GPT = (GROUPS + 255) / 256;  // groups per thread
-  constexpr bool TWO = sizeof(T) == 4;
+  constexpr int PER = sizeof(T) == 4 ? 4 : 2;            // normals per Philox block
+  constexpr int CALLS = KS * 128 / PER;                  // Philox blocks per stage
+  constexpr int CPT = CALLS / 256;                       // per thread
   __shared__ T tile[2][NCOL * LDT];
+  __shared__ T om[2][KS * 128];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int mi = lane & 15;
   const int kk = lane >> 4;
-  const int m0 = blockIdx.x * 128 + wave * 32;
+  const int mblk = blockIdx.x * 128;
   const int nbase = blockIdx.y * NCOL;
   const int sp = blockIdx.z;
   const int64_t k0 = (int64_t)sp * kchunk;
   int64_t k1 = k0 + kchunk;
   if (k1 > m) k1 = m;
-  const uint32_t rpair = (uint32_t)(m0 + 2 * mi);  // even sketch row of this lane's pair
-  const bool rvalid = (int)rpair < s;             // s is even or rpair + 1 == s is masked below
-  const bool r1valid = (int)rpair + 1 < s;
 
-  acc_t acc[2][NT], out[2][NT];
+  acc_t acc[2][NT];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      acc[t][q] = acc_t{0, 0, 0, 0};
-      out[t][q] = acc_t{0, 0, 0, 0};
-    }
+    for (int q = 0; q < NT; ++q) acc[t][q] = acc_t{0, 0, 0, 0};
 
   T stage_v[GPT][4];
   auto load_stage = [&](int64_t r0) {
+    const bool full = VEC && (r0 + KS <= k1);
 #pragma unroll
     for (int g = 0; g < GPT; ++g) {
       const int gi = tid + 256 * g;
@@ -118,9 +101,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       for (int e = 0; e < 4; ++e) stage_v[g][e] = T(0);
       if (gi < GROUPS && j < ncols) {
         const T* col = j < n ? A + j * lda : bcol;
+        if (full) {
+          if constexpr (sizeof(T) == 4) {
+            const float4 x = *reinterpret_cast<const float4*>(col + row);
+            stage_v[g][0] = x.x; stage_v[g][1] = x.y; stage_v[g][2] = x.z; stage_v[g][3] = x.w;
+          } else {
+            const double2 x = *reinterpret_cast<const double2*>(col + row);
+            const double2 y = *reinterpret_cast<const double2*>(col + row + 2);
+            stage_v[g][0] = x.x; stage_v[g][1] = x.y; stage_v[g][2] = y.x; stage_v[g][3] = y.y;
+          }
+        } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (row + e < k1) stage_v[g][e] = col[row + e];
+          for (int e = 0; e < 4; ++e)
+            if (row + e < k1) stage_v[g][e] = col[row + e];
+        }
       }
     }
   };
@@ -136,25 +130,53 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       }
     }
   };
+  // Omega[r0 + k, mblk + c] for k < KS, c < 128, written to om[b][k * 128 + c]
+  auto gen_omega = [&](int64_t r0, int b) {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int call = tid + 256 * u;
+      const int k = call / (128 / PER);
+      const int cq = call - k * (128 / PER);
+      const int64_t i = r0 + k;
+      const int c0 = mblk + PER * cq;
+      const bool ok = i < k1;
+      if constexpr (sizeof(T) == 4) {
+        float z[4];
+        gauss4_f32((uint64_t)i, (uint32_t)(c0 >> 2), tag, seed, z);
+        float4 o;
+        o.x = (ok && c0 + 0 < s) ? z[0] : 0.f;
+        o.y = (ok && c0 + 1 < s) ? z[1] : 0.f;
+        o.z = (ok && c0 + 2 < s) ? z[2] : 0.f;
+        o.w = (ok && c0 + 3 < s) ? z[3] : 0.f;
+        *reinterpret_cast<float4*>(&om[b][k * 128 + PER * cq]) = o;
+      } else {
+        double z[2];
+        gauss2_f64((uint64_t)i, (uint32_t)(c0 >> 1), tag, seed, z);
+        double2 o;
+        o.x = (ok && c0 < s) ? z[0] : 0.0;
+        o.y = (ok && c0 + 1 < s) ? z[1] : 0.0;
+        *reinterpret_cast<double2*>(&om[b][k * 128 + PER * cq]) = o;
+      }
+    }
+  };
 
   const int64_t nst = (k1 - k0 + KS - 1) / KS;
   if (nst > 0) {
     load_stage(k0);
+    gen_omega(k0, 0);
     store_stage(0);
   }
   __syncthreads();
+  const int arow = 32 * wave + mi;
   for (int64_t st = 0; st < nst; ++st) {
     const int b = (int)(st & 1);
     const int64_t r0 = k0 + st * KS;
-    if (st + 1 < nst) load_stage(r0 + KS);
-#pragma unroll 2
+    const bool more = st + 1 < nst;
+    if (more) load_stage(r0 + KS);
+#pragma unroll
     for (int ks = 0; ks < KS / 4; ++ks) {
-      const int64_t i = r0 + 4 * ks + kk;
-      T a0 = T(0), a1 = T(0);
-      if (i < k1 && rvalid) {
-        omega_pair((uint64_t)i, rpair, tag, seed, a0, a1);
-        if (!r1valid) a1 = T(0);
-      }
+      const T a0 = om[b][(4 * ks + kk) * 128 + arow];
+      const T a1 = om[b][(4 * ks + kk) * 128 + arow + 16];
       const T* tb = &tile[b][mi * LDT + 4 * ks + kk];
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
@@ -163,32 +185,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         acc[1][q] = mfma16(a1, bv, acc[1][q]);
       }
     }
-    if (TWO && (((st + 1) * KS) % 4096 == 0)) {
-#pragma unroll
-      for (int t = 0; t < 2; ++t)
-#pragma unroll
-        for (int q = 0; q < NT; ++q) {
-          out[t][q] += acc[t][q];
-          acc[t][q] = acc_t{0, 0, 0, 0};
-        }
+    if (more) {
+      gen_omega(r0 + KS, b ^ 1);
+      store_stage(b ^ 1);
     }
-    if (st + 1 < nst) store_stage(b ^ 1);
     __syncthreads();
   }
-  // lane holds D[row][lane & 15] of each 16x16 tile with row = 4 (lane >> 4) + v for
-  // the fp32 MFMA and row = (lane >> 4) + 4 v for the fp64 MFMA
   T* dst = partials + (int64_t)sp * ncols * s;
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
-      const acc_t tot = out[t][q] + acc[t][q];
       const int64_t j = nbase + q * 16 + mi;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = sizeof(T) == 4 ? 4 * kk + v : kk + 4 * v;
-        const int r = m0 + 2 * row + t;
-        if (j < ncols && r < s) dst[j * s + r] = tot[v];
+        const int r = mblk + 32 * wave + 16 * t + mfma_row(T(0), kk, v);
+        if (j < ncols && r < s) dst[j * s + r] = acc[t][q][v];
       }
     }
 }
@@ -217,14 +229,18 @@ struct GaussShape {
 template <typename T>
 GaussShape gauss_shape(const rmm_ctx* h, int64_t m, int ncols, int s) {
   GaussShape g;
-  g.NT = ncols > 128 ? 17 : ncols > 64 ? 8 : ncols > 16 ? 4 : 1;
+  // fp64 accumulators for 17 column tiles do not fit two waves per SIMD
+  const int ntmax = sizeof(T) == 4 ? 17 : 8;
+  g.NT = ncols > 128 ? ntmax : ncols > 64 ? 8 : ncols > 16 ? 4 : 1;
   g.ntiles = (ncols + g.NT * 16 - 1) / (g.NT * 16);
   g.mtiles = (s + 127) / 128;
   const int64_t KS = GaussCfg<T>::KS;
-  // enough K splits for about two workgroups per CU, at least 4096 rows each
-  int64_t want = (2ll * h->cus + (int64_t)g.mtiles * g.ntiles - 1) / ((int64_t)g.mtiles * g.ntiles);
-  int64_t maxsplit = (m + 4095) / 4096;
+  // enough K splits for about four workgroups per CU, each at most KMAX rows
+  int64_t want = (4ll * h->cus + (int64_t)g.mtiles * g.ntiles - 1) / ((int64_t)g.mtiles * g.ntiles);
+  const int64_t minsplit = (m + GaussCfg<T>::KMAX - 1) / GaussCfg<T>::KMAX;
+  const int64_t maxsplit = (m + 1023) / 1024;
   if (want > maxsplit) want = maxsplit;
+  if (want < minsplit) want = minsplit;
   if (want < 1) want = 1;
   int64_t kc = (m + want - 1) / want;
   kc = (kc + KS - 1) / KS * KS;
@@ -239,8 +255,13 @@ template <typename T, int NT>
 int launch_gauss(const rmm_ctx* h, const GaussShape& g, const T* A, int64_t lda, const T* b,
                  int n, int ncols, int64_t m, int s, uint32_t tag, uint64_t seed, T* partials) {
   dim3 grid((unsigned)g.mtiles, (unsigned)g.ntiles, (unsigned)g.splits);
-  hipLaunchKernelGGL((gauss_sketch_kernel<T, NT>), grid, dim3(256), 0, h->stream, A, lda, b, n,
-                     ncols, m, s, g.kchunk, tag, seed, partials);
+  const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) && (b == nullptr || (uintptr_t)b % 16 == 0);
+  if (vec)
+    hipLaunchKernelGGL((gauss_sketch_kernel<T, NT, true>), grid, dim3(256), 0, h->stream, A, lda, b,
+                       n, ncols, m, s, g.kchunk, tag, seed, partials);
+  else
+    hipLaunchKernelGGL((gauss_sketch_kernel<T, NT, false>), grid, dim3(256), 0, h->stream, A, lda, b,
+                       n, ncols, m, s, g.kchunk, tag, seed, partials);
   return launch_status();
 }
 
@@ -267,7 +288,12 @@ int gauss_project(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
   int rc;
   switch (g.NT) {
-    case 17: rc = launch_gauss<T, 17>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials); break;
+    case 17:
+      if constexpr (sizeof(T) == 4) {
+        rc = launch_gauss<T, 17>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials);
+        break;
+      }
+      return RMM_ERR_UNSUPPORTED;
     case 8: rc = launch_gauss<T, 8>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials); break;
     case 4: rc = launch_gauss<T, 4>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials); break;
     default: rc = launch_gauss<T, 1>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials); break;

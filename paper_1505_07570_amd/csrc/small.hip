@@ -17,13 +17,15 @@ __device__ __forceinline__ void or_status(int32_t* status, int32_t flag) {
 
 // W: l x (l + 1) column-major working array (ld = l).  On entry the upper
 // triangle holds G.  On exit: upper triangle = R, strict lower triangle =
-// R^{-1} transposed, column l = diag(R^{-1}).
-__device__ void cholinv_body(int l, double* W, double tau, double* __restrict__ Rinv,
-                             double* __restrict__ diag, int32_t* status, double* sh_orig,
-                             double* sh_piv) {
+// R^{-1} transposed, column l = diag(R^{-1}).  The drop test of pivot j
+// compares against orig[j * ostride] (the diagonal of the matrix the caller
+// considers original), or against G_jj itself when orig is null.
+__device__ void cholinv_body(int l, double* W, double tau, const double* orig, int64_t ostride,
+                             double* __restrict__ Rinv, int64_t ldr, double* __restrict__ diag,
+                             int32_t* status, double* sh_orig, double* sh_piv) {
   const int tid = threadIdx.x;
   const int nt = blockDim.x;
-  for (int j = tid; j < l; j += nt) sh_orig[j] = W[j + (int64_t)j * l];
+  for (int j = tid; j < l; j += nt) sh_orig[j] = orig ? orig[j * ostride] : W[j + (int64_t)j * l];
   __syncthreads();
   // right-looking Cholesky on the upper triangle: G = R^T R
   for (int j = 0; j < l; ++j) {
@@ -79,62 +81,108 @@ __device__ void cholinv_body(int l, double* W, double tau, double* __restrict__ 
     double v = 0.0;
     if (a == c) v = W[c + (int64_t)l * l];
     else if (a < c) v = W[c + (int64_t)a * l];
-    Rinv[a + (int64_t)c * l] = v;
+    Rinv[a + (int64_t)c * ldr] = v;
   }
   for (int j = tid; j < l; j += nt) diag[j] = W[j + (int64_t)j * l];
 }
 
 __global__ __launch_bounds__(kSmallThreads) void cholinv_lds_kernel(
-    int l, const double* __restrict__ G, int64_t ldg, double tau, double* __restrict__ Rinv,
-    double* __restrict__ diag, int32_t* status) {
+    int l, const double* __restrict__ G, int64_t ldg, double tau, const double* orig,
+    int64_t ostride, double* __restrict__ Rinv, int64_t ldr, double* __restrict__ diag,
+    int32_t* status) {
   extern __shared__ double W[];  // l * (l + 1) + l + 1
-  double* orig = W + (size_t)l * (l + 1);
-  double* piv = orig + l;
+  double* sorig = W + (size_t)l * (l + 1);
+  double* piv = sorig + l;
   for (int e = threadIdx.x; e < l * l; e += blockDim.x) {
     const int a = e % l, b = e / l;
     W[e] = G[a + (int64_t)b * ldg];
   }
   __syncthreads();
-  cholinv_body(l, W, tau, Rinv, diag, status, orig, piv);
+  cholinv_body(l, W, tau, orig, ostride, Rinv, ldr, diag, status, sorig, piv);
 }
 
-__global__ __launch_bounds__(kSmallThreads) void cholinv_global_kernel(
-    int l, const double* __restrict__ G, int64_t ldg, double tau, double* __restrict__ Rinv,
-    double* __restrict__ diag, int32_t* status, double* __restrict__ W) {
-  __shared__ double piv;
-  extern __shared__ double orig[];
-  for (int64_t e = threadIdx.x; e < (int64_t)l * l; e += blockDim.x) {
-    const int64_t a = e % l, b = e / l;
-    W[e] = G[a + b * ldg];
-  }
-  __syncthreads();
-  cholinv_body(l, W, tau, Rinv, diag, status, orig, &piv);
+__global__ void fill_block_kernel(int rows, double* __restrict__ X, int64_t ldx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows) X[i + (int64_t)blockIdx.y * ldx] = 0.0;
 }
 
-size_t cholinv_workspace(int l) {
+__global__ void copy_block_kernel(int rows, const double* __restrict__ X, int64_t ldx,
+                                  double* __restrict__ Y, int64_t ldy) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < rows) Y[i + (int64_t)blockIdx.y * ldy] = X[i + (int64_t)blockIdx.y * ldx];
+}
+
+size_t cholinv_workspace(const rmm_ctx* h, int l) {
+  if (l <= kLdsMaxL) return 0;
+  const int l1 = (l + 1) / 2, l2 = l - l1;
   Carver c(nullptr, 0);
-  if (l > kLdsMaxL) c.take<double>((size_t)l * (l + 1));
-  return c.off;
+  c.take<double>((size_t)l1 * l2);  // R12
+  c.take<double>((size_t)l2 * l2);  // S
+  c.take<double>((size_t)l1 * l2);  // T2
+  size_t w = gemm_workspace<double>(h, l1, l2, l1);
+  const size_t w2 = gemm_workspace<double>(h, l2, l2, l1);
+  const size_t w3 = gemm_workspace<double>(h, l1, l2, l2);
+  const size_t w4 = cholinv_workspace(h, l1);
+  const size_t w5 = cholinv_workspace(h, l2);
+  w = w2 > w ? w2 : w;
+  w = w3 > w ? w3 : w;
+  w = w4 > w ? w4 : w;
+  w = w5 > w ? w5 : w;
+  return c.off + w + 4 * kAlign;
 }
 
-int cholinv(const rmm_ctx* h, int l, const double* G, int64_t ldg, double tau, double* Rinv,
-            double* diag, int32_t* status, Carver& ws) {
-  if (l == 0) return RMM_OK;
+// Recursive 2 x 2 blocking above the LDS size:
+//   G = [[G11, G12], [G12^T, G22]] = R^T R,  R = [[R11, R12], [0, R22]]
+//   R11 = chol(G11), R12 = R11^{-T} G12, R22 = chol(G22 - R12^T R12)
+//   R^{-1} = [[X11, -X11 R12 X22], [0, X22]],  X = R^{-1} of each block.
+static int cholinv_rec(rmm_ctx* h, int l, const double* G, int64_t ldg, double tau,
+                       const double* orig, int64_t ostride, double* Rinv, int64_t ldr, double* diag,
+                       int32_t* status, Carver& ws) {
   if (l <= kLdsMaxL) {
     const size_t lds = ((size_t)l * (l + 1) + l + 1) * sizeof(double);
     RMM_HIP(hipFuncSetAttribute((const void*)cholinv_lds_kernel,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(cholinv_lds_kernel, dim3(1), dim3(kSmallThreads), lds, h->stream, l, G, ldg,
-                       tau, Rinv, diag, status);
+                       tau, orig, ostride, Rinv, ldr, diag, status);
     return launch_status();
   }
+  const int l1 = (l + 1) / 2, l2 = l - l1;
   const size_t mark = ws.off;
-  double* W = ws.take<double>((size_t)l * (l + 1));
+  double* R12 = ws.take<double>((size_t)l1 * l2);
+  double* S = ws.take<double>((size_t)l2 * l2);
+  double* T2 = ws.take<double>((size_t)l1 * l2);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
-  hipLaunchKernelGGL(cholinv_global_kernel, dim3(1), dim3(kSmallThreads), (size_t)l * sizeof(double),
-                     h->stream, l, G, ldg, tau, Rinv, diag, status, W);
+  const double* o = orig ? orig : G;
+  const int64_t os = orig ? ostride : ldg + 1;
+  const double* G12 = G + (int64_t)l1 * ldg;
+  const double* G22 = G + l1 + (int64_t)l1 * ldg;
+  double* X11 = Rinv;
+  double* X12 = Rinv + (int64_t)l1 * ldr;
+  double* X21 = Rinv + l1;
+  double* X22 = Rinv + l1 + (int64_t)l1 * ldr;
+  RMM_TRY(cholinv_rec(h, l1, G, ldg, tau, o, os, X11, ldr, diag, status, ws));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, l1, l2, l1, X11, ldr, G12, ldg, 1.0,
+                                                R12, l1, ws)));
+  hipLaunchKernelGGL(copy_block_kernel, dim3((l2 + 255) / 256, l2), dim3(256), 0, h->stream, l2, G22,
+                     ldg, S, l2);
+  RMM_TRY(launch_status());
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, l2, l2, l1, R12, l1, R12, l1, -1.0, S,
+                                                l2, ws, 1.0)));
+  RMM_TRY(cholinv_rec(h, l2, S, l2, tau, o + (int64_t)l1 * os, os, X22, ldr, diag + l1, status, ws));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, l1, l2, l2, R12, l1, X22, ldr, 1.0,
+                                                T2, l1, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, l1, l2, l1, X11, ldr, T2, l1, -1.0,
+                                                X12, ldr, ws)));
+  hipLaunchKernelGGL(fill_block_kernel, dim3((l2 + 255) / 256, l1), dim3(256), 0, h->stream, l2, X21,
+                     ldr);
   ws.off = mark;
   return launch_status();
+}
+
+int cholinv(rmm_ctx* h, int l, const double* G, int64_t ldg, double tau, double* Rinv,
+            double* diag, int32_t* status, Carver& ws) {
+  if (l == 0) return RMM_OK;
+  return cholinv_rec(h, l, G, ldg, tau, nullptr, 0, Rinv, l, diag, status, ws);
 }
 
 // ---- cyclic Jacobi eigensolver ------------------------------------------------------
