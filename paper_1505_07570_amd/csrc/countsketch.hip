@@ -162,6 +162,137 @@ __global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
   }
 }
 
+// ---- scheduled variant (s <= 16384) ------------------------------------------------
+//
+// LDS float atomics are slow, so the scatter-add is made conflict free
+// ahead of time.  A wave instruction of the consumer handles one row group:
+// lane l of group (k, e) of a 256-row block holds row 256 k + 4 l + e.  A
+// pre-pass records for every row its bucket, its sign and whether a lower
+// lane of its group has the same bucket.  The first lane of every bucket
+// does a plain LDS read-modify-write (those buckets are pairwise distinct);
+// the rare later lanes then add atomically, after it in program order.
+// Entry (16 bits): bits 0-13 bucket, bit 14 "not first", bit 15 sign.
+
+constexpr int kCsSchedMaxS = 1 << 14;
+
+__global__ __launch_bounds__(256) void cs_schedule_kernel(int64_t m, uint32_t s, uint64_t seed,
+                                                          uint16_t* __restrict__ table) {
+  const int lane = threadIdx.x & 63;
+  const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // 256-row block
+  const int64_t row0 = blk * 256;
+  if (row0 >= m) return;
+  const Words4 w = philox_at((uint64_t)(row0 >> 2) + lane, TAG_COUNTSKETCH, 0, seed);
+  uint16_t o[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t b = cs_bucket(w.w[e], s);
+    uint32_t dup = 0;
+    for (int off = 1; off < 64; ++off) {
+      const int src = lane - off;
+      const uint32_t ob = (uint32_t)__shfl(b, src & 63);
+      dup |= (src >= 0 && ob == b) ? 1u : 0u;
+    }
+    o[e] = (uint16_t)(b | (dup << 14) | ((w.w[e] & 1u) << 15));
+  }
+  const int64_t row = row0 + 4 * lane;
+  for (int e = 0; e < 4; ++e)
+    if (row + e < m) table[row + e] = o[e];
+}
+
+// worker = one wave; unit = (column, 2048-row chunk); private LDS buckets
+template <typename T, bool VEC>
+__global__ __launch_bounds__(64) void countsketch_sched_kernel(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
+    const uint16_t* __restrict__ table, T* __restrict__ partials) {
+  constexpr int UN = 8;  // 8 x 4 rows per lane = 2048 rows per chunk
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* acc = reinterpret_cast<T*>(smem);
+  const int lane = threadIdx.x;
+  const int64_t wk = blockIdx.x;
+  const int64_t u0 = plan_start(plan, wk);
+  const int64_t u1 = plan_start(plan, wk + 1);
+  const int s = plan.s;
+  for (int i = lane; i < s; i += 64) acc[i] = T(0);
+
+  auto load = [&](int64_t u, T v[UN][4], uint2 tb[UN]) {
+    const int64_t j = u / plan.nchunks;
+    const int64_t r0 = (u - j * plan.nchunks) * (256 * UN);
+    const T* col = j < n ? A + j * lda : bcol;
+    if (VEC && r0 + 256 * UN <= plan.m) {
+#pragma unroll
+      for (int k = 0; k < UN; ++k) {
+        const int64_t row = r0 + 256 * k + 4 * lane;
+        if constexpr (sizeof(T) == 4) {
+          const float4 x = *reinterpret_cast<const float4*>(col + row);
+          v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
+        } else {
+          const double2 x = *reinterpret_cast<const double2*>(col + row);
+          const double2 y = *reinterpret_cast<const double2*>(col + row + 2);
+          v[k][0] = x.x; v[k][1] = x.y; v[k][2] = y.x; v[k][3] = y.y;
+        }
+        tb[k] = *reinterpret_cast<const uint2*>(table + row);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < UN; ++k) {
+        uint32_t tw[2] = {0u, 0u};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = r0 + 256 * k + 4 * lane + e;
+          const bool ok = row < plan.m;
+          v[k][e] = ok ? col[row] : T(0);
+          // rows past the end add +0 into bucket 0 through the atomic path
+          const uint32_t ent = ok ? (uint32_t)table[row] : 0x4000u;
+          tw[e >> 1] |= ent << (16 * (e & 1));
+        }
+        tb[k] = make_uint2(tw[0], tw[1]);
+      }
+    }
+  };
+
+  T v[UN][4], vn[UN][4];
+  uint2 tb[UN], tbn[UN];
+  int64_t cur = u0 < u1 ? u0 / plan.nchunks : -1;
+  if (u0 < u1) load(u0, v, tb);
+  for (int64_t u = u0; u < u1; ++u) {
+    const int64_t j = u / plan.nchunks;
+    if (j != cur) {
+      T* dst = partials + (wk + cur) * plan.slot_elems;
+      for (int i = lane; i < s; i += 64) {
+        dst[i] = acc[i];
+        acc[i] = T(0);
+      }
+      cur = j;
+    }
+    if (u + 1 < u1) load(u + 1, vn, tbn);
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      const uint32_t tw[2] = {tb[k].x, tb[k].y};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t ent = (tw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+        T* p = acc + (ent & 0x3FFFu);
+        const T x = apply_sign<T>(v[k][e], ent << 16);
+        const bool later = (ent & 0x4000u) != 0u;
+        if (!later) *p += x;
+        if (__builtin_amdgcn_ballot_w64(later)) {
+          if (later) atomicAdd(p, x);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      tb[k] = tbn[k];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[k][e] = vn[k][e];
+    }
+  }
+  if (cur >= 0) {
+    T* dst = partials + (wk + cur) * plan.slot_elems;
+    for (int i = lane; i < s; i += 64) dst[i] = acc[i];
+  }
+}
+
 namespace {
 
 constexpr size_t kAccBudget = 128 * 1024;  // LDS bytes for the bucket accumulators
@@ -207,12 +338,33 @@ int launch_cs(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
 
 }  // namespace
 
+constexpr int kSchedChunk = 2048;
+
+bool cs_use_sched(int64_t s, size_t tsize) {
+  return s <= kCsSchedMaxS && (size_t)s * tsize <= 64 * 1024;
+}
+
+template <typename T>
+PanelPlan cs_sched_plan(const rmm_ctx* h, int64_t m, int ncols, int s) {
+  const size_t lds = (size_t)s * sizeof(T);
+  int per_cu = (int)(160 * 1024 / (lds > 0 ? lds : 1));
+  if (per_cu > 16) per_cu = 16;
+  if (per_cu < 1) per_cu = 1;
+  return make_plan(m, ncols, 1, s, s, kSchedChunk, h->cus * per_cu);
+}
+
 template <typename T>
 size_t countsketch_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s) {
+  Carver c(nullptr, 0);
+  if (cs_use_sched(s, sizeof(T))) {
+    const PanelPlan plan = cs_sched_plan<T>(h, m, ncols, (int)s);
+    c.take<uint16_t>((size_t)(m > 0 ? m : 1));
+    c.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
+    return c.off;
+  }
   int waves, ST;
   PanelPlan plan;
   cs_shape<T>(h, m, ncols, (int)s, &waves, &ST, &plan);
-  Carver c(nullptr, 0);
   c.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
   return c.off;
 }
@@ -223,6 +375,26 @@ int countsketch_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const
   const int ncols = n + (b ? 1 : 0);
   if (ncols == 0) return RMM_OK;
   if (m == 0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
+  const bool vecs = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) &&
+                    (b == nullptr || (uintptr_t)b % 16 == 0);
+  if (cs_use_sched(s, sizeof(T))) {
+    const PanelPlan plan = cs_sched_plan<T>(h, m, ncols, (int)s);
+    uint16_t* table = ws.take<uint16_t>((size_t)m);
+    T* partials = ws.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
+    if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+    const int64_t blocks256 = (m + 255) / 256;
+    hipLaunchKernelGGL(cs_schedule_kernel, dim3((unsigned)((blocks256 + 3) / 4)), dim3(256), 0,
+                       h->stream, m, (uint32_t)s, seed, table);
+    RMM_TRY(launch_status());
+    const size_t lds = (size_t)s * sizeof(T);
+    auto kern = vecs ? countsketch_sched_kernel<T, true> : countsketch_sched_kernel<T, false>;
+    RMM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL(kern, dim3(plan.G), dim3(64), lds, h->stream, A, lda, b, n, plan, table,
+                       partials);
+    RMM_TRY(launch_status());
+    return launch_panel_reduce<T>(plan, partials, 1.0, C, ldc, h->stream);
+  }
   int waves, ST;
   PanelPlan plan;
   cs_shape<T>(h, m, ncols, (int)s, &waves, &ST, &plan);

@@ -9,12 +9,14 @@
 // row index i = i_hi L + i_lo,
 //     H_N[r, i] = H_{N/L}[r_hi, i_hi] * H_L[r_lo, i_lo],
 //     (H_N x)[r] = sum_{i_hi} (-1)^popcount(r_hi & i_hi) (H_L x_{i_hi})[r_lo].
-// Each wave owns one column and a run of L-row chunks: it loads the chunk
-// (16-byte loads, 4 rows per lane), applies D, runs the 12-stage butterfly
-// network in registers with one LDS transpose, stores z = H_L x_chunk to its
-// LDS region, and adds +-z[r_lo] into register accumulators for the samples
-// it owns.  N < L is handled by zero padding to L: (H_L [x; 0])[r] equals
-// (H_N x)[r] for r < N.  Per-wave partial sums are reduced in fixed order.
+// A workgroup of 4 waves takes 4 consecutive L-row chunks of one column:
+// each wave loads its chunk (16-byte loads, 4 rows per lane), applies D,
+// runs the 12-stage butterfly network in registers with one LDS transpose
+// and leaves z = H_L x_chunk in its LDS buffer; the workgroup then adds the
+// four chunks' signed contributions to the s sampled rows, whose
+// accumulators are spread over its 256 threads.  N < L is handled by zero
+// padding to L: (H_L [x; 0])[r] equals (H_N x)[r] for r < N.  Per-workgroup
+// partial sums are reduced in a fixed order.
 #include "common.hpp"
 #include "rng.hpp"
 
@@ -57,30 +59,40 @@ __device__ __forceinline__ void bfly(T& a, T& b) {
   b = y;
 }
 
-template <typename T, int SPL, bool VEC>
-__global__ __launch_bounds__(64) void srht_kernel(const T* __restrict__ A, int64_t lda,
-                                                  const T* __restrict__ bcol, int n,
-                                                  PanelPlan plan, const uint32_t* __restrict__ idx,
-                                                  uint64_t seed, T* __restrict__ partials) {
+// One workgroup = 4 waves working on 4 consecutive chunks ("a quad") of the
+// same column; unit = (column, quad).  Wave w transforms chunk 4 q + w into
+// its own LDS buffer; then the 256 threads add, for the samples they own
+// (t = tid + 256 k), the quad's contribution
+//   sum_w (-1)^popcount(r_hi & (4 q + w)) z_w[r_lo]
+//   = (-1)^popcount((r_hi >> 2) & q) * [(z0 + a z1) + b (z2 + a z3)],
+// a = (-1)^{bit 0 of r_hi}, b = (-1)^{bit 1 of r_hi}.
+template <typename T, int SPQ, bool VEC>
+__device__ __forceinline__ void srht_body(const T* __restrict__ A, int64_t lda,
+                                          const T* __restrict__ bcol, int n, PanelPlan plan,
+                                          const uint32_t* __restrict__ idx, uint64_t seed,
+                                          T* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
-  T* buf = reinterpret_cast<T*>(smem);                          // kL values
-  uint32_t* sgn = reinterpret_cast<uint32_t*>(smem + kL * sizeof(T));  // 32 x 4 words
-  const int lane = threadIdx.x;
-  const int64_t wk = blockIdx.x;  // this wave's worker id
-  const int64_t u0 = plan_start(plan, wk);
-  const int64_t u1 = plan_start(plan, wk + 1);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  T* buf = reinterpret_cast<T*>(smem) + (size_t)wave * kL;  // this wave's chunk
+  uint32_t* sgn = reinterpret_cast<uint32_t*>(smem + 4 * kL * sizeof(T)) + wave * 128;
+  const int64_t blk = blockIdx.x;
+  const int64_t u0 = plan_start(plan, blk);
+  const int64_t u1 = plan_start(plan, blk + 1);
   const int s = plan.s;
+  const int64_t nquads = plan.nchunks;  // plan chunk = 4 L rows
 
-  // owned samples t = lane + 64 k: packed (r_hi << SH) | LDS byte address of z[r_lo]
-  constexpr uint32_t SH = sizeof(T) == 4 ? 14 : 15;
-  constexpr uint32_t AMASK = (1u << SH) - 1u;
-  uint32_t pk[SPL];
-  T acc[SPL];
+  // owned samples: packed byte address of z[r_lo] (bits 0..14) and r_hi >> 2 (bits 16..)
+  // with bits 0 and 1 of r_hi kept in pa (bit 31) and pb (bit 31) form on the fly
+  uint32_t pk[SPQ];
+  T acc[SPQ];
 #pragma unroll
-  for (int k = 0; k < SPL; ++k) {
-    const int t = lane + 64 * k;
+  for (int k = 0; k < SPQ; ++k) {
+    const int t = tid + 256 * k;
     const uint32_t r = t < s ? idx[t] : 0u;
-    pk[k] = ((r >> kLogL) << SH) | (swz(r & (kL - 1)) * (uint32_t)sizeof(T));
+    const uint32_t hi = r >> kLogL;
+    pk[k] = ((hi >> 2) << 16) | ((hi & 3u) << 14) | (swz(r & (kL - 1)) * 4u);
     acc[k] = T(0);
   }
   // lane-constant parts of the swizzled addresses (swz only touches bits 2..4)
@@ -88,49 +100,59 @@ __global__ __launch_bounds__(64) void srht_kernel(const T* __restrict__ A, int64
   uint32_t woff[8], roff[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    woff[i] = 4u * ((uint32_t)lane ^ (uint32_t)i);              // + 256 k, k & 7 == i
-    roff[i] = a + 256u * bq + 4u * ((uint32_t)i ^ (bq & 7u));   // + 32 (i >> 3)
+    woff[i] = 4u * ((uint32_t)lane ^ (uint32_t)i);
+    roff[i] = a + 256u * bq + 4u * ((uint32_t)i ^ (bq & 7u));
   }
-  int64_t cur_panel = -1;
-  for (int64_t u = u0; u < u1; ++u) {
-    const int64_t panel = u / plan.nchunks;
-    const int64_t c = u - panel * plan.nchunks;
-    if (panel != cur_panel) {
-      if (cur_panel >= 0) {
-        T* dst = partials + (wk + cur_panel) * plan.slot_elems;
+
+  T x[64];
+  auto load_chunk = [&](int64_t u) {
+    const int64_t j = u / nquads;
+    const int64_t c = (u - j * nquads) * 4 + wave;
+    const int64_t r0 = c * kL;
+    const T* col = (j < n) ? A + j * lda : bcol;
+    if (VEC && r0 + kL <= plan.m) {
+      const T* p = col + r0 + 4 * lane;
 #pragma unroll
-        for (int k = 0; k < SPL; ++k) {
-          const int t = lane + 64 * k;
+      for (int k = 0; k < 16; ++k) {
+        if constexpr (sizeof(T) == 4) {
+          const float4 q = *reinterpret_cast<const float4*>(p + 256 * k);
+          x[4 * k] = q.x; x[4 * k + 1] = q.y; x[4 * k + 2] = q.z; x[4 * k + 3] = q.w;
+        } else {
+          const double2 q0 = *reinterpret_cast<const double2*>(p + 256 * k);
+          const double2 q1 = *reinterpret_cast<const double2*>(p + 256 * k + 2);
+          x[4 * k] = q0.x; x[4 * k + 1] = q0.y; x[4 * k + 2] = q1.x; x[4 * k + 3] = q1.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = r0 + 256 * k + 4 * lane + e;
+          x[4 * k + e] = (row < plan.m) ? col[row] : T(0);
+        }
+    }
+  };
+
+  int64_t cur = -1;
+  if (u0 < u1) load_chunk(u0);
+  for (int64_t u = u0; u < u1; ++u) {
+    const int64_t j = u / nquads;
+    const int64_t q = u - j * nquads;
+    if (j != cur) {
+      if (cur >= 0) {
+        T* dst = partials + (blk + cur) * plan.slot_elems;
+#pragma unroll
+        for (int k = 0; k < SPQ; ++k) {
+          const int t = tid + 256 * k;
           if (t < s) dst[t] = acc[k];
           acc[k] = T(0);
         }
       }
-      cur_panel = panel;
+      cur = j;
     }
-    const int64_t j = panel;  // one column per panel
-    const T* col = (j < n) ? A + j * lda : bcol;
-    const int64_t r0 = c * kL;
-
-    // 1. load: lane holds rows r0 + 256 k + 4 lane + e in x[4k + e]
-    T x[64];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int64_t row = r0 + 256 * k + 4 * lane;
-      if (VEC && row + 3 < plan.m) {
-        if constexpr (sizeof(T) == 4) {
-          const float4 q = *reinterpret_cast<const float4*>(col + row);
-          x[4 * k] = q.x; x[4 * k + 1] = q.y; x[4 * k + 2] = q.z; x[4 * k + 3] = q.w;
-        } else {
-          const double2 q0 = *reinterpret_cast<const double2*>(col + row);
-          const double2 q1 = *reinterpret_cast<const double2*>(col + row + 2);
-          x[4 * k] = q0.x; x[4 * k + 1] = q0.y; x[4 * k + 2] = q1.x; x[4 * k + 3] = q1.y;
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) x[4 * k + e] = (row + e < plan.m) ? col[row + e] : T(0);
-      }
-    }
-    // 2. signs: 32 Philox blocks of 128 rows cover the chunk
+    const int64_t r0 = (q * 4 + wave) * kL;
+    // signs: 32 Philox blocks of 128 rows cover the chunk (rows beyond m are zero anyway)
     if (lane < 32) {
       const Words4 w = philox_at((uint64_t)(r0 >> 7) + lane, TAG_SRHT_SIGN, 0, seed);
       *reinterpret_cast<uint4*>(sgn + 4 * lane) = make_uint4(w.w[0], w.w[1], w.w[2], w.w[3]);
@@ -146,15 +168,14 @@ __global__ __launch_bounds__(64) void srht_kernel(const T* __restrict__ A, int64
         for (int e = 0; e < 4; ++e) x[4 * k + e] = flip<T>(x[4 * k + e], (word >> e) & 1u);
       }
     }
-    // 3. butterflies on row bits 0,1 (e) and 8..11 (k): register index bits 0..5
+    // butterflies on row bits 0,1 (e) and 8..11 (k): register index bits 0..5
 #pragma unroll
     for (int b = 0; b < 6; ++b) {
 #pragma unroll
       for (int i = 0; i < 64; ++i)
         if (!(i & (1 << b))) bfly(x[i], x[i | (1 << b)]);
     }
-    // 4. transpose through LDS: afterwards lane (a | b' << 2) holds rows
-    //    a + 4 i + 256 b' in x[i], i = 0..63
+    // transpose through LDS: afterwards lane (a | b' << 2) holds rows a + 4 i + 256 b'
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       T* p = buf + 256 * k + woff[k & 7];
@@ -168,7 +189,7 @@ __global__ __launch_bounds__(64) void srht_kernel(const T* __restrict__ A, int64
     wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < 64; ++i) x[i] = buf[roff[i & 7] + 32 * (i >> 3)];
-    // 5. butterflies on row bits 2..7
+    // butterflies on row bits 2..7
 #pragma unroll
     for (int b = 0; b < 6; ++b) {
 #pragma unroll
@@ -178,48 +199,73 @@ __global__ __launch_bounds__(64) void srht_kernel(const T* __restrict__ A, int64
     wave_lds_sync();
 #pragma unroll
     for (int i = 0; i < 64; ++i) buf[roff[i & 7] + 32 * (i >> 3)] = x[i];
-    wave_lds_sync();
-    // 6. combine: acc[t] += (-1)^popcount(r_hi & c) z[r_lo]
-    const uint32_t cmask = (uint32_t)c << SH;
+    // the registers are free again: the next unit's loads fly during the combine
+    if (u + 1 < u1) load_chunk(u + 1);
+    __syncthreads();
+    const uint32_t qmask = (uint32_t)q << 16;
 #pragma unroll
-    for (int k = 0; k < SPL; ++k) {
-      const T z = *reinterpret_cast<const T*>(smem + (pk[k] & AMASK));
-      const uint32_t par = __builtin_popcount(pk[k] & cmask) & 1u;
-      acc[k] += flip<T>(z, par);
+    for (int k = 0; k < SPQ; ++k) {
+      const unsigned char* zb = smem + (pk[k] & 0x3FFFu) * (sizeof(T) / 4);
+      const T z0 = *reinterpret_cast<const T*>(zb);
+      const T z1 = *reinterpret_cast<const T*>(zb + kL * sizeof(T));
+      const T z2 = *reinterpret_cast<const T*>(zb + 2 * kL * sizeof(T));
+      const T z3 = *reinterpret_cast<const T*>(zb + 3 * kL * sizeof(T));
+      const uint32_t ba = (pk[k] >> 14) & 1u, bb = (pk[k] >> 15) & 1u;
+      const T lo = z0 + flip<T>(z1, ba);
+      const T hi = z2 + flip<T>(z3, ba);
+      const T uq = lo + flip<T>(hi, bb);
+      const uint32_t par = __builtin_popcount(pk[k] & qmask) & 1u;
+      acc[k] += flip<T>(uq, par);
     }
-    wave_lds_sync();
+    __syncthreads();
   }
-  if (cur_panel >= 0) {
-    T* dst = partials + (wk + cur_panel) * plan.slot_elems;
+  if (cur >= 0) {
+    T* dst = partials + (blk + cur) * plan.slot_elems;
 #pragma unroll
-    for (int k = 0; k < SPL; ++k) {
-      const int t = lane + 64 * k;
+    for (int k = 0; k < SPQ; ++k) {
+      const int t = tid + 256 * k;
       if (t < s) dst[t] = acc[k];
     }
   }
 }
 
+// two workgroups per CU for fp32 with s <= 4096; otherwise the registers of
+// one wave per SIMD (the fp64 chunk buffers leave room for one workgroup anyway)
+template <typename T, int SPQ, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void srht_kernel2(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
+    const uint32_t* __restrict__ idx, uint64_t seed, T* __restrict__ partials) {
+  srht_body<T, SPQ, VEC>(A, lda, bcol, n, plan, idx, seed, partials);
+}
+template <typename T, int SPQ, bool VEC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void srht_kernel1(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
+    const uint32_t* __restrict__ idx, uint64_t seed, T* __restrict__ partials) {
+  srht_body<T, SPQ, VEC>(A, lda, bcol, n, plan, idx, seed, partials);
+}
+
 template <typename T>
 size_t srht_lds() {
-  return (size_t)kL * sizeof(T) + 512;
+  return 4 * (size_t)kL * sizeof(T) + 4 * 512;
 }
 
 PanelPlan srht_plan(const rmm_ctx* h, int64_t m, int ncols, int s, size_t tsize) {
-  const size_t lds = (size_t)kL * tsize + 512;
-  int per_cu = (int)(h->lds_bytes / lds);
-  if (per_cu > 8) per_cu = 8;
+  const size_t lds = 4 * (size_t)kL * tsize + 4 * 512;
+  int per_cu = (int)(160 * 1024 / lds);
+  if (per_cu > 2) per_cu = 2;
   if (per_cu < 1) per_cu = 1;
-  return make_plan(m, ncols, 1, s, s, kL, h->cus * per_cu);
+  return make_plan(m, ncols, 1, s, s, 4 * (int64_t)kL, h->cus * per_cu);
 }
 
-template <typename T, int SPL, bool VEC>
+template <typename T, int SPQ, bool VEC>
 int launch_srht(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
                 const PanelPlan& plan, const uint32_t* idx, uint64_t seed, T* partials) {
-  auto kern = srht_kernel<T, SPL, VEC>;
+  constexpr bool two = sizeof(T) == 4 && SPQ <= 16;
+  auto kern = two ? srht_kernel2<T, SPQ, VEC> : srht_kernel1<T, SPQ, VEC>;
   const size_t lds = srht_lds<T>();
   RMM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
-  hipLaunchKernelGGL(kern, dim3(plan.G), dim3(64), lds, h->stream, A, lda, b, n, plan, idx, seed,
+  hipLaunchKernelGGL(kern, dim3(plan.G), dim3(256), lds, h->stream, A, lda, b, n, plan, idx, seed,
                      partials);
   return launch_status();
 }
@@ -245,7 +291,7 @@ int srht_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b, 
   if (ncols == 0) return RMM_OK;
   const int k = ceil_log2((uint64_t)(m > 0 ? m : 1));
   if (s > (1ll << k) || s > 8192) return s > (1ll << k) ? RMM_ERR_INVALID_ARG : RMM_ERR_UNSUPPORTED;
-  if (k > 29) return RMM_ERR_UNSUPPORTED;  // r_hi must fit the packed sample field
+  if (k > 30) return RMM_ERR_UNSUPPORTED;  // r_hi >> 2 must fit the packed sample field
   if (m == 0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
   const PanelPlan plan = srht_plan(h, m, ncols, (int)s, sizeof(T));
   uint32_t* idx = ws.take<uint32_t>((size_t)s);
@@ -255,17 +301,17 @@ int srht_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b, 
   const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) &&
                    (b == nullptr || (uintptr_t)b % 16 == 0);
   int rc;
-#define RMM_SRHT_CASE(SPL)                                                                 \
-  rc = vec ? launch_srht<T, SPL, true>(h, A, lda, b, n, plan, idx, seed, partials)         \
-           : launch_srht<T, SPL, false>(h, A, lda, b, n, plan, idx, seed, partials);
+#define RMM_SRHT_CASE(SPQ)                                                                 \
+  rc = vec ? launch_srht<T, SPQ, true>(h, A, lda, b, n, plan, idx, seed, partials)         \
+           : launch_srht<T, SPQ, false>(h, A, lda, b, n, plan, idx, seed, partials);
   if (s <= 256) {
-    RMM_SRHT_CASE(4)
+    RMM_SRHT_CASE(1)
   } else if (s <= 1024) {
-    RMM_SRHT_CASE(16)
+    RMM_SRHT_CASE(4)
   } else if (s <= 4096) {
-    RMM_SRHT_CASE(64)
+    RMM_SRHT_CASE(16)
   } else {
-    RMM_SRHT_CASE(128)
+    RMM_SRHT_CASE(32)
   }
 #undef RMM_SRHT_CASE
   RMM_TRY(rc);
