@@ -15,90 +15,73 @@ __device__ __forceinline__ void or_status(int32_t* status, int32_t flag) {
   if (status) atomicOr(status, flag);
 }
 
-// W: l x (l + 1) column-major working array (ld = l).  On entry the upper
-// triangle holds G.  On exit: upper triangle = R, strict lower triangle =
-// R^{-1} transposed, column l = diag(R^{-1}).  The drop test of pivot j
-// compares against orig[j * ostride] (the diagonal of the matrix the caller
-// considers original), or against G_jj itself when orig is null.
-__device__ void cholinv_body(int l, double* W, double tau, const double* orig, int64_t ostride,
-                             double* __restrict__ Rinv, int64_t ldr, double* __restrict__ diag,
-                             int32_t* status, double* sh_orig, double* sh_piv) {
+// W: l x l column-major working array (ld = l) holding G on entry (upper
+// triangle read).  Elimination of [G | I] without row scaling: step j
+// subtracts W[j][i] / p_j times row j from every row i > j, where p_j is the
+// j-th pivot.  Afterwards the upper triangle holds D L~^T (G = L~ D L~^T,
+// L~ unit lower triangular), the strict lower triangle holds L~^{-1}, and
+//   R = D^{1/2} L~^T,   R^{-1}[c][j] = L~^{-1}[j][c] / sqrt(p_j)   (c <= j).
+// One barrier per step: row j is final before step j and is only read.
+// The drop test of pivot j compares against orig[j * ostride] (the diagonal
+// of the matrix the caller considers original), or G_jj when orig is null;
+// a dropped pivot eliminates nothing and gives a zero column of R^{-1}.
+__device__ void cholinv_body(int l, double* W, int ldw, double tau, const double* orig,
+                             int64_t ostride, double* __restrict__ Rinv, int64_t ldr,
+                             double* __restrict__ diag, int32_t* status, double* sh_orig,
+                             double* sh_piv) {
+  // blockDim.x == 1024, l <= 128: thread = (column c, row phase i0)
   const int tid = threadIdx.x;
-  const int nt = blockDim.x;
-  for (int j = tid; j < l; j += nt) sh_orig[j] = orig ? orig[j * ostride] : W[j + (int64_t)j * l];
+  const int c = tid & 127;
+  const int i0 = tid >> 7;
+  if (tid < l) sh_orig[tid] = orig ? orig[tid * ostride] : W[tid + tid * ldw];
+  if (c < l)
+    for (int i = i0; i < l; i += 8)
+      if (c < i) W[i + c * ldw] = 0.0;  // strict lower triangle: L~^{-1} below its unit diagonal
   __syncthreads();
-  // right-looking Cholesky on the upper triangle: G = R^T R
   for (int j = 0; j < l; ++j) {
+    const double p = W[j + j * ldw];
+    const bool keep = p > tau * sh_orig[j] && p > 1e-300;
     if (tid == 0) {
-      const double p = W[j + (int64_t)j * l];
-      double r = 0.0;
-      if (p > tau * sh_orig[j] && p > 1e-300) r = sqrt(p);
-      else or_status(status, RMM_STATUS_QR_FALLBACK);
-      *sh_piv = r;
-      W[j + (int64_t)j * l] = r;
+      sh_piv[j] = keep ? p : 0.0;
+      if (!keep) or_status(status, RMM_STATUS_QR_FALLBACK);
     }
-    __syncthreads();
-    const double r = *sh_piv;
-    const double inv = r > 0.0 ? 1.0 / r : 0.0;
-    for (int k = j + 1 + tid; k < l; k += nt) W[j + (int64_t)k * l] *= inv;
-    __syncthreads();
-    const int w = l - j - 1;
-    for (int e = tid; e < w * w; e += nt) {
-      const int a = j + 1 + e % w, b = j + 1 + e / w;
-      if (a <= b) W[a + (int64_t)b * l] -= W[j + (int64_t)a * l] * W[j + (int64_t)b * l];
+    if (keep && c < l) {
+      const double inv = 1.0 / p;
+      const double wjc = W[j + c * ldw];
+      const double lj = (c == j) ? 1.0 : wjc;  // L~^{-1}[j][c] for c <= j
+      for (int i = i0; i < l; i += 8) {
+        if (i <= j) continue;
+        const double f = W[j + i * ldw] * inv;  // W[j][i] / p_j
+        if (c >= i) W[i + c * ldw] -= f * wjc;   // Schur complement (upper)
+        else if (c <= j) W[i + c * ldw] -= f * lj;
+      }
     }
     __syncthreads();
   }
-  // X = R^{-1} by the column-oriented back substitution of R X = I.
-  // X[a][c] (a <= c) is kept at W[c + a l] for a < c and in column l for a == c.
-  for (int e = tid; e < l * l; e += nt) {
-    const int a = e % l, c = e / l;
-    if (a < c) W[c + (int64_t)a * l] = 0.0;
-  }
-  for (int c = tid; c < l; c += nt) W[c + (int64_t)l * l] = 1.0;
-  __syncthreads();
-  for (int i = l - 1; i >= 0; --i) {
-    const double r = W[i + (int64_t)i * l];
-    const double inv = r > 0.0 ? 1.0 / r : 0.0;
-    // row i of X is final after scaling
-    for (int c = i + tid; c < l; c += nt) {
-      if (c == i) W[c + (int64_t)l * l] *= inv;
-      else W[c + (int64_t)i * l] *= inv;
+  if (c < l) {
+    for (int j = i0; j < l; j += 8) {  // Rinv[c][j]
+      const double pj = sh_piv[j];
+      double v = 0.0;
+      if (pj > 0.0 && c <= j) v = ((c == j) ? 1.0 : W[j + c * ldw]) / sqrt(pj);
+      Rinv[c + (int64_t)j * ldr] = v;
     }
-    __syncthreads();
-    // X[a][c] -= R[a][i] X[i][c] for a < i <= c
-    const int w = l - i;
-    for (int e = tid; e < i * w; e += nt) {
-      const int a = e % i, c = i + e / i;
-      const double xic = (c == i) ? W[c + (int64_t)l * l] : W[c + (int64_t)i * l];
-      const double rai = W[a + (int64_t)i * l];
-      W[c + (int64_t)a * l] -= rai * xic;
-    }
-    __syncthreads();
   }
-  for (int e = tid; e < l * l; e += nt) {
-    const int a = e % l, c = e / l;
-    double v = 0.0;
-    if (a == c) v = W[c + (int64_t)l * l];
-    else if (a < c) v = W[c + (int64_t)a * l];
-    Rinv[a + (int64_t)c * ldr] = v;
-  }
-  for (int j = tid; j < l; j += nt) diag[j] = W[j + (int64_t)j * l];
+  if (tid < l) diag[tid] = sqrt(sh_piv[tid]);
 }
 
 __global__ __launch_bounds__(kSmallThreads) void cholinv_lds_kernel(
     int l, const double* __restrict__ G, int64_t ldg, double tau, const double* orig,
     int64_t ostride, double* __restrict__ Rinv, int64_t ldr, double* __restrict__ diag,
     int32_t* status) {
-  extern __shared__ double W[];  // l * (l + 1) + l + 1
-  double* sorig = W + (size_t)l * (l + 1);
+  extern __shared__ double W[];  // l x (l + 1) (padded), then 2 l
+  const int ldw = l + 1;           // odd stride: rows of W spread over the LDS banks
+  double* sorig = W + (size_t)l * ldw;
   double* piv = sorig + l;
-  for (int e = threadIdx.x; e < l * l; e += blockDim.x) {
-    const int a = e % l, b = e / l;
-    W[e] = G[a + (int64_t)b * ldg];
-  }
+  const int c = threadIdx.x & 127;
+  if (c < l)
+    for (int i = threadIdx.x >> 7; i < l; i += 8) W[i + c * ldw] = G[i + (int64_t)c * ldg];
   __syncthreads();
-  cholinv_body(l, W, tau, orig, ostride, Rinv, ldr, diag, status, sorig, piv);
+  cholinv_body(l, W, ldw, tau, orig, ostride, Rinv, ldr, diag, status, sorig, piv);
 }
 
 __global__ void fill_block_kernel(int rows, double* __restrict__ X, int64_t ldx) {
@@ -139,7 +122,7 @@ static int cholinv_rec(rmm_ctx* h, int l, const double* G, int64_t ldg, double t
                        const double* orig, int64_t ostride, double* Rinv, int64_t ldr, double* diag,
                        int32_t* status, Carver& ws) {
   if (l <= kLdsMaxL) {
-    const size_t lds = ((size_t)l * (l + 1) + l + 1) * sizeof(double);
+    const size_t lds = ((size_t)l * (l + 1) + 2 * (size_t)l) * sizeof(double);
     RMM_HIP(hipFuncSetAttribute((const void*)cholinv_lds_kernel,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(cholinv_lds_kernel, dim3(1), dim3(kSmallThreads), lds, h->stream, l, G, ldg,
@@ -197,26 +180,30 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
                                                                double* __restrict__ Vout,
                                                                double* __restrict__ Vw,
                                                                int32_t* status, int max_sweeps) {
-  extern __shared__ double S[];  // l * l, then pair tables
+  extern __shared__ double S[];  // l x (l + 1) (padded), then pair tables
+  const int lds = l + 1;
   const int L = (l + 1) & ~1;     // even number of players
   const int npairs = L / 2;
-  double* cs = S + (size_t)l * l;       // npairs
+  double* cs = S + (size_t)l * lds;     // npairs
   double* sn = cs + npairs;             // npairs
   int* pp = reinterpret_cast<int*>(sn + npairs);
   int* qq = pp + npairs;
-  __shared__ double red[kSmallThreads / 64];
+  __shared__ double red[1];
   __shared__ int done;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int e = tid; e < l * l; e += nt) {
-    const int a = e % l, b = e / l;
-    S[e] = G[a + (int64_t)b * ldg];
-    Vw[e] = (a == b) ? 1.0 : 0.0;
-  }
+  const int tid = threadIdx.x;
+  // thread = (column / row index k, pair phase i0); l <= 128, 1024 threads
+  const int k = tid & 127;
+  const int i0 = tid >> 7;
+  if (k < l)
+    for (int a = i0; a < l; a += 8) {
+      S[a + k * lds] = G[a + (int64_t)k * ldg];
+      Vw[a + (int64_t)k * l] = (a == k) ? 1.0 : 0.0;
+    }
   __syncthreads();
   // scale for the absolute part of the rotation threshold
   if (tid == 0) {
     double mx = 0.0;
-    for (int i = 0; i < l; ++i) mx = fmax(mx, fabs(S[i + (int64_t)i * l]));
+    for (int i = 0; i < l; ++i) mx = fmax(mx, fabs(S[i + i * lds]));
     red[0] = mx;
   }
   __syncthreads();
@@ -228,14 +215,15 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
     if (tid == 0) done = 1;
     __syncthreads();
     for (int r = 0; r < L - 1; ++r) {
-      for (int i = tid; i < npairs; i += nt) {
+      if (tid < npairs) {
+        const int i = tid;
         const int a = (i == 0) ? 0 : ((i - 1 + r) % (L - 1)) + 1;
         const int b = ((L - 2 - i + r) % (L - 1)) + 1;
         int p = a < b ? a : b, q = a < b ? b : a;
         double c = 1.0, s = 0.0;
         if (q < l) {
-          const double gpq = S[p + (int64_t)q * l];
-          const double gpp = S[p + (int64_t)p * l], gqq = S[q + (int64_t)q * l];
+          const double gpq = S[p + q * lds];
+          const double gpp = S[p + p * lds], gqq = S[q + q * lds];
           if (fabs(gpq) > abs_tol && fabs(gpq) > 0x1p-52 * sqrt(fabs(gpp * gqq))) {
             done = 0;
             const double theta = (gqq - gpp) / (2.0 * gpq);
@@ -243,9 +231,8 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
             c = 1.0 / sqrt(t * t + 1.0);
             s = t * c;
           }
-        } else {
-          p = q = -1;
         }
+        if (s == 0.0) p = -1;
         pp[i] = p;
         qq[i] = q;
         cs[i] = c;
@@ -253,44 +240,46 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
       }
       __syncthreads();
       // rows: G <- J^T G
-      for (int e = tid; e < npairs * l; e += nt) {
-        const int i = e / l, k = e % l;
-        const int p = pp[i], q = qq[i];
-        if (p < 0 || sn[i] == 0.0) continue;
-        const double c = cs[i], s = sn[i];
-        const double gp = S[p + (int64_t)k * l], gq = S[q + (int64_t)k * l];
-        S[p + (int64_t)k * l] = c * gp - s * gq;
-        S[q + (int64_t)k * l] = s * gp + c * gq;
-      }
+      if (k < l)
+        for (int i = i0; i < npairs; i += 8) {
+          const int p = pp[i];
+          if (p < 0) continue;
+          const int q = qq[i];
+          const double c = cs[i], s = sn[i];
+          const double gp = S[p + k * lds], gq = S[q + k * lds];
+          S[p + k * lds] = c * gp - s * gq;
+          S[q + k * lds] = s * gp + c * gq;
+        }
       __syncthreads();
       // columns: G <- G J and V <- V J
-      for (int e = tid; e < npairs * l; e += nt) {
-        const int i = e / l, k = e % l;
-        const int p = pp[i], q = qq[i];
-        if (p < 0 || sn[i] == 0.0) continue;
-        const double c = cs[i], s = sn[i];
-        const double gp = S[k + (int64_t)p * l], gq = S[k + (int64_t)q * l];
-        S[k + (int64_t)p * l] = c * gp - s * gq;
-        S[k + (int64_t)q * l] = s * gp + c * gq;
-        const double vp = Vw[k + (int64_t)p * l], vq = Vw[k + (int64_t)q * l];
-        Vw[k + (int64_t)p * l] = c * vp - s * vq;
-        Vw[k + (int64_t)q * l] = s * vp + c * vq;
-      }
+      if (k < l)
+        for (int i = i0; i < npairs; i += 8) {
+          const int p = pp[i];
+          if (p < 0) continue;
+          const int q = qq[i];
+          const double c = cs[i], s = sn[i];
+          const double gp = S[k + p * lds], gq = S[k + q * lds];
+          S[k + p * lds] = c * gp - s * gq;
+          S[k + q * lds] = s * gp + c * gq;
+          const double vp = Vw[k + (int64_t)p * l], vq = Vw[k + (int64_t)q * l];
+          Vw[k + (int64_t)p * l] = c * vp - s * vq;
+          Vw[k + (int64_t)q * l] = s * vp + c * vq;
+        }
       __syncthreads();
     }
     if (done) break;
   }
   if (sweep == max_sweeps && tid == 0) or_status(status, RMM_STATUS_NOT_CONVERGED);
   // sort descending (ties by index) and emit
-  for (int j = tid; j < l; j += nt) {
-    const double v = S[j + (int64_t)j * l];
+  for (int j = tid; j < l; j += blockDim.x) {
+    const double v = S[j + j * lds];
     int rank = 0;
     for (int i = 0; i < l; ++i) {
-      const double u = S[i + (int64_t)i * l];
+      const double u = S[i + i * lds];
       rank += (u > v) || (u == v && i < j);
     }
     evals[rank] = v;
-    for (int k = 0; k < l; ++k) Vout[k + (int64_t)rank * l] = Vw[k + (int64_t)j * l];
+    for (int kk = 0; kk < l; ++kk) Vout[kk + (int64_t)rank * l] = Vw[kk + (int64_t)j * l];
   }
 }
 
@@ -308,7 +297,7 @@ int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* ev
   double* Vw = ws.take<double>((size_t)l * l);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
   const int L = (l + 1) & ~1;
-  const size_t lds = (size_t)l * l * sizeof(double) + (size_t)L * sizeof(double) + (size_t)L * sizeof(int);
+  const size_t lds = (size_t)l * (l + 1) * sizeof(double) + (size_t)L * sizeof(double) + (size_t)L * sizeof(int);
   RMM_HIP(hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
   hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kSmallThreads), lds, h->stream, l, G, ldg, evals, V,
