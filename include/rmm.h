@@ -154,6 +154,20 @@ int rmm_plain_lsr(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d,
                   const void* A, int64_t lda, const void* b, double* x,
                   double* resid, int32_t* status);
 
+/* ---- mixed-precision product (test hook for the BF16 / FP8 passes of rsvd) --
+ * A (m x n fp32, lda >= m) is quantized per column (scale = max |A_ij| / QMAX,
+ * QMAX = 1 for BF16 and 448 for FP8 e4m3, round to nearest even) and the
+ * small operand X is quantized per column after the column scales of A are
+ * folded in (mode 0) or not (mode 1); the MFMA product accumulates in FP32:
+ *   mode 0: out (m x l, ldo >= m) = A X with X n x l (ldx >= n)
+ *   mode 1: out (n x l, ldo >= n) = A^T X with X m x l (ldx >= m)
+ * All pointers device; workspace from rmm_mixed_product_workspace. */
+int rmm_mixed_product_workspace(rmm_handle h, rmm_precision prec, int64_t m, int64_t n,
+                                int64_t l, size_t* bytes);
+int rmm_mixed_product(rmm_handle h, rmm_precision prec, int mode, int64_t m, int64_t n,
+                      const float* A, int64_t lda, const float* X, int64_t ldx, int64_t l,
+                      float* out, int64_t ldo);
+
 /* ---- random quantities (test hooks; Sec. 3.2, Alg. 3.1) ------------------- */
 /* CountSketch buckets h_i in [0, s) for rows 0..m-1 (int32, device). */
 int rmm_sketch_hashes(rmm_handle h, int64_t m, int64_t s, uint64_t seed,

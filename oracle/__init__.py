@@ -18,6 +18,8 @@ as plain, slow, obviously-correct numpy in float64:
 * ``lsr``      - sketch-and-solve least squares (eq. 4.2, Sec. 4.2) and the
                  exact solution of Sec. 4.1.
 * ``nystrom``  - the RBF kernel (Sec. 6.1.1) and the Nystrom method (Sec. 6.4).
+* ``mixed``    - BF16 / FP8 rounding and the per-column-scaled quantized
+                 products of the mixed-precision subspace iteration.
 
 Inputs reach the oracle as the exact bits the GPU path sees (float32 data is
 promoted exactly to float64).  Shared with the GPU path: nothing but the
@@ -26,4 +28,4 @@ arithmetic) and the written RNG contract, which both sides implement
 independently.
 """
 
-from . import rng, sketch, rsvd, lsr, nystrom  # noqa: F401
+from . import rng, sketch, rsvd, lsr, nystrom, mixed  # noqa: F401

@@ -71,6 +71,8 @@ def lib():
             "rmm_lsr_solve": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp],
             "rmm_residual_workspace": [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_residual": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp],
+            "rmm_mixed_product_workspace": [_vp, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_mixed_product": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _vp, _i64],
             "rmm_sketch_hashes": [_vp, _i64, _i64, _u64, _vp],
             "rmm_sketch_signs": [_vp, _i32, _i64, _u64, _vp],
             "rmm_srht_indices": [_vp, _i64, _i64, _u64, _vp],
@@ -264,6 +266,22 @@ class Handle:
         _check(lib().rmm_plain_lsr(self._h, dt, m, d, _ptr(A), _ld(A), _ptr(b), _ptr(x), _ptr(res),
                                    _ptr(status)), "rmm_plain_lsr")
         return x, res, status
+
+    def mixed_product(self, A: torch.Tensor, X: torch.Tensor, prec: int, mode: int) -> torch.Tensor:
+        """Quantized A X (mode 0) or A^T X (mode 1), fp32 accumulation."""
+        A = colmajor(A)
+        X = colmajor(X)
+        m, n = A.shape
+        l = X.shape[1]
+        rows = m if mode == 0 else n
+        out = torch.empty(l, rows, dtype=torch.float32, device=A.device).t()
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_mixed_product_workspace(self._h, prec, m, n, l, ctypes.byref(ws)),
+               "rmm_mixed_product_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_mixed_product(self._h, prec, mode, m, n, _ptr(A), _ld(A), _ptr(X), _ld(X), l,
+                                       _ptr(out), _ld(out)), "rmm_mixed_product")
+        return out
 
     # ---- random quantities ---------------------------------------------------
     def sketch_hashes(self, m: int, s: int, seed: int) -> torch.Tensor:

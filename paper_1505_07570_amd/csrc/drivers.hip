@@ -12,6 +12,7 @@
 
 #include "common.hpp"
 #include "dense.hpp"
+#include "mixed.hpp"
 #include "ops.hpp"
 #include "rng.hpp"
 
@@ -116,6 +117,78 @@ int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t ld
   RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, k, l, Q, m, Vr, l, 1.0, U, ldu, ws)));
   RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)n, k, l, Z, n, W, l, 1.0, V, ldv, ws)));
   return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
+}
+
+// ---- randomized SVD with BF16 / FP8 passes over A ----------------------------------------
+//
+// Same steps as rsvd_impl; every product with A runs on a one-time quantized
+// copy of A (mixed.hip), the small operands are quantized per column before
+// each pass, and the results come back in fp32 for the fp64 CholeskyQR2.
+int rsvd_mixed(rmm_ctx* h, bool run, rmm_precision prec, int64_t m, int64_t n, const float* A,
+               int64_t lda, int k, int p, int q, uint64_t seed, float* U, int64_t ldu, float* sigma,
+               float* V, int64_t ldv, int32_t* status, size_t* bytes) {
+  const int l = k + p;
+  const size_t eb = mp_elem_bytes(prec);
+  const int64_t pm = mp_pad(m), pn = mp_pad(n);
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  float* sc = ws.take<float>((size_t)n);
+  unsigned char* Aq = ws.take<unsigned char>((size_t)pm * n * eb);
+  unsigned char* Aqt = ws.take<unsigned char>((size_t)pn * m * eb);
+  unsigned char* Qq = ws.take<unsigned char>((size_t)pm * l * eb);
+  unsigned char* Xq = ws.take<unsigned char>((size_t)pn * l * eb);
+  float* uq = ws.take<float>((size_t)l);
+  float* ux = ws.take<float>((size_t)l);
+  float* Om = ws.take<float>((size_t)n * l);
+  float* Y = ws.take<float>((size_t)m * l);
+  float* Q = ws.take<float>((size_t)m * l);
+  float* Z = ws.take<float>((size_t)n * l);
+  float* Qz = ws.take<float>((size_t)n * l);
+  OrthBufs ob;
+  ob.G = ws.take<double>((size_t)l * l);
+  ob.Rinv = ws.take<double>((size_t)l * l);
+  ob.diag = ws.take<double>((size_t)l);
+  ob.Xd = ws.take<double>((size_t)(m > n ? m : n) * l);
+  double* evals = ws.take<double>((size_t)l);
+  double* Vr = ws.take<double>((size_t)l * l);
+  double* W = ws.take<double>((size_t)l * k);
+  size_t scratch = orth_scratch<float>(h, m, l);
+  scratch = smax(scratch, orth_scratch<float>(h, n, l));
+  scratch = smax(scratch, qgemm_workspace(h, (int)m, l, pn));
+  scratch = smax(scratch, qgemm_workspace(h, (int)n, l, pm));
+  scratch = smax(scratch, gemm_workspace<double>(h, l, l, n));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, l));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, l));
+  scratch = smax(scratch, jacobi_workspace(l));
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const double tau_m = 64.0 * kEps * (double)(m > l ? m : l);
+  const double tau_n = 64.0 * kEps * (double)(n > l ? n : l);
+  RMM_TRY(zero_status(h, status));
+  RMM_TRY(mp_quantize_matrix(h, prec, m, n, A, lda, sc, Aq, Aqt));
+  RMM_TRY(launch_gaussian<float>(h, TAG_GAUSS_RSVD, n, l, seed, Om, n));
+  // Y = A Omega = Aq_t^T q(diag(sc) Omega)
+  RMM_TRY(mp_quantize_cols(h, prec, n, l, Om, n, sc, Xq, ux));
+  RMM_TRY(mp_gemm_tn(h, prec, (int)m, l, pn, Aqt, Xq, nullptr, ux, Y, m, ws));
+  RMM_TRY(orth<float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
+  for (int t = 0; t < q; ++t) {
+    RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq));
+    RMM_TRY(mp_gemm_tn(h, prec, (int)n, l, pm, Aq, Qq, sc, uq, Z, n, ws));
+    RMM_TRY(orth<float>(h, n, l, Z, n, Qz, n, ob, tau_n, status, ws));
+    RMM_TRY(mp_quantize_cols(h, prec, n, l, Qz, n, sc, Xq, ux));
+    RMM_TRY(mp_gemm_tn(h, prec, (int)m, l, pn, Aqt, Xq, nullptr, ux, Y, m, ws));
+    RMM_TRY(orth<float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
+  }
+  RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq));
+  RMM_TRY(mp_gemm_tn(h, prec, (int)n, l, pm, Aq, Qq, sc, uq, Z, n, ws));
+  RMM_TRY((gemm<float, float, double, double>(h, true, false, l, l, n, Z, n, Z, n, 1.0, ob.G, l, ws)));
+  RMM_TRY(jacobi_eig(h, l, ob.G, l, evals, Vr, status, ws));
+  RMM_TRY(svd_from_eig<float>(h, l, k, evals, Vr, W, sigma));
+  RMM_TRY((gemm<float, double, double, float>(h, false, false, (int)m, k, l, Q, m, Vr, l, 1.0, U, ldu, ws)));
+  RMM_TRY((gemm<float, double, double, float>(h, false, false, (int)n, k, l, Z, n, W, l, 1.0, V, ldv, ws)));
+  return sign_fix<float>(h, m, n, k, U, ldu, V, ldv);
 }
 
 // ---- sketch-and-solve least squares ---------------------------------------------------
@@ -255,7 +328,9 @@ int rsvd_args(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t
   if (!h || !dt_ok(dt) || m < 1 || n < 1 || k < 1 || p < 0) return RMM_ERR_INVALID_ARG;
   if (k + p > (m < n ? m : n) || k + p > 128) return k + p > 128 ? RMM_ERR_UNSUPPORTED : RMM_ERR_INVALID_ARG;
   if (m >= (1ll << 31) || n >= (1ll << 31)) return RMM_ERR_UNSUPPORTED;
-  if (prec != RMM_PREC_NATIVE) return RMM_ERR_UNSUPPORTED;
+  if (prec != RMM_PREC_NATIVE && prec != RMM_PREC_BF16 && prec != RMM_PREC_FP8)
+    return RMM_ERR_INVALID_ARG;
+  if (prec != RMM_PREC_NATIVE && dt != RMM_F32) return RMM_ERR_UNSUPPORTED;
   return RMM_OK;
 }
 
@@ -277,6 +352,9 @@ int rmm_rsvd_workspace(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m
                        int64_t k, int64_t p, size_t* bytes) {
   RMM_TRY(rsvd_args(h, dt, prec, m, n, k, p));
   if (!bytes) return RMM_ERR_INVALID_ARG;
+  if (prec != RMM_PREC_NATIVE)
+    return rsvd_mixed(h, false, prec, m, n, nullptr, m, (int)k, (int)p, 0, 0, nullptr, m, nullptr,
+                      nullptr, n, nullptr, bytes);
   if (dt == RMM_F32)
     return rsvd_impl<float>(h, false, m, n, nullptr, m, (int)k, (int)p, 0, 0, nullptr, m, nullptr,
                             nullptr, n, nullptr, bytes);
@@ -290,6 +368,9 @@ int rmm_rsvd(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t 
   RMM_TRY(rsvd_args(h, dt, prec, m, n, k, p));
   if (!A || !U || !sigma || !V || q < 0 || ld_bad(lda, m) || ld_bad(ldu, m) || ld_bad(ldv, n))
     return RMM_ERR_INVALID_ARG;
+  if (prec != RMM_PREC_NATIVE)
+    return rsvd_mixed(h, true, prec, m, n, (const float*)A, lda, (int)k, (int)p, (int)q, seed,
+                      (float*)U, ldu, (float*)sigma, (float*)V, ldv, status, nullptr);
   if (dt == RMM_F32)
     return rsvd_impl<float>(h, true, m, n, (const float*)A, lda, (int)k, (int)p, (int)q, seed,
                             (float*)U, ldu, (float*)sigma, (float*)V, ldv, status, nullptr);

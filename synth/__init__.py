@@ -21,6 +21,10 @@ Workloads (the paper has no datasets; these follow its problem statements):
                   means N(0, 4 I), unit covariances, equal weights, and the
                   RBF bandwidth taken as the lower median of 10,000 pairwise
                   distances between distinct random points.
+* ``spectrum_matrix`` A = U diag(sigma) V^T with exactly orthonormal factors
+                  built from signed, permuted Hadamard transforms (a cheap
+                  construction of dense orthogonal matrices; it only shapes
+                  the input), e.g. sigma_i = 1/i on 65536 x 8192.
 """
 
 from __future__ import annotations
@@ -126,3 +130,67 @@ def gmm_points(seed: int = None, n: int = 200000, d: int = 32,
     dist.sort()
     sigma = float(dist[(pairs - 1) // 2])  # lower median
     return np.ascontiguousarray(X), sigma
+
+
+def _fwht_rows(x, xp):
+    """Unnormalized Walsh-Hadamard transform along axis 0 (length 2^k)."""
+    n = x.shape[0]
+    rest = x.shape[1:]
+    h = 1
+    while h < n:
+        y = x.reshape((n // (2 * h), 2, h) + rest)
+        a = y[:, 0]
+        b = y[:, 1]
+        x = xp.stack([a + b, a - b], axis=1).reshape((n,) + rest)
+        h *= 2
+    return x
+
+
+def spectrum_matrix(seed: int, m: int, n: int, sigma, backend: str = "numpy", device=None):
+    """A = U diag(sigma) V^T (m x n, float32) with exactly orthonormal U, V.
+
+    "Random orthonormal factors" read as: U = the first n columns of
+    (1/m) H_m D2 P H_m D1 and V = (1/n) H_n D4 P' H_n D3, with H the
+    Sylvester Hadamard matrix, D random signs and P random permutations
+    (a product of orthogonal matrices).  m and n must be powers of two.
+    backend "torch" builds the same recipe on `device` (random draws come
+    from numpy, so both backends use the same signs and permutations).
+    Returns A column-major: an (m, n) view of an (n, m) row-major buffer.
+    """
+    assert m & (m - 1) == 0 and n & (n - 1) == 0 and m >= n
+    rng = _rng(seed)
+    d1 = rng.choice([-1.0, 1.0], size=m)
+    d2 = rng.choice([-1.0, 1.0], size=m)
+    p = rng.permutation(m)
+    d3 = rng.choice([-1.0, 1.0], size=n)
+    d4 = rng.choice([-1.0, 1.0], size=n)
+    pp = rng.permutation(n)
+    sig = np.asarray(sigma, dtype=np.float64)
+    if backend == "torch":
+        import torch
+        xp = torch
+        f = lambda a: torch.as_tensor(a, dtype=torch.float64, device=device)  # noqa: E731
+        ip = lambda a: torch.as_tensor(a, dtype=torch.int64, device=device)   # noqa: E731
+        eye = torch.eye(n, dtype=torch.float64, device=device)
+    else:
+        xp = np
+        f = lambda a: np.asarray(a, dtype=np.float64)  # noqa: E731
+        ip = lambda a: np.asarray(a)  # noqa: E731
+        eye = np.eye(n)
+    # M = diag(sigma) V^T = (1/n) diag(sigma d3) H P'^T D4 H   (n x n)
+    T = _fwht_rows(eye, xp)                   # H
+    T = f(d4)[:, None] * T                    # D4 H
+    T = T[ip(np.argsort(pp))]                 # P'^T D4 H
+    T = _fwht_rows(T, xp)                     # H P'^T D4 H
+    M = (f(sig * d3) / n)[:, None] * T
+    # A = (1/m) H D2 P H D1 [M; 0]
+    X = xp.zeros((m, n), dtype=M.dtype) if backend != "torch" else torch.zeros((m, n), dtype=M.dtype, device=device)
+    X[:n] = M
+    X = f(d1)[:, None] * X
+    X = _fwht_rows(X, xp)
+    X = X[ip(p)]
+    X = f(d2)[:, None] * X
+    X = _fwht_rows(X, xp) / m
+    if backend == "torch":
+        return X.to(torch.float32).t().contiguous().t()
+    return np.asfortranarray(X.astype(np.float32))
