@@ -16,7 +16,6 @@ from tests.gpu_util import dev, host, rel
 
 pytestmark = pytest.mark.gpu
 rmm = pytest.importorskip("paper_1505_07570_amd")
-PRECS = [(rmm.PREC_BF16, omixed.BF16), (rmm.PREC_FP8, omixed.FP8)]
 
 
 @pytest.fixture(scope="module")
@@ -26,16 +25,90 @@ def h():
     return rmm.handle()
 
 
-@pytest.mark.parametrize("prec,oprec", PRECS)
-@pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("m,n,l", [(1000, 300, 37), (4096, 1024, 128), (70, 33, 5)])
-def test_quantized_product_matches_oracle(h, prec, oprec, mode, m, n, l):
+SHAPES = [(1000, 300, 37), (4096, 1024, 128), (70, 33, 5)]
+
+
+def _inputs(m, n, l, mode):
     r = np.random.default_rng(m + n + l)
     A = (r.standard_normal((m, n)) * np.exp2(r.integers(-4, 4, n))).astype(np.float32)
     X = r.standard_normal((n if mode == 0 else m, l)).astype(np.float32)
-    got = host(h.mixed_product(dev(A), dev(X), prec, mode))
-    ref = omixed.quantized_product(A, X, oprec, mode)
+    return A, X
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("m,n,l", SHAPES)
+def test_bf16_product_matches_oracle(h, mode, m, n, l):
+    # BF16 operands: every product is exact in fp32 and the MFMA accumulates
+    # in fp32, so the fp32 tolerance applies.
+    A, X = _inputs(m, n, l, mode)
+    got = host(h.mixed_product(dev(A), dev(X), rmm.PREC_BF16, mode))
+    ref = omixed.quantized_product(A, X, omixed.BF16, mode)
     assert rel(got, ref) < 1e-5
+
+
+def _fp8_bound(A, X, mode):
+    """Elementwise error bound of the FP8 MFMA product.
+
+    The fp8 16x16x32 MFMA adds each lane's 8 products (an aligned block of 8
+    along K) in a fixed-point window whose last bit is 2^-13 of the largest
+    product's power of two; lower bits of the other 7 are dropped (measured:
+    with a largest product of 2^e * [1, 4), a term 2^(e-13) is kept and
+    2^(e-14) vanishes, either sign).  Per block the error is therefore below
+    7 * 2^-13 * max|p|; the fp32 sums over blocks add K/8 + 2 roundings.
+    """
+    sc = omixed.column_scales(A, omixed.FP8)
+    Aq = omixed.quantize(A / sc[None, :], omixed.FP8).astype(np.float64)
+    Xs = X * sc[:, None] if mode == 0 else X
+    u = omixed.column_scales(Xs, omixed.FP8).astype(np.float64)
+    Xq = omixed.quantize(Xs / u[None, :].astype(np.float32), omixed.FP8).astype(np.float64)
+    L = np.abs(Aq if mode == 0 else Aq.T)   # rows x K
+    R = np.abs(Xq)                          # K x l
+    K = L.shape[1]
+    blockmax = np.zeros((L.shape[0], R.shape[1]))
+    for k0 in range(0, K, 8):
+        mx = np.zeros_like(blockmax)
+        for k in range(k0, min(k0 + 8, K)):
+            np.maximum(mx, np.outer(L[:, k], R[k]), out=mx)
+        blockmax += mx
+    bound = 7 * 2.0 ** -13 * blockmax + (K / 8 + 2) * 2.0 ** -24 * (L @ R)
+    bound *= u[None, :]
+    if mode == 1:
+        bound *= sc[:, None].astype(np.float64)
+    return bound
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("m,n,l", SHAPES)
+def test_fp8_product_matches_oracle(h, mode, m, n, l):
+    A, X = _inputs(m, n, l, mode)
+    got = host(h.mixed_product(dev(A), dev(X), rmm.PREC_FP8, mode))
+    ref = omixed.quantized_product(A, X, omixed.FP8, mode)
+    err = np.abs(got - ref)
+    bound = _fp8_bound(A, X, mode)
+    assert (err <= bound + 1e-6 * np.abs(ref)).all()
+    # the window error is small next to the e4m3 rounding itself (2^-4)
+    assert rel(got, ref) < 1e-3
+
+
+def test_fp8_block_window(h):
+    """The MFMA's per-block window, pinned on exact operands (unit scales)."""
+    m, n, l = 4, 64, 3
+    A = np.zeros((m, n), np.float32)
+    A[0, :] = 448                 # column maxima 448: unit column scales
+    A[1:, 0] = 448
+    A[1:, 1] = 1.0                # same K-block as the large product
+    A[1:, 9] = 1.0                # another K-block
+    A[2, 1] = -1.0
+    X = np.zeros((n, l), np.float32)
+    X[0, :] = 448
+    X[1, :] = [2.0 ** 3, 2.0 ** 2, 2.0 ** 5]
+    X[9, :] = 2.0 ** -6
+    got = host(h.mixed_product(dev(A), dev(X), rmm.PREC_FP8, 0))
+    big = 448.0 * 448.0           # 1.75^2 * 2^16: window ends at 2^3
+    assert got[1, 0] == big + 8 + 2.0 ** -6
+    assert got[1, 1] == big + 2.0 ** -6     # 2^2 falls below the window
+    assert got[2, 0] == big - 8 + 2.0 ** -6
+    assert got[2, 1] == big + 2.0 ** -6
 
 
 @pytest.mark.parametrize("prec,oprec,tol", [(rmm.PREC_BF16, omixed.BF16, 5e-3),
