@@ -15,8 +15,10 @@ per second of step time.
 
 Prints one JSON line.  Extra keys: per-family sketch time and roofline,
 sketch-and-solve p50/p99 latency next to the plain FP64 normal-equation
-solve, rsvd solves/s on the 2048 x 512 fp64 problem, and the CPU oracle timed
-on a bounded row sample of the same workload.
+solve, rsvd solves/s on the 2048 x 512 fp64 problem, the 65536 x 8192 rsvd
+(sigma_i = 1/i) in fp32, BF16 and FP8 with its error against the known
+spectrum, and the CPU oracle timed on a bounded row sample of the same
+workload.
 """
 
 from __future__ import annotations
@@ -99,6 +101,49 @@ def cpu_baseline(A, b, s, kinds, seed, rows):
     }
 
 
+def rsvd_spectrum(h, reps, lat):
+    """Randomized SVD of A = U diag(1/i) V^T (65536 x 8192 fp32), k=100, p=28, q=2,
+    in fp32 and with BF16 / FP8 operands: time per solve and the error against
+    the exactly known spectrum."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_1505_07570_amd as rmm
+    m, n, k, p, q = 65536, 8192, 100, 28, 2
+    sig = 1.0 / np.arange(1, n + 1)
+    A = synth.spectrum_matrix(synth.data_seed(3), m, n, sig, backend="torch", device="cuda")
+    torch.cuda.synchronize()
+    a_bytes = m * n * 4
+    opt = float(np.sqrt((sig[k:] ** 2).sum()))        # ||A - A_k||_F
+    seed = synth.sketch_seed(3)
+    out = {"m": m, "n": n, "k": k, "p": p, "q": q, "sigma": "1/i", "opt_resid_fro": opt}
+    for name, prec in (("fp32", rmm.PREC_NATIVE), ("bf16", rmm.PREC_BF16), ("fp8", rmm.PREC_FP8)):
+        U, s, V, st = h.rsvd(A, k, p, q, seed, prec=prec)
+        ts = lat(lambda: h.rsvd(A, k, p, q, seed, prec=prec), reps)
+        s64 = s.double().cpu().numpy()
+        # ||A - U diag(s) V^T||_F in row blocks
+        acc = 0.0
+        for r0 in range(0, m, 8192):
+            blk = A[r0:r0 + 8192] - (U[r0:r0 + 8192] * s[None, :]) @ V.t()
+            acc += float(torch.linalg.vector_norm(blk.double()) ** 2)
+        eb = {"fp32": 4, "bf16": 2, "fp8": 1}[name]
+        # algorithmic bytes: fp32 reads A in each of the 2q+2 products; the mixed
+        # paths read A once to quantize it, write two quantized copies and read one
+        # quantized copy per product
+        nb = (2 * q + 2) * a_bytes if eb == 4 else a_bytes * (1 + 2 * eb / 4 + (2 * q + 2) * eb / 4)
+        p50 = percentile(ts, 50)
+        out[name] = {"p50_ms": p50, "p99_ms": percentile(ts, 99), "solves_per_s": 1e3 / float(np.mean(ts)),
+                     "hbm_gbs_algorithmic": nb / (p50 * 1e-3) / 1e9, "status": int(st.item()),
+                     "max_sigma_err_rel_sigma1": float(np.abs(s64 - sig[:k]).max() / sig[0]),
+                     "max_sigma_rel_err": float((np.abs(s64 - sig[:k]) / sig[:k]).max()),
+                     "resid_fro_over_opt": float(np.sqrt(acc)) / opt}
+        del U, s, V
+    del A
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +154,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip latency / rsvd side measurements")
+    ap.add_argument("--rsvd-reps", type=int, default=5)
+    ap.add_argument("--only-rsvd-spectrum", action="store_true",
+                    help="run only the 65536 x 8192 rsvd leg (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the sketching path on a single "
@@ -128,6 +176,22 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
 
+    def lat(fn, reps):
+        ts = []
+        for _ in range(reps):
+            a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            z.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(z))
+        return ts
+
+    h = rmm.handle()
+    if args.only_rsvd_spectrum:
+        print(json.dumps({"rsvd_65536x8192": rsvd_spectrum(h, args.rsvd_reps, lat)}), flush=True)
+        return
+
     kinds = [k.strip() for k in args.kinds.split(",") if k.strip()]
     s, seed = 4096, synth.sketch_seed(2)
     t0 = time.perf_counter()
@@ -136,7 +200,6 @@ def main():
     m, d = A.shape
     Ad = torch.from_numpy(A.T.copy()).cuda().t()   # column-major, lda = m
     bd = torch.from_numpy(b).cuda()
-    h = rmm.handle()
     C = {k: torch.empty(d + 1, s, dtype=torch.float32, device="cuda").t() for k in kinds}
     res = {k: torch.empty(1, dtype=torch.float64, device="cuda") for k in kinds}
     xsol = {}
@@ -209,16 +272,6 @@ def main():
     }
 
     if not args.no_extras:
-        def lat(fn, reps):
-            ts = []
-            for _ in range(reps):
-                a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                a.record()
-                fn()
-                z.record()
-                torch.cuda.synchronize()
-                ts.append(a.elapsed_time(z))
-            return ts
         R = args.latency_reps
         lsr_lat = {}
         for k in kinds:
@@ -238,6 +291,8 @@ def main():
         out["rsvd_2048x512_fp64"] = {"k": 20, "p": 10, "q": 2, "p50_ms": percentile(ts, 50),
                                      "p99_ms": percentile(ts, 99),
                                      "solves_per_s": 1e3 / float(np.mean(ts))}
+        del A1d
+        out["rsvd_65536x8192"] = rsvd_spectrum(h, args.rsvd_reps, lat)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, b, s, kinds, seed, args.cpu_rows)
