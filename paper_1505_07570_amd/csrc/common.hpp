@@ -54,6 +54,14 @@ inline int launch_status() { return hip_status(hipGetLastError()); }
     if ((expr) != hipSuccess) return RMM_ERR_HIP; \
   } while (0)
 
+// Workgroup barrier that orders LDS accesses only: global stores issued
+// before it are not waited for (they are consumed by later kernels).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 inline bool dt_ok(rmm_dtype dt) { return dt == RMM_F32 || dt == RMM_F64; }
 inline size_t dt_size(rmm_dtype dt) { return dt == RMM_F64 ? 8 : 4; }
 

@@ -15,73 +15,109 @@ __device__ __forceinline__ void or_status(int32_t* status, int32_t flag) {
   if (status) atomicOr(status, flag);
 }
 
-// W: l x l column-major working array (ld = l) holding G on entry (upper
-// triangle read).  Elimination of [G | I] without row scaling: step j
+// Cholesky factor and triangular inverse of an l x l SPD matrix G (l <= 128,
+// upper triangle read) by elimination of [G | I] without row scaling: step j
 // subtracts W[j][i] / p_j times row j from every row i > j, where p_j is the
-// j-th pivot.  Afterwards the upper triangle holds D L~^T (G = L~ D L~^T,
-// L~ unit lower triangular), the strict lower triangle holds L~^{-1}, and
+// j-th pivot.  The working matrix W holds G's upper triangle and, below the
+// diagonal, L~^{-1} (initially 0, with an implicit unit diagonal).
+// Afterwards the upper triangle holds D L~^T (G = L~ D L~^T, L~ unit lower
+// triangular), the strict lower triangle holds L~^{-1}, and
 //   R = D^{1/2} L~^T,   R^{-1}[c][j] = L~^{-1}[j][c] / sqrt(p_j)   (c <= j).
-// One barrier per step: row j is final before step j and is only read.
+// Entry (i, c) changes in step j < i only for c >= i (Schur complement) or
+// c <= j (inverse part); there it loses f_i r_c with f_i = W[j][i] / p_j and
+// r = row j of W with r_j = 1.
+//
+// W lives in registers: thread (r0, c0) of the 32 x 32 thread grid owns rows
+// r0 + 32a and columns c0 + 32b (a, b < 4).  Step j only needs row j: its
+// owners publish it, with 1 / p_j, into one of two LDS row buffers right
+// after their step j - 1 update, so one barrier per step suffices.  All LDS
+// reads of a step are issued together, and the per-entry condition is a
+// select, so a step has a single LDS wait and no branches per entry.
 // The drop test of pivot j compares against orig[j * ostride] (the diagonal
 // of the matrix the caller considers original), or G_jj when orig is null;
 // a dropped pivot eliminates nothing and gives a zero column of R^{-1}.
-__device__ void cholinv_body(int l, double* W, int ldw, double tau, const double* orig,
-                             int64_t ostride, double* __restrict__ Rinv, int64_t ldr,
-                             double* __restrict__ diag, int32_t* status, double* sh_orig,
-                             double* sh_piv) {
-  // blockDim.x == 1024, l <= 128: thread = (column c, row phase i0)
-  const int tid = threadIdx.x;
-  const int c = tid & 127;
-  const int i0 = tid >> 7;
-  if (tid < l) sh_orig[tid] = orig ? orig[tid * ostride] : W[tid + tid * ldw];
-  if (c < l)
-    for (int i = i0; i < l; i += 8)
-      if (c < i) W[i + c * ldw] = 0.0;  // strict lower triangle: L~^{-1} below its unit diagonal
-  __syncthreads();
-  for (int j = 0; j < l; ++j) {
-    const double p = W[j + j * ldw];
-    const bool keep = p > tau * sh_orig[j] && p > 1e-300;
-    if (tid == 0) {
-      sh_piv[j] = keep ? p : 0.0;
-      if (!keep) or_status(status, RMM_STATUS_QR_FALLBACK);
-    }
-    if (keep && c < l) {
-      const double inv = 1.0 / p;
-      const double wjc = W[j + c * ldw];
-      const double lj = (c == j) ? 1.0 : wjc;  // L~^{-1}[j][c] for c <= j
-      for (int i = i0; i < l; i += 8) {
-        if (i <= j) continue;
-        const double f = W[j + i * ldw] * inv;  // W[j][i] / p_j
-        if (c >= i) W[i + c * ldw] -= f * wjc;   // Schur complement (upper)
-        else if (c <= j) W[i + c * ldw] -= f * lj;
-      }
-    }
-    __syncthreads();
-  }
-  if (c < l) {
-    for (int j = i0; j < l; j += 8) {  // Rinv[c][j]
-      const double pj = sh_piv[j];
-      double v = 0.0;
-      if (pj > 0.0 && c <= j) v = ((c == j) ? 1.0 : W[j + c * ldw]) / sqrt(pj);
-      Rinv[c + (int64_t)j * ldr] = v;
-    }
-  }
-  if (tid < l) diag[tid] = sqrt(sh_piv[tid]);
-}
-
-__global__ __launch_bounds__(kSmallThreads) void cholinv_lds_kernel(
+__global__ __launch_bounds__(kSmallThreads) void cholinv_reg_kernel(
     int l, const double* __restrict__ G, int64_t ldg, double tau, const double* orig,
     int64_t ostride, double* __restrict__ Rinv, int64_t ldr, double* __restrict__ diag,
     int32_t* status) {
-  extern __shared__ double W[];  // l x (l + 1) (padded), then 2 l
-  const int ldw = l + 1;           // odd stride: rows of W spread over the LDS banks
-  double* sorig = W + (size_t)l * ldw;
-  double* piv = sorig + l;
-  const int c = threadIdx.x & 127;
-  if (c < l)
-    for (int i = threadIdx.x >> 7; i < l; i += 8) W[i + c * ldw] = G[i + (int64_t)c * ldg];
+  __shared__ double rowbuf[2][kLdsMaxL];
+  __shared__ double invbuf[2];
+  __shared__ double sorig[kLdsMaxL];
+  __shared__ double piv[kLdsMaxL];
+  const int tid = threadIdx.x;
+  const int c0 = tid & 31, r0 = tid >> 5;
+  double w[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = r0 + 32 * a, c = c0 + 32 * b;
+      w[a][b] = (i < l && c < l && i <= c) ? G[i + (int64_t)c * ldg] : 0.0;
+    }
+  if (tid < l) sorig[tid] = orig ? orig[tid * ostride] : G[tid + (int64_t)tid * ldg];
   __syncthreads();
-  cholinv_body(l, W, ldw, tau, orig, ostride, Rinv, ldr, diag, status, sorig, piv);
+  // publish row j (held by the threads with r0 == j % 32, a == j / 32)
+  auto publish = [&](int j) {
+    if (j >= l || r0 != (j & 31)) return;
+    const int a = j >> 5;
+    double* rb = rowbuf[j & 1];
+#pragma unroll
+    for (int aa = 0; aa < 4; ++aa) {
+      if (aa != a) continue;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int c = c0 + 32 * b;
+        rb[c] = w[aa][b];
+        if (c == j) {
+          const double p = w[aa][b];
+          const bool keep = p > tau * sorig[j] && p > 1e-300;
+          invbuf[j & 1] = keep ? 1.0 / p : 0.0;
+          piv[j] = keep ? p : 0.0;
+          if (!keep) or_status(status, RMM_STATUS_QR_FALLBACK);
+        }
+      }
+    }
+  };
+  publish(0);
+  for (int j = 0; j < l; ++j) {
+    __syncthreads();
+    const double inv = invbuf[j & 1];
+    const double* rb = rowbuf[j & 1];
+    double rc[4], fr[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) rc[b] = rb[c0 + 32 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) fr[a] = rb[r0 + 32 * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if (c0 + 32 * b == j) rc[b] = 1.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const int i = r0 + 32 * a;
+      if (i <= j) continue;  // uniform over half-waves
+      const double f = fr[a] * inv;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int c = c0 + 32 * b;
+        const double d = (c >= i || c <= j) ? f * rc[b] : 0.0;
+        w[a][b] -= d;
+      }
+    }
+    publish(j + 1);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = r0 + 32 * a, c = c0 + 32 * b;  // W[j][c]
+      if (j >= l || c >= l) continue;
+      const double pj = piv[j];
+      double v = 0.0;
+      if (pj > 0.0 && c <= j) v = ((c == j) ? 1.0 : w[a][b]) / sqrt(pj);
+      Rinv[c + (int64_t)j * ldr] = v;
+    }
+  if (tid < l) diag[tid] = sqrt(piv[tid]);
 }
 
 __global__ void fill_block_kernel(int rows, double* __restrict__ X, int64_t ldx) {
@@ -122,10 +158,7 @@ static int cholinv_rec(rmm_ctx* h, int l, const double* G, int64_t ldg, double t
                        const double* orig, int64_t ostride, double* Rinv, int64_t ldr, double* diag,
                        int32_t* status, Carver& ws) {
   if (l <= kLdsMaxL) {
-    const size_t lds = ((size_t)l * (l + 1) + 2 * (size_t)l) * sizeof(double);
-    RMM_HIP(hipFuncSetAttribute((const void*)cholinv_lds_kernel,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(cholinv_lds_kernel, dim3(1), dim3(kSmallThreads), lds, h->stream, l, G, ldg,
+    hipLaunchKernelGGL(cholinv_reg_kernel, dim3(1), dim3(kSmallThreads), 0, h->stream, l, G, ldg,
                        tau, orig, ostride, Rinv, ldr, diag, status);
     return launch_status();
   }
@@ -171,36 +204,52 @@ int cholinv(rmm_ctx* h, int l, const double* G, int64_t ldg, double tau, double*
 // ---- cyclic Jacobi eigensolver ------------------------------------------------------
 //
 // Parallel (round-robin) ordering: in each of the L-1 rounds of a sweep the
-// L/2 disjoint pairs (p, q) of the circle method are rotated at once, first
-// the rows (J^T G), then the columns (G J) and the eigenvector columns (V J).
-// The rotation zeroing G_pq follows the classical choice
-// t = sgn(theta) / (|theta| + sqrt(theta^2 + 1)), theta = (G_qq - G_pp) / (2 G_pq).
+// L/2 disjoint pairs (p, q) of the circle method are rotated at once.  The
+// rotation zeroing G_pq follows the classical choice
+//   t = sgn(theta) / (|theta| + sqrt(theta^2 + 1)),  theta = (G_qq - G_pp) / (2 G_pq),
+//   c = 1 / sqrt(t^2 + 1),  s = t c,
+// with G_pp -= t G_pq, G_qq += t G_pq, G_pq = 0 on the rotated pair.
+//
+// jacobi_kernel works on G only: the upper triangle sits in LDS and the
+// update of one round is done per 2 x 2 block of pairs (i <= j), J_i^T G J_j,
+// so every stored element is read and written once per round.  The (c, s)
+// of every pair of every round are appended to a log in global memory;
+// jacobi_vectors_kernel then accumulates V = J_1 J_2 ... row by row, each
+// row of V being independent, with one wave per group of rows.
+constexpr int kJacobiMaxSweeps = 40;
+constexpr int kVecRows = 4;  // rows of V per wave
+
+__device__ __forceinline__ void rr_pair(int i, int r, int L, int& p, int& q) {
+  // circle method: player 0 fixed, players 1 .. L-1 rotate by one per round
+  const int a = (i == 0) ? 0 : ((i - 1 + r) % (L - 1)) + 1;
+  const int b = ((L - 2 - i + r) % (L - 1)) + 1;
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
 __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const double* __restrict__ G,
                                                                int64_t ldg, double* __restrict__ evals,
-                                                               double* __restrict__ Vout,
-                                                               double* __restrict__ Vw,
+                                                               int* __restrict__ perm,
+                                                               double2* __restrict__ rlog,
+                                                               int* __restrict__ nrounds,
                                                                int32_t* status, int max_sweeps) {
-  extern __shared__ double S[];  // l x (l + 1) (padded), then pair tables
-  const int lds = l + 1;
-  const int L = (l + 1) & ~1;     // even number of players
+  extern __shared__ double S[];  // L x (L + 1), upper triangle (a <= b at S[a + b * lds])
+  const int L = (l + 1) & ~1;     // even number of players; index l is a zero dummy when l is odd
+  const int lds = L + 1;
   const int npairs = L / 2;
-  double* cs = S + (size_t)l * lds;     // npairs
-  double* sn = cs + npairs;             // npairs
-  int* pp = reinterpret_cast<int*>(sn + npairs);
+  double* cs = S + (size_t)L * lds;  // per pair: c, s, t
+  double* sn = cs + npairs;
+  double* tn = sn + npairs;
+  int* pp = reinterpret_cast<int*>(tn + npairs);
   int* qq = pp + npairs;
   __shared__ double red[1];
   __shared__ int done;
   const int tid = threadIdx.x;
-  // thread = (column / row index k, pair phase i0); l <= 128, 1024 threads
-  const int k = tid & 127;
-  const int i0 = tid >> 7;
-  if (k < l)
-    for (int a = i0; a < l; a += 8) {
-      S[a + k * lds] = G[a + (int64_t)k * ldg];
-      Vw[a + (int64_t)k * l] = (a == k) ? 1.0 : 0.0;
-    }
+  for (int e = tid; e < L * L; e += blockDim.x) {
+    const int a = e % L, b = e / L;
+    if (a <= b) S[a + b * lds] = (b < l) ? G[a + (int64_t)b * ldg] : 0.0;
+  }
   __syncthreads();
-  // scale for the absolute part of the rotation threshold
   if (tid == 0) {
     double mx = 0.0;
     for (int i = 0; i < l; ++i) mx = fmax(mx, fabs(S[i + i * lds]));
@@ -208,69 +257,106 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
   }
   __syncthreads();
   const double abs_tol = 1e-17 * red[0];
-  int sweep = 0;
+  // blocks (i, j), i <= j, of the pair grid: row pair (u, npairs-1-u) holds
+  // npairs + 1 blocks; 32 threads share one row pair
+  const int rp = tid >> 5, w = tid & 31;
+  int sweep = 0, rounds = 0;
   for (; sweep < max_sweeps; ++sweep) {
-    // a sweep that rotates nothing ends the iteration
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) done = 1;
-    __syncthreads();
-    for (int r = 0; r < L - 1; ++r) {
+    lds_barrier();
+    for (int r = 0; r < L - 1; ++r, ++rounds) {
+      // the log stores are not waited for at the barriers below
       if (tid < npairs) {
-        const int i = tid;
-        const int a = (i == 0) ? 0 : ((i - 1 + r) % (L - 1)) + 1;
-        const int b = ((L - 2 - i + r) % (L - 1)) + 1;
-        int p = a < b ? a : b, q = a < b ? b : a;
-        double c = 1.0, s = 0.0;
+        int p, q;
+        rr_pair(tid, r, L, p, q);
+        double c = 1.0, s = 0.0, tt = 0.0;
         if (q < l) {
           const double gpq = S[p + q * lds];
           const double gpp = S[p + p * lds], gqq = S[q + q * lds];
           if (fabs(gpq) > abs_tol && fabs(gpq) > 0x1p-52 * sqrt(fabs(gpp * gqq))) {
             done = 0;
             const double theta = (gqq - gpp) / (2.0 * gpq);
-            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
+            tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(tt * tt + 1.0);
+            s = tt * c;
           }
         }
-        if (s == 0.0) p = -1;
-        pp[i] = p;
-        qq[i] = q;
-        cs[i] = c;
-        sn[i] = s;
+        pp[tid] = p;
+        qq[tid] = q;
+        cs[tid] = c;
+        sn[tid] = s;
+        tn[tid] = tt;
+        rlog[(size_t)rounds * npairs + tid] = make_double2(c, s);
       }
-      __syncthreads();
-      // rows: G <- J^T G
-      if (k < l)
-        for (int i = i0; i < npairs; i += 8) {
-          const int p = pp[i];
-          if (p < 0) continue;
-          const int q = qq[i];
-          const double c = cs[i], s = sn[i];
-          const double gp = S[p + k * lds], gq = S[q + k * lds];
-          S[p + k * lds] = c * gp - s * gq;
-          S[q + k * lds] = s * gp + c * gq;
+      lds_barrier();
+      if (rp < (npairs + 1) / 2) {
+        // up to 3 blocks per thread; all LDS reads of a thread's blocks are
+        // issued before any arithmetic so their latencies overlap
+        const int u0 = rp, u1 = npairs - 1 - rp;
+        const int n0 = npairs - u0;  // blocks (u0, u0 .. npairs-1), then (u1, u1 .. npairs-1)
+        const int nb = (u0 == u1) ? n0 : npairs + 1;
+        int bi[3], bj[3];
+        bool live[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int b = w + 32 * k;
+          live[k] = b < nb;
+          bi[k] = b < n0 ? u0 : u1;
+          bj[k] = b < n0 ? u0 + b : u1 + (b - n0);
+          if (!live[k]) bi[k] = bj[k] = 0;
         }
-      __syncthreads();
-      // columns: G <- G J and V <- V J
-      if (k < l)
-        for (int i = i0; i < npairs; i += 8) {
-          const int p = pp[i];
-          if (p < 0) continue;
-          const int q = qq[i];
-          const double c = cs[i], s = sn[i];
-          const double gp = S[k + p * lds], gq = S[k + q * lds];
-          S[k + p * lds] = c * gp - s * gq;
-          S[k + q * lds] = s * gp + c * gq;
-          const double vp = Vw[k + (int64_t)p * l], vq = Vw[k + (int64_t)q * l];
-          Vw[k + (int64_t)p * l] = c * vp - s * vq;
-          Vw[k + (int64_t)q * l] = s * vp + c * vq;
+        double ci[3], si[3], cj[3], sj[3], ti[3];
+        int pi[3], qi[3], pj[3], qj[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          ci[k] = cs[bi[k]]; si[k] = sn[bi[k]]; ti[k] = tn[bi[k]];
+          cj[k] = cs[bj[k]]; sj[k] = sn[bj[k]];
+          pi[k] = pp[bi[k]]; qi[k] = qq[bi[k]]; pj[k] = pp[bj[k]]; qj[k] = qq[bj[k]];
         }
-      __syncthreads();
+        int ad[3][4];
+        double x[3][4];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          // element (a, b) of the symmetric matrix lives at (min, max)
+          ad[k][0] = pi[k] < pj[k] ? pi[k] + pj[k] * lds : pj[k] + pi[k] * lds;
+          ad[k][1] = pi[k] < qj[k] ? pi[k] + qj[k] * lds : qj[k] + pi[k] * lds;
+          ad[k][2] = qi[k] < pj[k] ? qi[k] + pj[k] * lds : pj[k] + qi[k] * lds;
+          ad[k][3] = qi[k] < qj[k] ? qi[k] + qj[k] * lds : qj[k] + qi[k] * lds;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[k][e] = S[ad[k][e]];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          if (!live[k] || (si[k] == 0.0 && sj[k] == 0.0)) continue;
+          if (bi[k] == bj[k]) {
+            // x = (pp, pq, qp, qq) of the rotated pair
+            const double gpq = x[k][1];
+            S[ad[k][0]] = x[k][0] - ti[k] * gpq;
+            S[ad[k][3]] = x[k][3] + ti[k] * gpq;
+            S[ad[k][1]] = 0.0;
+            continue;
+          }
+          // rows: J_i^T X, then columns: (J_i^T X) J_j
+          const double y00 = ci[k] * x[k][0] - si[k] * x[k][2];
+          const double y01 = ci[k] * x[k][1] - si[k] * x[k][3];
+          const double y10 = si[k] * x[k][0] + ci[k] * x[k][2];
+          const double y11 = si[k] * x[k][1] + ci[k] * x[k][3];
+          S[ad[k][0]] = cj[k] * y00 - sj[k] * y01;
+          S[ad[k][1]] = sj[k] * y00 + cj[k] * y01;
+          S[ad[k][2]] = cj[k] * y10 - sj[k] * y11;
+          S[ad[k][3]] = sj[k] * y10 + cj[k] * y11;
+        }
+      }
+      lds_barrier();
     }
     if (done) break;
   }
-  if (sweep == max_sweeps && tid == 0) or_status(status, RMM_STATUS_NOT_CONVERGED);
-  // sort descending (ties by index) and emit
+  if (tid == 0) {
+    *nrounds = rounds;
+    if (sweep == max_sweeps) or_status(status, RMM_STATUS_NOT_CONVERGED);
+  }
+  // sort descending (ties by index)
   for (int j = tid; j < l; j += blockDim.x) {
     const double v = S[j + j * lds];
     int rank = 0;
@@ -279,29 +365,109 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
       rank += (u > v) || (u == v && i < j);
     }
     evals[rank] = v;
-    for (int kk = 0; kk < l; ++kk) Vout[kk + (int64_t)rank * l] = Vw[kk + (int64_t)j * l];
+    perm[rank] = j;
+  }
+}
+
+// V = J_1 J_2 ... J_R from the rotation log; Vout[:, rank] = V[:, perm[rank]].
+// One wave owns kVecRows rows of V in LDS; lane i applies pair i of every
+// round to those rows (the pairs of a round are disjoint, and one wave's LDS
+// accesses are performed in program order, so no barrier is needed).
+__global__ __launch_bounds__(256) void jacobi_vectors_kernel(int l, const double2* __restrict__ rlog,
+                                                             const int* __restrict__ nrounds,
+                                                             const int* __restrict__ perm,
+                                                             double* __restrict__ Vout) {
+  extern __shared__ double vs[];  // 4 waves x kVecRows x L, then the pair tables
+  const int L = (l + 1) & ~1;
+  const int npairs = L / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* V = vs + (size_t)wave * kVecRows * L;
+  unsigned char* ptab = reinterpret_cast<unsigned char*>(vs + (size_t)4 * kVecRows * L);
+  unsigned char* qtab = ptab + (size_t)(L - 1) * npairs;
+  for (int e = threadIdx.x; e < (L - 1) * npairs; e += blockDim.x) {
+    int p, q;
+    rr_pair(e % npairs, e / npairs, L, p, q);
+    ptab[e] = (unsigned char)p;
+    qtab[e] = (unsigned char)q;
+  }
+  const int row0 = (blockIdx.x * 4 + wave) * kVecRows;
+  for (int e = lane; e < kVecRows * L; e += 64) {
+    const int rr = e / L, c = e % L;
+    V[e] = (row0 + rr == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int R = *nrounds;
+  const bool active = lane < npairs;
+  // the log is read kPrefetch rounds ahead: the next batch is in flight while
+  // the current one is applied
+  constexpr int kPrefetch = 16;
+  double2 cur[kPrefetch], nxt[kPrefetch];
+#pragma unroll
+  for (int u = 0; u < kPrefetch; ++u)
+    cur[u] = (active && u < R) ? rlog[(size_t)u * npairs + lane] : make_double2(1.0, 0.0);
+  int r = 0;  // round within the sweep
+  for (int t0 = 0; t0 < R; t0 += kPrefetch) {
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      const int t = t0 + kPrefetch + u;
+      nxt[u] = (active && t < R) ? rlog[(size_t)t * npairs + lane] : make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      if (t0 + u < R && cur[u].y != 0.0) {
+        const int p = ptab[r * npairs + lane], q = qtab[r * npairs + lane];
+#pragma unroll
+        for (int rr = 0; rr < kVecRows; ++rr) {
+          const double vp = V[rr * L + p], vq = V[rr * L + q];
+          V[rr * L + p] = cur[u].x * vp - cur[u].y * vq;
+          V[rr * L + q] = cur[u].y * vp + cur[u].x * vq;
+        }
+      }
+      if (++r == L - 1) r = 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) cur[u] = nxt[u];
+  }
+  for (int rr = 0; rr < kVecRows; ++rr) {
+    const int k = row0 + rr;
+    if (k >= l) break;
+    for (int rank = lane; rank < l; rank += 64) Vout[k + (int64_t)rank * l] = V[rr * L + perm[rank]];
   }
 }
 
 size_t jacobi_workspace(int l) {
+  const int L = (l + 1) & ~1;
   Carver c(nullptr, 0);
-  c.take<double>((size_t)l * l);
-  return c.off;
+  c.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * (L / 2));
+  c.take<int>((size_t)l);
+  c.take<int>(1);
+  return c.off + 3 * kAlign;
 }
 
 int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals, double* V,
                int32_t* status, Carver& ws) {
   if (l == 0) return RMM_OK;
   if (l > kLdsMaxL) return RMM_ERR_UNSUPPORTED;
-  const size_t mark = ws.off;
-  double* Vw = ws.take<double>((size_t)l * l);
-  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
   const int L = (l + 1) & ~1;
-  const size_t lds = (size_t)l * (l + 1) * sizeof(double) + (size_t)L * sizeof(double) + (size_t)L * sizeof(int);
+  const int npairs = L / 2;
+  const size_t mark = ws.off;
+  double2* rlog = ws.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * npairs);
+  int* perm = ws.take<int>((size_t)l);
+  int* nr = ws.take<int>(1);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const size_t lds = (size_t)L * (L + 1) * sizeof(double) + 3 * (size_t)npairs * sizeof(double) +
+                     2 * (size_t)npairs * sizeof(int);
   RMM_HIP(hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kSmallThreads), lds, h->stream, l, G, ldg, evals, V,
-                     Vw, status, 40);
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kSmallThreads), lds, h->stream, l, G, ldg, evals,
+                     perm, rlog, nr, status, kJacobiMaxSweeps);
+  RMM_TRY(launch_status());
+  const size_t vlds = (size_t)4 * kVecRows * L * sizeof(double) + 2 * (size_t)(L - 1) * npairs;
+  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
+  const int groups = (l + 4 * kVecRows - 1) / (4 * kVecRows);
+  hipLaunchKernelGGL(jacobi_vectors_kernel, dim3(groups), dim3(256), vlds, h->stream, l, rlog, nr,
+                     perm, V);
   ws.off = mark;
   return launch_status();
 }
