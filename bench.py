@@ -51,12 +51,22 @@ def src_sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kind, launches_bytes):
-    """HBM bytes per launch from committed rocprofv3 counter summaries.
+# main kernel of each sketch family (the one the counters are read for)
+KERNEL_NAME = {
+    "countsketch": "countsketch_sched_kernel",
+    "srht": "srht_kernel",
+    "gaussian": "gauss_sketch_kernel",
+}
+COPY_ELEMS = 1 << 28  # fp32 elements of the calibration copy (1 GiB read, 1 GiB written)
 
-    profiles/traffic.json maps a sketch family to the FETCH_SIZE / WRITE_SIZE
-    (KiB per dispatch) of its kernels, the copy-kernel calibration factor and
-    the sha of the kernel source they were taken on; stale entries give null.
+
+def measured_traffic(kind):
+    """HBM bytes per launch of a family's main kernel from committed counters.
+
+    profiles/traffic.json holds, per sketch family, the FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch) of its main kernel, the factors that map
+    each counter onto the bytes of a plain copy of known size, and the sha
+    of the kernel source they were taken on; stale entries give null.
     """
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
@@ -65,7 +75,63 @@ def measured_traffic(kind, launches_bytes):
         t = json.load(f).get(kind)
     if not t or t.get("src_sha") != src_sha(KERNEL_SRC[kind]):
         return None
-    return (t["fetch_kib"] + t["write_kib"]) * 1024.0 * t.get("scale", 1.0)
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
+def traffic_workload(h, Ad, bd, C, s, seed, kinds):
+    """The dispatches the counter runs read: a plain copy of known size, then
+    two sketches per family (the second one is the measured dispatch)."""
+    import torch
+    x = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+    for k in kinds:
+        for _ in range(2):
+            h.sketch(Ad, s, k, seed, b=bd, out=C[k])
+        torch.cuda.synchronize()
+
+
+def summarize_traffic(fetch_csv, write_csv, kinds):
+    """profiles/traffic.json from the counter CSVs of the two runs."""
+    import csv
+
+    def per_dispatch(path, counter):
+        rows = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r.get("Counter_Name", counter) != counter:
+                    continue
+                d = int(r["Dispatch_Id"])
+                rows.setdefault(d, [r["Kernel_Name"], 0.0])
+                rows[d][1] += float(r["Counter_Value"])
+        return [rows[d] for d in sorted(rows)]
+
+    out = {}
+    fetch = per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = per_dispatch(write_csv, "WRITE_SIZE")
+    kib = COPY_ELEMS * 4 / 1024.0
+
+    def last(rows, needle):
+        hits = [v for n, v in rows if needle in n]
+        return hits[-1] if hits else None
+
+    # the calibration copy is the largest copy dispatch of the run
+    cf = max((v for n, v in fetch if "copy" in n), default=None)
+    cw = max((v for n, v in write if "copy" in n), default=None)
+    for k in kinds:
+        fk, wk = last(fetch, KERNEL_NAME[k]), last(write, KERNEL_NAME[k])
+        if None in (fk, wk, cf, cw):
+            continue
+        out[k] = {"kernel": KERNEL_NAME[k], "fetch_kib": fk, "write_kib": wk,
+                  "fetch_scale": kib / cf, "write_scale": kib / cw,
+                  "copy_fetch_kib": cf, "copy_write_kib": cw, "copy_kib_each_way": kib,
+                  "src_sha": src_sha(KERNEL_SRC[k])}
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
 
 
 def percentile(xs, q):
@@ -157,7 +223,15 @@ def main():
     ap.add_argument("--rsvd-reps", type=int, default=5)
     ap.add_argument("--only-rsvd-spectrum", action="store_true",
                     help="run only the 65536 x 8192 rsvd leg (for profiling)")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="run only the dispatches read by the FETCH_SIZE / WRITE_SIZE counter runs")
+    ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from the two counter-collection CSVs")
     args = ap.parse_args()
+    if args.traffic_summarize:
+        kinds = [k.strip() for k in args.kinds.split(",") if k.strip()]
+        print(json.dumps(summarize_traffic(*args.traffic_summarize, kinds)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the sketching path on a single "
               "MI355X (the multi-GPU sharding is a design, not a measured configuration).",
@@ -204,6 +278,9 @@ def main():
     res = {k: torch.empty(1, dtype=torch.float64, device="cuda") for k in kinds}
     xsol = {}
     ab_bytes = (m * (d + 1)) * 4
+    if args.traffic_run:
+        traffic_workload(h, Ad, bd, C, s, seed, kinds)
+        return
 
     def step(ev=None):
         for k in kinds:
@@ -240,11 +317,11 @@ def main():
             flops = 2.0 * s * m * (d + 1)
             rl[k] = {"bound": "mfma", "achieved": flops / t / 1e12, "peak": FP32_MFMA_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": flops / t / 1e12 / FP32_MFMA_PEAK_TFLOPS,
-                     "traffic": measured_traffic(k, ab_bytes)}
+                     "traffic": measured_traffic(k)}
         else:
             nb = ab_bytes + s * (d + 1) * 4
             rl[k] = {"bound": "hbm", "achieved": nb / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": nb / t / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic(k, nb)}
+                     "frac": nb / t / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic(k)}
     dominant = max(kinds, key=lambda k: sketch_ms[k])
 
     out = {
