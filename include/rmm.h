@@ -8,6 +8,7 @@
  *   - randomized k-SVD with subspace iteration (Alg. 5.2, power step of Alg. 5.1)
  *   - sketch-and-solve least squares          (eq. 4.2, Sec. 4.2)
  *   - exact least squares x* = A^+ b           (Sec. 4.1), the "plain" comparator
+ *   - Nystrom approximation of an RBF kernel   (Sec. 6.4, kernel of Sec. 6.1.1)
  *
  * Conventions shared by every call
  * --------------------------------
@@ -153,6 +154,26 @@ int rmm_plain_lsr_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d,
 int rmm_plain_lsr(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d,
                   const void* A, int64_t lda, const void* b, double* x,
                   double* resid, int32_t* status);
+
+/* ---- Nystrom approximation of an RBF kernel matrix (Sec. 6.4; kernel of
+ * Sec. 6.1.1) -----------------------------------------------------------------
+ * X: n points of dimension d (row-major n x d fp32, ldx >= d, device).
+ * K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) is never formed.
+ *   idx (c int64)     S, c sorted indices drawn uniformly without replacement
+ *                     from [0, n) (stream tag 6)
+ *   C (n x c fp32, ldc >= n, column-major)   K[:, S]
+ *   evals (c doubles) eigenvalues of W = K[S, S] (computed in FP64), descending
+ *   L (n x k fp32, ldl >= n)  C U_k Lam_k^{-1/2}, so that K ~ L L^T =
+ *                     C W_k^+ C^T; eigenvalues <= c * 2^-52 * lambda_max give
+ *                     zero columns
+ * Requires 1 <= k <= c <= n; d <= 64 and c <= 128 (RMM_ERR_UNSUPPORTED
+ * beyond).  status: RMM_STATUS_NOT_CONVERGED from the eigensolver. */
+int rmm_nystrom_workspace(rmm_handle h, int64_t n, int64_t d, int64_t c, int64_t k,
+                          size_t* bytes);
+int rmm_nystrom(rmm_handle h, int64_t n, int64_t d, const float* X, int64_t ldx,
+                double sigma, int64_t c, int64_t k, uint64_t seed, int64_t* idx,
+                float* C, int64_t ldc, float* L, int64_t ldl, double* evals,
+                int32_t* status);
 
 /* ---- mixed-precision product (test hook for the BF16 / FP8 passes of rsvd) --
  * A (m x n fp32, lda >= m) is quantized per column (scale = max |A_ij| / QMAX,

@@ -9,7 +9,8 @@ directly (the listing's expanded form cancels badly in low precision).
 Nystrom (Sec. 6.4 and its listing): S = c sorted uniform indices drawn
 without replacement; C = K[:, S]; W = C[S, :]; W = U Lam U^T;
 keep the top k = ceil(0.8 c) eigenpairs; L = C U_k Lam_k^{-1/2} so that
-K ~ L L^T = C W_k^+ C^T.  Reading: the footnote writes Lam^{-1}; only the
+K ~ L L^T = C W_k^+ C^T.  Eigenvalues at or below c * 2^-52 * lambda_max are
+treated as zero (the pseudo-inverse drops them), on both sides.  Reading: the footnote writes Lam^{-1}; only the
 listing's Lam^{-1/2} gives L L^T = C W_k^+ C^T.
 
 Gaussian variant: C = K Omega with Omega (n x c) i.i.d. N(0, 1) and
@@ -41,13 +42,25 @@ def sample(n: int, c: int, seed: int):
     return rng.sample_indices(n, c, rng.TAG_NYSTROM_SAMPLE, seed)
 
 
-def _factor(C, W, k):
+def _scaled_basis(W, k):
+    """F = U_k Lam_k^{-1/2} (c x k) and the eigenvalues of W, descending.
+
+    Eigenvalues at or below c * 2^-52 * lambda_max are numerically zero: their
+    columns of F are zero, which is the pseudo-inverse W_k^+ = F F^T.
+    """
     lam, U = np.linalg.eigh(W)
     order = np.argsort(lam)[::-1]
     lam = lam[order]
     U = U[:, order]
-    L = C @ (U[:, :k] / np.sqrt(lam[:k])[None, :])
-    return L, lam
+    c = W.shape[0]
+    keep = (lam[:k] > c * 2.0 ** -52 * lam[0]) & (lam[:k] > 0)
+    inv = np.where(keep, 1.0 / np.sqrt(np.where(keep, lam[:k], 1.0)), 0.0)
+    return U[:, :k] * inv[None, :], lam
+
+
+def _factor(C, W, k):
+    F, lam = _scaled_basis(W, k)
+    return C @ F, lam
 
 
 def nystrom(X, sigma: float, c: int, seed: int, k=None):
@@ -60,6 +73,21 @@ def nystrom(X, sigma: float, c: int, seed: int, k=None):
     W = C[S, :]
     L, lam = _factor(C, W, k)
     return L, S, C, W, lam
+
+
+def nystrom_rows(X, sigma: float, c: int, seed: int, rows, k=None):
+    """Rows `rows` of the column-sampling Nystrom factor L, without forming C.
+
+    Returns (L[rows], S, W, eigenvalues).  Row i of L is K[i, S] U_k
+    Lam_k^{-1/2}, so the rows are computed independently of each other.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    k = default_rank(c) if k is None else int(k)
+    S = sample(n, c, seed)
+    W = rbf(X[S], X[S], sigma)
+    F, lam = _scaled_basis(W, k)
+    return rbf(X[np.asarray(rows)], X[S], sigma) @ F, S, W, lam
 
 
 def nystrom_gaussian(X, sigma: float, c: int, seed: int, k=None, fp64=True):

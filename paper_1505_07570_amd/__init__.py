@@ -12,6 +12,7 @@ Matrices are torch tensors on the GPU in column-major layout
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 
 import torch
@@ -73,6 +74,9 @@ def lib():
             "rmm_residual": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp],
             "rmm_mixed_product_workspace": [_vp, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_mixed_product": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _vp, _i64],
+            "rmm_nystrom_workspace": [_vp, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_nystrom": [_vp, _i64, _i64, _vp, _i64, ctypes.c_double, _i64, _i64, _u64, _vp, _vp,
+                            _i64, _vp, _i64, _vp, _vp],
             "rmm_sketch_hashes": [_vp, _i64, _i64, _u64, _vp],
             "rmm_sketch_signs": [_vp, _i32, _i64, _u64, _vp],
             "rmm_srht_indices": [_vp, _i64, _i64, _u64, _vp],
@@ -282,6 +286,28 @@ class Handle:
         _check(lib().rmm_mixed_product(self._h, prec, mode, m, n, _ptr(A), _ld(A), _ptr(X), _ld(X), l,
                                        _ptr(out), _ld(out)), "rmm_mixed_product")
         return out
+
+    # ---- Nystrom --------------------------------------------------------------
+    def nystrom(self, X: torch.Tensor, sigma: float, c: int, seed: int, k: int = None):
+        """RBF-kernel Nystrom factor of the rows of X (n x d, fp32, row-major).
+
+        Returns (L (n x k), idx (c), C (n x c), evals (c), status)."""
+        if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+            X = X.to(torch.float32).contiguous()
+        n, d = X.shape
+        k = int(math.ceil(0.8 * c)) if k is None else int(k)
+        idx = torch.empty(c, dtype=torch.int64, device=X.device)
+        C = torch.empty(c, n, dtype=torch.float32, device=X.device).t()
+        L = torch.empty(k, n, dtype=torch.float32, device=X.device).t()
+        evals = torch.empty(c, dtype=torch.float64, device=X.device)
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_nystrom_workspace(self._h, n, d, c, k, ctypes.byref(ws)), "rmm_nystrom_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_nystrom(self._h, n, d, _ptr(X), X.stride(0), float(sigma), c, k, seed, _ptr(idx),
+                                 _ptr(C), _ld(C), _ptr(L), _ld(L), _ptr(evals), _ptr(status)),
+               "rmm_nystrom")
+        return L, idx, C, evals, status
 
     # ---- random quantities ---------------------------------------------------
     def sketch_hashes(self, m: int, s: int, seed: int) -> torch.Tensor:

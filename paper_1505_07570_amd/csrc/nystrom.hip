@@ -1,0 +1,195 @@
+// Nystrom approximation of an RBF kernel matrix (Sec. 6.4, kernel of Sec. 6.1.1).
+//
+//   K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)),  x_i = row i of X (n x d).
+//   S = c sorted indices drawn uniformly without replacement from [0, n);
+//   C = K[:, S] (n x c, fp32), W = K[S, S] (c x c, fp64),
+//   W = U Lam U^T, L = C U_k Lam_k^{-1/2}  so that  K ~ L L^T = C W_k^+ C^T.
+//
+// The kernel matrix is never formed: C is computed tile by tile from X.  The
+// squared distances are formed from the differences (not from the expanded
+// inner products, which cancel in fp32).  W is computed in fp64 from the same
+// fp32 points, so that its eigendecomposition does not see C's rounding.
+#include "common.hpp"
+#include "dense.hpp"
+#include "ops.hpp"
+#include "rng.hpp"
+
+namespace rmm {
+
+constexpr int kRbfRows = 256;  // rows of C per workgroup (one per thread)
+constexpr int kRbfCols = 32;   // columns of C per LDS stage
+constexpr int kRbfMaxD = 64;   // point dimension held in registers
+
+// C[i + j * ldc] = exp(-||x_i - x_{S_j}||^2 * g), g = 1 / (2 sigma^2).
+// Thread = one row i.  The workgroup's 256 points sit in LDS (rows padded to
+// D + 1 floats: conflict-free per-thread reads) and the workgroup walks over
+// all c columns in stages of kRbfCols sampled points, stored coordinate-major
+// so that one broadcast 16-byte LDS read serves four columns.  Writes are
+// coalesced along i.
+template <int D>
+__global__ __launch_bounds__(kRbfRows) void rbf_columns_kernel(int64_t n, int d, const float* __restrict__ X,
+                                                               int64_t ldx, int c, const int64_t* __restrict__ idx,
+                                                               float g, float* __restrict__ C, int64_t ldc) {
+  __shared__ __align__(16) float ys[D][kRbfCols];
+  __shared__ float xs[kRbfRows][D + 1];
+  const int64_t r0 = (int64_t)blockIdx.x * kRbfRows;
+  const int64_t i = r0 + threadIdx.x;
+  for (int e = threadIdx.x; e < kRbfRows * D; e += kRbfRows) {
+    const int r = e / D, k = e % D;
+    xs[r][k] = (r0 + r < n && k < d) ? X[(r0 + r) * ldx + k] : 0.0f;
+  }
+  for (int j0 = 0; j0 < c; j0 += kRbfCols) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kRbfCols * D; e += kRbfRows) {
+      const int jj = e / D, k = e % D;
+      const int j = j0 + jj;
+      ys[k][jj] = (j < c && k < d) ? X[idx[j] * ldx + k] : 0.0f;
+    }
+    __syncthreads();
+    const int jn = (c - j0) < kRbfCols ? (c - j0) : kRbfCols;
+    if (i >= n) continue;
+    float acc[kRbfCols];
+#pragma unroll
+    for (int q = 0; q < kRbfCols; ++q) acc[q] = 0.0f;
+#pragma unroll 2
+    for (int k = 0; k < d; ++k) {
+      const float xk = xs[threadIdx.x][k];
+#pragma unroll
+      for (int q = 0; q < kRbfCols; q += 4) {
+        const float4 y = *reinterpret_cast<const float4*>(&ys[k][q]);
+        float t = xk - y.x;
+        acc[q] = fmaf(t, t, acc[q]);
+        t = xk - y.y;
+        acc[q + 1] = fmaf(t, t, acc[q + 1]);
+        t = xk - y.z;
+        acc[q + 2] = fmaf(t, t, acc[q + 2]);
+        t = xk - y.w;
+        acc[q + 3] = fmaf(t, t, acc[q + 3]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kRbfCols; ++q)
+      if (q < jn) C[i + (int64_t)(j0 + q) * ldc] = expf(-acc[q] * g);
+  }
+}
+
+// W[a + b * c] = exp(-||x_{S_a} - x_{S_b}||^2 / (2 sigma^2)) in fp64.
+__global__ void rbf_gram_f64_kernel(int d, const float* __restrict__ X, int64_t ldx, int c,
+                                    const int64_t* __restrict__ idx, double g, double* __restrict__ W) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (a >= c) return;
+  const float* xa = X + idx[a] * ldx;
+  const float* xb = X + idx[b] * ldx;
+  double acc = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double t = (double)xa[k] - (double)xb[k];
+    acc = fma(t, t, acc);
+  }
+  W[a + (int64_t)b * c] = exp(-acc * g);
+}
+
+// F[:, t] = V[:, t] / sqrt(lam_t) for lam_t > c * eps * lam_0, else 0 (t < k).
+__global__ void nystrom_scale_kernel(int c, int k, const double* __restrict__ lam,
+                                     const double* __restrict__ V, double* __restrict__ F) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  if (a >= c) return;
+  const double cut = (double)c * 0x1p-52 * lam[0];
+  const double l = lam[t];
+  F[a + (int64_t)t * c] = (l > cut && l > 0.0) ? V[a + (int64_t)t * c] / sqrt(l) : 0.0;
+}
+
+namespace {
+
+struct NysBufs {
+  double* W;
+  double* V;
+  double* F;
+};
+
+// layout shared by the size query and the run
+size_t nystrom_layout(const rmm_ctx* h, int64_t n, int c, int k, Carver& ws, NysBufs* b) {
+  double* W = ws.take<double>((size_t)c * c);
+  double* V = ws.take<double>((size_t)c * c);
+  double* F = ws.take<double>((size_t)c * k);
+  if (b) *b = NysBufs{W, V, F};
+  size_t scratch = jacobi_workspace(c);
+  const size_t g = gemm_workspace<double>(h, (int)n, k, c);
+  if (g > scratch) scratch = g;
+  return ws.off + scratch + 4 * kAlign;
+}
+
+}  // namespace
+
+size_t nystrom_workspace(const rmm_ctx* h, int64_t n, int c, int k) {
+  Carver ws(nullptr, 0);
+  return nystrom_layout(h, n, c, k, ws, nullptr);
+}
+
+int nystrom_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, double sigma, int c,
+                int k, uint64_t seed, int64_t* idx, float* C, int64_t ldc, float* L, int64_t ldl,
+                double* evals, int32_t* status) {
+  Carver ws(h->ws, h->ws_bytes);
+  NysBufs b;
+  const size_t need = nystrom_layout(h, n, c, k, ws, &b);
+  if (need > h->ws_bytes) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  RMM_TRY(zero_status(h, status));
+  RMM_TRY(launch_sample_indices_i64(h, (uint64_t)n, ceil_log2((uint64_t)n), c, TAG_NYSTROM_SAMPLE,
+                                    seed, idx));
+  const double g = 1.0 / (2.0 * sigma * sigma);
+  const unsigned blocks = (unsigned)((n + kRbfRows - 1) / kRbfRows);
+  if (d <= 32)
+    hipLaunchKernelGGL(rbf_columns_kernel<32>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n, d, X,
+                       ldx, c, idx, (float)g, C, ldc);
+  else
+    hipLaunchKernelGGL(rbf_columns_kernel<kRbfMaxD>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n,
+                       d, X, ldx, c, idx, (float)g, C, ldc);
+  RMM_TRY(launch_status());
+  hipLaunchKernelGGL(rbf_gram_f64_kernel, dim3((unsigned)((c + 127) / 128), (unsigned)c), dim3(128), 0,
+                     h->stream, d, X, ldx, c, idx, g, b.W);
+  RMM_TRY(launch_status());
+  RMM_TRY(jacobi_eig(h, c, b.W, c, evals, b.V, status, ws));
+  hipLaunchKernelGGL(nystrom_scale_kernel, dim3((unsigned)((c + 127) / 128), (unsigned)k), dim3(128), 0,
+                     h->stream, c, k, evals, b.V, b.F);
+  RMM_TRY(launch_status());
+  return gemm<float, double, double, float>(h, false, false, (int)n, k, c, C, ldc, b.F, c, 1.0, L, ldl,
+                                            ws);
+}
+
+}  // namespace rmm
+
+using namespace rmm;
+
+namespace {
+
+int nystrom_args(rmm_handle h, int64_t n, int64_t d, int64_t c, int64_t k, double sigma) {
+  if (!h || n < 1 || d < 1 || c < 1 || c > n || k < 1 || k > c || !(sigma > 0.0) ||
+      !(sigma < 1e300))
+    return RMM_ERR_INVALID_ARG;
+  if (d > kRbfMaxD || c > 128 || n >= (1ll << 31)) return RMM_ERR_UNSUPPORTED;
+  return RMM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rmm_nystrom_workspace(rmm_handle h, int64_t n, int64_t d, int64_t c, int64_t k,
+                          size_t* bytes) {
+  RMM_TRY(nystrom_args(h, n, d, c, k, 1.0));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  *bytes = nystrom_workspace(h, n, (int)c, (int)k);
+  return RMM_OK;
+}
+
+int rmm_nystrom(rmm_handle h, int64_t n, int64_t d, const float* X, int64_t ldx, double sigma,
+                int64_t c, int64_t k, uint64_t seed, int64_t* idx, float* C, int64_t ldc, float* L,
+                int64_t ldl, double* evals, int32_t* status) {
+  RMM_TRY(nystrom_args(h, n, d, c, k, sigma));
+  if (!X || !idx || !C || !L || !evals || ldx < d || ldc < n || ldl < n) return RMM_ERR_INVALID_ARG;
+  return nystrom_run(h, n, (int)d, X, ldx, sigma, (int)c, (int)k, seed, idx, C, ldc, L, ldl, evals,
+                     status);
+}
+
+}  // extern "C"

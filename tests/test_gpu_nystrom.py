@@ -1,0 +1,98 @@
+"""GPU parity of the Nystrom method (Sec. 6.4) against the FP64 oracle.
+
+Sample indices bit-exact; C = K[:, S] (fp32) within the fp32 tolerance;
+eigenvalues of W = K[S, S] (fp64 on both sides) within the fp64 tolerance
+relative to lambda_max; L within a bound derived from C's fp32 rounding
+propagated through F = U_k Lam_k^{-1/2}, after aligning column signs (each
+column of L is unique up to sign when the kept eigenvalues are distinct).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import nystrom as onys
+from tests.gpu_util import host, rel
+
+pytestmark = pytest.mark.gpu
+rmm = pytest.importorskip("paper_1505_07570_amd")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return rmm.handle()
+
+
+def _align(L, Lo):
+    s = np.sign((L * Lo).sum(axis=0))
+    s[s == 0] = 1.0
+    return L * s[None, :]
+
+
+def _check_L(L, Lo, Co, lam, k, c):
+    keep = (lam[:k] > c * 2.0 ** -52 * lam[0]) & (lam[:k] > 0)
+    fnorm = 1.0 / np.sqrt(lam[:k][keep].min())
+    # fp32 rounding of C (relative 2^-24 per entry plus the distance error)
+    # times ||F||_2, relative to ||L||_F
+    bound = 64 * 2.0 ** -24 * np.linalg.norm(Co) * fnorm / np.linalg.norm(Lo) + 1e-6
+    assert rel(_align(L, Lo), Lo) <= bound
+
+
+@pytest.mark.parametrize("n,d,c,k", [(3000, 32, 100, None), (777, 3, 37, 37), (5000, 64, 128, 64),
+                                     (129, 7, 129 - 1, None)])
+def test_nystrom_parity(h, n, d, c, k):
+    X, sigma = synth.gmm_points(seed=n + d, n=n, d=d, pairs=2000)
+    Lo, So, Co, Wo, lamo = onys.nystrom(X, sigma, c, seed=41, k=k)
+    kk = onys.default_rank(c) if k is None else k
+    L, idx, C, ev, st = h.nystrom(torch.from_numpy(X).cuda(), sigma, c, 41, k=kk)
+    assert int(st.item()) == 0
+    np.testing.assert_array_equal(idx.cpu().numpy(), So)
+    C = host(C)
+    assert rel(C, Co) < 1e-5
+    assert np.abs(host(ev) - lamo).max() <= 1e-12 * lamo[0]
+    _check_L(host(L), Lo, Co, lamo, kk, c)
+
+
+def test_nystrom_full_rows_sampled(h):
+    """n = 200,000 points in 32 dimensions, c = 128: C and L on sampled rows."""
+    n, d, c = 200000, 32, 128
+    X, sigma = synth.gmm_points(n=n, d=d)
+    L, idx, C, ev, st = h.nystrom(torch.from_numpy(X).cuda(), sigma, c, 43)
+    rows = np.unique(np.random.default_rng(5).integers(0, n, 512))
+    Lr, So, Wo, lamo = onys.nystrom_rows(X, sigma, c, 43, rows)
+    np.testing.assert_array_equal(idx.cpu().numpy(), So)
+    Cr = onys.rbf(X[rows], X[So], sigma)
+    assert rel(host(C[torch.from_numpy(rows).cuda()]), Cr) < 1e-5
+    assert np.abs(host(ev) - lamo).max() <= 1e-12 * lamo[0]
+    _check_L(host(L[torch.from_numpy(rows).cuda()]), Lr, Cr, lamo, onys.default_rank(c), c)
+
+
+def test_nystrom_identity_on_sample(h):
+    """With k = c, (L L^T)[S, S] reproduces W (Sec. 6.4, W W^+ W = W)."""
+    X, sigma = synth.gmm_points(seed=9, n=2000, d=16, pairs=2000)
+    c = 64
+    L, idx, C, ev, st = h.nystrom(torch.from_numpy(X).cuda(), sigma, c, 5, k=c)
+    S = idx.cpu().numpy()
+    Ls = host(L)[S]
+    W = onys.rbf(X[S], X[S], sigma)
+    lam = np.linalg.eigvalsh(W)
+    assert lam.min() > 1e-8 * lam.max()
+    # C[S, :] is the fp32 rounding of W: the identity holds to fp32 accuracy
+    # amplified by ||W^-1|| ||W||
+    assert rel(Ls @ Ls.T, W) < 1e-6 * lam.max() / lam.min() + 1e-6
+
+
+def test_nystrom_invalid(h):
+    X = torch.zeros(100, 4, dtype=torch.float32, device="cuda")
+    with pytest.raises(rmm.RmmError):
+        h.nystrom(X, 1.0, 129, 1)          # c > 128: eigensolver limit
+    with pytest.raises(rmm.RmmError):
+        h.nystrom(X, 1.0, 10, 1, k=11)     # k > c
+    with pytest.raises(rmm.RmmError):
+        h.nystrom(X, 0.0, 10, 1)           # sigma <= 0
+    Xw = torch.zeros(100, 65, dtype=torch.float32, device="cuda")
+    with pytest.raises(rmm.RmmError):
+        h.nystrom(Xw, 1.0, 10, 1)          # d > 64

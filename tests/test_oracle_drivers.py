@@ -171,3 +171,24 @@ def test_nystrom_gaussian_variant():
     np.testing.assert_allclose(W, Om.T @ K @ Om, rtol=1e-10, atol=1e-9)
     # L L^T = C W^+ C^T, and its projection onto Omega reproduces W
     np.testing.assert_allclose(Om.T @ L @ L.T @ Om, W, rtol=0, atol=1e-6 * np.abs(W).max())
+
+
+def test_nystrom_rows_and_zero_eigenvalues():
+    X, sigma = synth.gmm_points(seed=8, n=500, d=5, pairs=500)
+    X = X.copy()
+    c = 24
+    S = nystrom.sample(500, c, 9)
+    X[S[1]] = X[S[0]]          # two identical sampled points: W is exactly singular
+    L, S2, C, W, lam = nystrom.nystrom(X, sigma, c, seed=9, k=c)
+    np.testing.assert_array_equal(S, S2)
+    assert lam[-1] <= c * 2.0 ** -52 * lam[0]
+    # the dropped direction gives a zero column; L L^T is still C W^+ C^T and
+    # reproduces W on S (W W^+ W = W, Fact A.4)
+    assert np.abs(L[:, -1]).max() == 0.0
+    LLt = L @ L.T
+    np.testing.assert_allclose(LLt[np.ix_(S, S)], W, rtol=0, atol=1e-8)
+    np.testing.assert_allclose(LLt, C @ np.linalg.pinv(W, rcond=1e-13) @ C.T, rtol=0, atol=1e-7)
+    rows = np.array([0, 7, 123, 499])
+    Lr, _, Wr, lamr = nystrom.nystrom_rows(X, sigma, c, 9, rows, k=c)
+    np.testing.assert_array_equal(Wr, W)
+    np.testing.assert_allclose(Lr, L[rows], rtol=0, atol=1e-13)
