@@ -106,6 +106,48 @@ int rmm_sketch(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m,
                int64_t n, const void* A, int64_t lda, const void* b, int64_t s,
                uint64_t seed, void* C, int64_t ldc);
 
+/* ---- batches of sketches (grouped execution) ----------------------------------
+ * One call sketches `count` independent problems of different shapes, each
+ * as in rmm_sketch (C_i = S_i^T [A_i | b_i] with its own s_i and seed_i; A_i
+ * m_i x n_i column-major, b_i optional).  descs is a HOST array of `count`
+ * descriptors; the pointers in it are device pointers.  For COUNTSKETCH with
+ * every s_i <= 16384 the batch runs as one grouped launch per stage over a
+ * descriptor table uploaded to the workspace (hipMemcpyAsync on the handle's
+ * stream); otherwise the problems run one after another.  Either way each
+ * C_i is bitwise identical to rmm_sketch on problem i alone.  Workspace from
+ * rmm_sketch_batch_workspace with the same descriptors. */
+typedef struct {
+  int64_t m, n;      /* A is m x n */
+  const void* A;
+  int64_t lda;
+  const void* b;     /* optional extra column (NULL: none) */
+  int64_t s;
+  uint64_t seed;
+  void* C;           /* s x (n + (b != NULL)), ldc >= s */
+  int64_t ldc;
+} rmm_sketch_desc;
+int rmm_sketch_batch_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,
+                               int64_t count, const rmm_sketch_desc* descs,
+                               size_t* bytes);
+int rmm_sketch_batch(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t count,
+                     const rmm_sketch_desc* descs);
+
+/* ---- admission for serving (host only; no device calls) ---------------------
+ * A first-come-first-served queue of requests, each holding `bytes` of
+ * device memory while it runs, under a total budget.  rmm_sched_admit moves
+ * queued requests to running, in arrival order, while they fit next to the
+ * running ones, and stops at the first that does not (no starvation);
+ * rmm_sched_complete releases a running request.  A request larger than the
+ * budget is rejected by rmm_sched_submit (RMM_ERR_INVALID_ARG), as is a
+ * duplicate id.  Not thread safe: one scheduler per serving thread. */
+typedef struct rmm_sched* rmm_sched_t;
+int rmm_sched_create(size_t budget_bytes, rmm_sched_t* out);
+int rmm_sched_destroy(rmm_sched_t s);
+int rmm_sched_submit(rmm_sched_t s, int64_t id, size_t bytes);
+int rmm_sched_admit(rmm_sched_t s, int64_t max_ids, int64_t* ids, int64_t* n);
+int rmm_sched_complete(rmm_sched_t s, int64_t id);
+int rmm_sched_stats(rmm_sched_t s, size_t* in_use, int64_t* queued, int64_t* running);
+
 /* ---- randomized k-SVD (Alg. 5.2 with the subspace iteration of Alg. 5.1) --
  * A (m x n) ~ U diag(sigma) V^T with U m x k (ldu >= m), sigma k entries,
  * V n x k (ldv >= n), all in dtype dt.  l = k + p <= min(m, n); q >= 0 is the

@@ -77,6 +77,15 @@ def lib():
             "rmm_nystrom_workspace": [_vp, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_nystrom": [_vp, _i64, _i64, _vp, _i64, ctypes.c_double, _i64, _i64, _u64, _vp, _vp,
                             _i64, _vp, _i64, _vp, _vp],
+            "rmm_sketch_batch_workspace": [_vp, _i32, _i32, _i64, _vp, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_sketch_batch": [_vp, _i32, _i32, _i64, _vp],
+            "rmm_sched_create": [ctypes.c_size_t, ctypes.POINTER(_vp)],
+            "rmm_sched_destroy": [_vp],
+            "rmm_sched_submit": [_vp, _i64, ctypes.c_size_t],
+            "rmm_sched_admit": [_vp, _i64, _vp, ctypes.POINTER(_i64)],
+            "rmm_sched_complete": [_vp, _i64],
+            "rmm_sched_stats": [_vp, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_i64),
+                                ctypes.POINTER(_i64)],
             "rmm_sketch_hashes": [_vp, _i64, _i64, _u64, _vp],
             "rmm_sketch_signs": [_vp, _i32, _i64, _u64, _vp],
             "rmm_srht_indices": [_vp, _i64, _i64, _u64, _vp],
@@ -140,6 +149,59 @@ def _ptr(x):
     return None if x is None else ctypes.c_void_p(x.data_ptr())
 
 
+def _bptr(b, out):
+    """Pointer of the optional extra column.  NULL means "no column", so an
+    empty column (zero rows, no storage) is passed as a non-null pointer that
+    is never read (the output's)."""
+    if b is None:
+        return None
+    return ctypes.c_void_p(b.data_ptr() if b.numel() > 0 else out.data_ptr())
+
+
+class SketchDesc(ctypes.Structure):
+    """rmm_sketch_desc of the C ABI."""
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("A", ctypes.c_void_p),
+                ("lda", ctypes.c_int64), ("b", ctypes.c_void_p), ("s", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
+
+
+class Scheduler:
+    """First-come-first-served admission under a device-memory budget
+    (host-only; the rmm_sched_* calls of the C ABI)."""
+
+    def __init__(self, budget_bytes: int):
+        s = ctypes.c_void_p()
+        _check(lib().rmm_sched_create(ctypes.c_size_t(budget_bytes), ctypes.byref(s)), "rmm_sched_create")
+        self._s = s
+
+    def __del__(self):
+        try:
+            if self._s:
+                lib().rmm_sched_destroy(self._s)
+        except Exception:
+            pass
+
+    def submit(self, rid: int, nbytes: int):
+        _check(lib().rmm_sched_submit(self._s, rid, ctypes.c_size_t(nbytes)), "rmm_sched_submit")
+
+    def admit(self, max_ids: int = 1 << 16):
+        ids = (ctypes.c_int64 * max(1, max_ids))()
+        n = ctypes.c_int64()
+        _check(lib().rmm_sched_admit(self._s, max_ids, ids, ctypes.byref(n)), "rmm_sched_admit")
+        return list(ids[:n.value])
+
+    def complete(self, rid: int):
+        _check(lib().rmm_sched_complete(self._s, rid), "rmm_sched_complete")
+
+    def stats(self):
+        u = ctypes.c_size_t()
+        q = ctypes.c_int64()
+        r = ctypes.c_int64()
+        _check(lib().rmm_sched_stats(self._s, ctypes.byref(u), ctypes.byref(q), ctypes.byref(r)),
+               "rmm_sched_stats")
+        return {"in_use": u.value, "queued": q.value, "running": r.value}
+
+
 class Handle:
     """A library handle bound to one device, its stream and a workspace."""
 
@@ -150,6 +212,7 @@ class Handle:
         _check(lib().rmm_create(ctypes.byref(h), device.index or 0), "rmm_create")
         self._h = h
         self._ws = None
+        self._ws_streams = set()
 
     def __del__(self):
         try:
@@ -168,8 +231,14 @@ class Handle:
         """Bind the current torch stream and a workspace of >= nbytes."""
         stream = torch.cuda.current_stream(self.device)
         _check(lib().rmm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "rmm_set_stream")
+        if self._ws is not None and stream not in self._ws_streams:
+            # work on another stream uses the workspace: the allocator must not
+            # hand its memory out again before that work is done
+            self._ws.record_stream(stream)
+            self._ws_streams.add(stream)
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            self._ws_streams = {stream}
         _check(lib().rmm_set_workspace(self._h, _ptr(self._ws), self._ws.numel()),
                "rmm_set_workspace")
 
@@ -194,7 +263,7 @@ class Handle:
             out = torch.empty(ncols, s, dtype=A.dtype, device=A.device).t()
         ws = self.sketch_workspace(A.dtype, kind, m, ncols, s)
         self._prepare(ws)
-        _check(lib().rmm_sketch(self._h, _dt(A), _kind(kind), m, n, _ptr(A), _ld(A), _ptr(b), s,
+        _check(lib().rmm_sketch(self._h, _dt(A), _kind(kind), m, n, _ptr(A), _ld(A), _bptr(b, out), s,
                                 seed, _ptr(out), _ld(out)), "rmm_sketch")
         return out
 
@@ -286,6 +355,31 @@ class Handle:
         _check(lib().rmm_mixed_product(self._h, prec, mode, m, n, _ptr(A), _ld(A), _ptr(X), _ld(X), l,
                                        _ptr(out), _ld(out)), "rmm_mixed_product")
         return out
+
+    def sketch_batch(self, kind, problems, dtype=torch.float32):
+        """Sketches of several problems in one grouped call.
+
+        problems: list of (A, b or None, s, seed); returns the list of C_i
+        (s_i x n_i', column-major), each bitwise equal to sketch() alone."""
+        descs = (SketchDesc * max(1, len(problems)))()
+        outs, keep = [], []
+        for i, (A, b, s, seed) in enumerate(problems):
+            A = colmajor(A)
+            keep.append(A)
+            m, n = A.shape
+            ncols = n + (1 if b is not None else 0)
+            C = torch.empty(ncols, s, dtype=A.dtype, device=A.device).t()
+            outs.append(C)
+            bp = _bptr(b, C)
+            descs[i] = SketchDesc(m, n, A.data_ptr(), _ld(A), None if bp is None else bp.value, s, seed,
+                                  C.data_ptr(), _ld(C))
+        dt = F32 if dtype == torch.float32 else F64
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_sketch_batch_workspace(self._h, dt, _kind(kind), len(problems), descs,
+                                                ctypes.byref(ws)), "rmm_sketch_batch_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_sketch_batch(self._h, dt, _kind(kind), len(problems), descs), "rmm_sketch_batch")
+        return outs
 
     # ---- Nystrom --------------------------------------------------------------
     def nystrom(self, X: torch.Tensor, sigma: float, c: int, seed: int, k: int = None):

@@ -1,8 +1,9 @@
 """Build librmm.so (HIP, gfx950) in-tree.
 
-Every ``csrc/*.hip`` file is compiled with hipcc for gfx950 and linked into
-``paper_1505_07570_amd/librmm.so``.  Packed-fp32 instructions are disabled
-(``-packed-fp32-ops``).  Objects go to ``paper_1505_07570_amd/_build``.
+Every ``csrc/*.hip`` file is compiled with hipcc for gfx950 and every
+``csrc/*.cpp`` (host-only code: the request scheduler) with g++; all are
+linked into ``paper_1505_07570_amd/librmm.so``.  Packed-fp32 instructions are
+disabled (``-packed-fp32-ops``).  Objects go to ``paper_1505_07570_amd/_build``.
 """
 
 from __future__ import annotations
@@ -35,9 +36,15 @@ def hipcc() -> str:
     return p
 
 
+HOST_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
+    if src.endswith(".cpp"):
+        cmd = [shutil.which("g++") or "g++", *HOST_FLAGS, "-c", src, "-o", obj]
+    else:
+        cmd = [hipcc(), *FLAGS, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {src}\n{r.stdout}\n{r.stderr}")
@@ -46,7 +53,7 @@ def _compile(src: str) -> str:
 
 def build(jobs: int = None, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(8, os.cpu_count() or 1)
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, srcs))

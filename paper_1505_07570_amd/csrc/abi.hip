@@ -43,6 +43,50 @@ bool kind_ok(rmm_sketch_kind k) {
 
 }  // namespace
 
+namespace {
+
+int batch_args(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t count,
+               const rmm_sketch_desc* d) {
+  if (!h || !dt_ok(dt) || !kind_ok(kind) || count < 0 || (count > 0 && !d) || count >= (1 << 24))
+    return RMM_ERR_INVALID_ARG;
+  for (int64_t i = 0; i < count; ++i) {
+    const rmm_sketch_desc& q = d[i];
+    if (!sketch_dims_ok(q.m, q.n + 1, q.s)) return RMM_ERR_INVALID_ARG;
+    if ((q.n > 0 && q.m > 0 && !q.A) || !q.C || bad_ld(q.lda, q.m) || bad_ld(q.ldc, q.s))
+      return RMM_ERR_INVALID_ARG;
+    if (kind == RMM_SRHT && q.s > (1ll << ceil_log2((uint64_t)(q.m > 0 ? q.m : 1))))
+      return RMM_ERR_INVALID_ARG;
+  }
+  return RMM_OK;
+}
+
+template <typename T>
+size_t batch_ws(const rmm_ctx* h, rmm_sketch_kind kind, int count, const rmm_sketch_desc* d) {
+  if (kind == RMM_COUNTSKETCH && countsketch_batch_grouped<T>(count, d))
+    return countsketch_batch_workspace<T>(h, count, d);
+  size_t w = 0;
+  for (int i = 0; i < count; ++i) {
+    const size_t x = sketch_ws<T>(h, kind, d[i].m, (int)d[i].n + (d[i].b ? 1 : 0), d[i].s);
+    if (x > w) w = x;
+  }
+  return w;
+}
+
+template <typename T>
+int batch_run(rmm_ctx* h, rmm_sketch_kind kind, int count, const rmm_sketch_desc* d) {
+  Carver ws(h->ws, h->ws_bytes);
+  if (kind == RMM_COUNTSKETCH && countsketch_batch_grouped<T>(count, d))
+    return countsketch_batch_run<T>(h, count, d, ws);
+  for (int i = 0; i < count; ++i) {
+    Carver w1(h->ws, h->ws_bytes);
+    RMM_TRY(sketch_dispatch<T>(h, kind, d[i].m, (int)d[i].n, (const T*)d[i].A, d[i].lda,
+                               (const T*)d[i].b, d[i].s, d[i].seed, (T*)d[i].C, d[i].ldc, w1));
+  }
+  return RMM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int rmm_create(rmm_handle* h, int device) {
@@ -123,6 +167,22 @@ int rmm_sketch(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m, int6
                                   seed, (float*)C, ldc, ws);
   return sketch_dispatch<double>(h, kind, m, (int)n, (const double*)A, lda, (const double*)b, s,
                                  seed, (double*)C, ldc, ws);
+}
+
+int rmm_sketch_batch_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t count,
+                               const rmm_sketch_desc* descs, size_t* bytes) {
+  RMM_TRY(batch_args(h, dt, kind, count, descs));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  *bytes = dt == RMM_F32 ? batch_ws<float>(h, kind, (int)count, descs)
+                         : batch_ws<double>(h, kind, (int)count, descs);
+  return RMM_OK;
+}
+
+int rmm_sketch_batch(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t count,
+                     const rmm_sketch_desc* descs) {
+  RMM_TRY(batch_args(h, dt, kind, count, descs));
+  return dt == RMM_F32 ? batch_run<float>(h, kind, (int)count, descs)
+                       : batch_run<double>(h, kind, (int)count, descs);
 }
 
 int rmm_sketch_hashes(rmm_handle h, int64_t m, int64_t s, uint64_t seed, int32_t* out) {

@@ -7,6 +7,8 @@
 
 #include "../../include/rmm.h"
 
+#include <vector>
+
 struct rmm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -14,6 +16,7 @@ struct rmm_ctx {
   size_t ws_bytes = 0;
   int cus = 256;
   size_t lds_bytes = 65536;  // usable LDS per workgroup
+  std::vector<unsigned char> table_host;  // staging of the last batch descriptor table
 };
 
 namespace rmm {
@@ -101,6 +104,28 @@ __host__ __device__ __forceinline__ int64_t plan_worker(const PanelPlan& p, int6
 
 PanelPlan make_plan(int64_t m, int ncols, int width, int s, int ST, int64_t chunk, int G);
 inline int64_t plan_slots(const PanelPlan& p) { return (int64_t)p.G + (int64_t)p.P * p.BT; }
+
+// Output column j of the fixed-order reduction: C[r, j] = scale * (sum of
+// the slots of the contiguous run of workers that touched (panel, tile) of
+// row r, in increasing worker order, in fp64).
+template <typename T>
+__device__ __forceinline__ void panel_reduce_body(const PanelPlan& plan, const T* __restrict__ partials,
+                                                  double scale, T* __restrict__ C, int64_t ldc,
+                                                  int64_t j) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= plan.s || j >= plan.ncols) return;
+  const int p = (int)(((j + 1) * plan.P - 1) / plan.ncols);
+  const int bt = (int)(r / plan.ST);
+  const int64_t vp = (int64_t)p * plan.BT + bt;
+  const int64_t w = j - plan_col0(plan, p);
+  const int64_t rr = r - (int64_t)bt * plan.ST;
+  const int64_t lo = plan_worker(plan, vp * plan.nchunks);
+  const int64_t hi = plan_worker(plan, (vp + 1) * plan.nchunks - 1);
+  double acc = 0.0;
+  for (int64_t b = lo; b <= hi; ++b)
+    acc += (double)partials[(b + vp) * plan.slot_elems + w * plan.ST + rr];
+  C[r + j * ldc] = (T)(acc * scale);
+}
 
 // Fixed-order reduction of partial slots into C (scaled), see reduce.hip.
 template <typename T>

@@ -15,6 +15,9 @@
 //    before the hash generation so the loads are in flight meanwhile;
 //  * at a panel change the accumulators are flushed to a partial slot and a
 //    fixed-order reduction (reduce.hip) sums the slots into C.
+#include <cstring>
+#include <vector>
+
 #include "common.hpp"
 #include "rng.hpp"
 
@@ -175,10 +178,10 @@ __global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
 
 constexpr int kCsSchedMaxS = 1 << 14;
 
-__global__ __launch_bounds__(256) void cs_schedule_kernel(int64_t m, uint32_t s, uint64_t seed,
-                                                          uint16_t* __restrict__ table) {
+__device__ __forceinline__ void cs_schedule_body(int64_t m, uint32_t s, uint64_t seed,
+                                                 uint16_t* __restrict__ table, int64_t bx) {
   const int lane = threadIdx.x & 63;
-  const int64_t blk = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // 256-row block
+  const int64_t blk = bx * 4 + (threadIdx.x >> 6);  // 256-row block
   const int64_t row0 = blk * 256;
   if (row0 >= m) return;
   const Words4 w = philox_at((uint64_t)(row0 >> 2) + lane, TAG_COUNTSKETCH, 0, seed);
@@ -199,16 +202,22 @@ __global__ __launch_bounds__(256) void cs_schedule_kernel(int64_t m, uint32_t s,
     if (row + e < m) table[row + e] = o[e];
 }
 
+__global__ __launch_bounds__(256) void cs_schedule_kernel(int64_t m, uint32_t s, uint64_t seed,
+                                                          uint16_t* __restrict__ table) {
+  cs_schedule_body(m, s, seed, table, blockIdx.x);
+}
+
 // worker = one wave; unit = (column, 2048-row chunk); private LDS buckets
 template <typename T, bool VEC>
-__global__ __launch_bounds__(64) void countsketch_sched_kernel(
-    const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
-    const uint16_t* __restrict__ table, T* __restrict__ partials) {
+__device__ __forceinline__ void cs_sched_body(const T* __restrict__ A, int64_t lda,
+                                              const T* __restrict__ bcol, int n,
+                                              const PanelPlan& plan,
+                                              const uint16_t* __restrict__ table,
+                                              T* __restrict__ partials, int64_t wk) {
   constexpr int UN = 8;  // 8 x 4 rows per lane = 2048 rows per chunk
   extern __shared__ __align__(16) unsigned char smem[];
   T* acc = reinterpret_cast<T*>(smem);
   const int lane = threadIdx.x;
-  const int64_t wk = blockIdx.x;
   const int64_t u0 = plan_start(plan, wk);
   const int64_t u1 = plan_start(plan, wk + 1);
   const int s = plan.s;
@@ -291,6 +300,77 @@ __global__ __launch_bounds__(64) void countsketch_sched_kernel(
     T* dst = partials + (wk + cur) * plan.slot_elems;
     for (int i = lane; i < s; i += 64) dst[i] = acc[i];
   }
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(64) void countsketch_sched_kernel(
+    const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
+    const uint16_t* __restrict__ table, T* __restrict__ partials) {
+  cs_sched_body<T, VEC>(A, lda, bcol, n, plan, table, partials, blockIdx.x);
+}
+
+// ---- grouped execution over a descriptor table ----------------------------------------
+//
+// A batch of CountSketch problems of different shapes runs as one launch per
+// stage (schedule, scatter-add, reduction).  Each problem keeps exactly the
+// work partition of its solo call, so its result is bitwise identical to
+// rmm_sketch on it alone; the grids are the concatenation of the solo grids,
+// and a workgroup finds its problem by binary search over the prefix offsets.
+template <typename T>
+struct CsGroupDesc {
+  const T* A;
+  const T* b;
+  T* C;
+  uint16_t* table;
+  T* partials;
+  int64_t lda, ldc, m;
+  uint64_t seed;
+  int64_t sblk0;  // first schedule block of this problem
+  int64_t wk0;    // first scatter-add worker
+  int64_t col0;   // first reduction column
+  PanelPlan plan;
+  int n;          // columns of A (the optional b column comes after)
+  int vec;        // 16-byte loads allowed
+};
+
+template <typename T>
+__device__ __forceinline__ int group_find(const CsGroupDesc<T>* __restrict__ d, int count,
+                                          int64_t x, int which) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t start = which == 0 ? d[mid].sblk0 : which == 1 ? d[mid].wk0 : d[mid].col0;
+    if (start <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void cs_schedule_group_kernel(const CsGroupDesc<T>* __restrict__ d,
+                                                                int count) {
+  const int p = group_find(d, count, blockIdx.x, 0);
+  cs_schedule_body(d[p].m, (uint32_t)d[p].plan.s, d[p].seed, d[p].table,
+                   (int64_t)blockIdx.x - d[p].sblk0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void countsketch_group_kernel(const CsGroupDesc<T>* __restrict__ d,
+                                                               int count) {
+  const int p = group_find(d, count, blockIdx.x, 1);
+  const CsGroupDesc<T>& g = d[p];
+  const int64_t wk = (int64_t)blockIdx.x - g.wk0;
+  if (g.vec)
+    cs_sched_body<T, true>(g.A, g.lda, g.b, g.n, g.plan, g.table, g.partials, wk);
+  else
+    cs_sched_body<T, false>(g.A, g.lda, g.b, g.n, g.plan, g.table, g.partials, wk);
+}
+
+template <typename T>
+__global__ void panel_reduce_group_kernel(const CsGroupDesc<T>* __restrict__ d, int count) {
+  const int p = group_find(d, count, blockIdx.y, 2);
+  const CsGroupDesc<T>& g = d[p];
+  panel_reduce_body<T>(g.plan, g.partials, 1.0, g.C, g.ldc, (int64_t)blockIdx.y - g.col0);
 }
 
 namespace {
@@ -420,6 +500,118 @@ int countsketch_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const
   RMM_TRY(rc);
   return launch_panel_reduce<T>(plan, partials, 1.0, C, ldc, h->stream);
 }
+
+// ---- batch: host side ------------------------------------------------------------------
+
+namespace {
+
+// carve the per-problem buffers and fill the descriptor table (ws may have a
+// null base: size query)
+template <typename T>
+int cs_batch_layout(const rmm_ctx* h, int count, const rmm_sketch_desc* d, Carver& ws,
+                    std::vector<CsGroupDesc<T>>* out, int64_t* nsblk, int64_t* nwk, int64_t* ncol,
+                    int* max_s) {
+  int64_t sb = 0, wk = 0, col = 0;
+  int ms = 1;
+  for (int i = 0; i < count; ++i) {
+    const int ncols = (int)d[i].n + (d[i].b ? 1 : 0);
+    if (d[i].m == 0 || ncols == 0) continue;
+    const int s = (int)d[i].s;
+    const PanelPlan plan = cs_sched_plan<T>(h, d[i].m, ncols, s);
+    uint16_t* table = ws.take<uint16_t>((size_t)d[i].m);
+    T* partials = ws.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
+    if (out) {
+      CsGroupDesc<T> g{};
+      g.A = (const T*)d[i].A;
+      g.b = (const T*)d[i].b;
+      g.C = (T*)d[i].C;
+      g.table = table;
+      g.partials = partials;
+      g.lda = d[i].lda;
+      g.ldc = d[i].ldc;
+      g.m = d[i].m;
+      g.seed = d[i].seed;
+      g.sblk0 = sb;
+      g.wk0 = wk;
+      g.col0 = col;
+      g.plan = plan;
+      g.n = (int)d[i].n;
+      g.vec = ((uintptr_t)d[i].A % 16 == 0) && (d[i].lda % 4 == 0) &&
+              (d[i].b == nullptr || (uintptr_t)d[i].b % 16 == 0);
+      out->push_back(g);
+    }
+    sb += ((d[i].m + 255) / 256 + 3) / 4;
+    wk += plan.G;
+    col += ncols;
+    if (s > ms) ms = s;
+  }
+  *nsblk = sb;
+  *nwk = wk;
+  *ncol = col;
+  *max_s = ms;
+  return RMM_OK;
+}
+
+}  // namespace
+
+template <typename T>
+bool countsketch_batch_grouped(int count, const rmm_sketch_desc* d) {
+  for (int i = 0; i < count; ++i)
+    if (!cs_use_sched(d[i].s, sizeof(T))) return false;
+  return true;
+}
+
+template <typename T>
+size_t countsketch_batch_workspace(const rmm_ctx* h, int count, const rmm_sketch_desc* d) {
+  Carver c(nullptr, 0);
+  int64_t a, b, e;
+  int ms;
+  cs_batch_layout<T>(h, count, d, c, nullptr, &a, &b, &e, &ms);
+  c.take<CsGroupDesc<T>>((size_t)count + 1);
+  return c.off;
+}
+
+template <typename T>
+int countsketch_batch_run(rmm_ctx* h, int count, const rmm_sketch_desc* d, Carver& ws) {
+  std::vector<CsGroupDesc<T>> g;
+  g.reserve(count);
+  int64_t nsblk, nwk, ncol;
+  int ms;
+  RMM_TRY(cs_batch_layout<T>(h, count, d, ws, &g, &nsblk, &nwk, &ncol, &ms));
+  CsGroupDesc<T>* dd = ws.take<CsGroupDesc<T>>((size_t)count + 1);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  for (int i = 0; i < count; ++i) {
+    const int ncols = (int)d[i].n + (d[i].b ? 1 : 0);
+    if (d[i].m == 0 && ncols > 0)
+      RMM_TRY(launch_fill_zero<T>((T*)d[i].C, d[i].s, ncols, d[i].ldc, h->stream));
+  }
+  const int gc = (int)g.size();
+  if (gc == 0) return RMM_OK;
+  // the table is staged in the handle so the host bytes outlive the async copy
+  h->table_host.resize(sizeof(CsGroupDesc<T>) * gc);
+  std::memcpy(h->table_host.data(), g.data(), h->table_host.size());
+  RMM_HIP(hipMemcpyAsync(dd, h->table_host.data(), h->table_host.size(), hipMemcpyHostToDevice,
+                         h->stream));
+  hipLaunchKernelGGL(cs_schedule_group_kernel<T>, dim3((unsigned)nsblk), dim3(256), 0, h->stream, dd,
+                     gc);
+  RMM_TRY(launch_status());
+  const size_t lds = (size_t)ms * sizeof(T);
+  RMM_HIP(hipFuncSetAttribute((const void*)countsketch_group_kernel<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(countsketch_group_kernel<T>, dim3((unsigned)nwk), dim3(64), lds, h->stream, dd,
+                     gc);
+  RMM_TRY(launch_status());
+  hipLaunchKernelGGL(panel_reduce_group_kernel<T>, dim3((unsigned)((ms + 255) / 256), (unsigned)ncol),
+                     dim3(256), 0, h->stream, dd, gc);
+  return launch_status();
+}
+
+template bool countsketch_batch_grouped<float>(int, const rmm_sketch_desc*);
+template bool countsketch_batch_grouped<double>(int, const rmm_sketch_desc*);
+template size_t countsketch_batch_workspace<float>(const rmm_ctx*, int, const rmm_sketch_desc*);
+template size_t countsketch_batch_workspace<double>(const rmm_ctx*, int, const rmm_sketch_desc*);
+template int countsketch_batch_run<float>(rmm_ctx*, int, const rmm_sketch_desc*, Carver&);
+template int countsketch_batch_run<double>(rmm_ctx*, int, const rmm_sketch_desc*, Carver&);
 
 template size_t countsketch_workspace<float>(const rmm_ctx*, int64_t, int, int64_t);
 template size_t countsketch_workspace<double>(const rmm_ctx*, int64_t, int, int64_t);

@@ -23,6 +23,16 @@ template <typename T>
 int gauss_sketch_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b,
                      int64_t s, uint64_t seed, T* C, int64_t ldc, Carver& ws);
 
+// Batch of CountSketch problems (see rmm_sketch_batch): grouped launches when
+// every problem takes the scheduled path (s <= 16384), results bitwise equal
+// to the solo calls.
+template <typename T>
+bool countsketch_batch_grouped(int count, const rmm_sketch_desc* d);
+template <typename T>
+size_t countsketch_batch_workspace(const rmm_ctx* h, int count, const rmm_sketch_desc* d);
+template <typename T>
+int countsketch_batch_run(rmm_ctx* h, int count, const rmm_sketch_desc* d, Carver& ws);
+
 int launch_sample_indices_u32(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
                               uint32_t tag, uint64_t seed, uint32_t* out);
 int launch_sample_indices_i64(const rmm_ctx* h, uint64_t domain, int k, int64_t s,

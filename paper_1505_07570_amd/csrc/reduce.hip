@@ -31,20 +31,7 @@ PanelPlan make_plan(int64_t m, int ncols, int width, int s, int ST, int64_t chun
 template <typename T>
 __global__ void panel_reduce_kernel(PanelPlan plan, const T* __restrict__ partials,
                                     double scale, T* __restrict__ C, int64_t ldc) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t j = blockIdx.y;
-  if (r >= plan.s) return;
-  const int p = (int)(((j + 1) * plan.P - 1) / plan.ncols);
-  const int bt = (int)(r / plan.ST);
-  const int64_t vp = (int64_t)p * plan.BT + bt;
-  const int64_t w = j - plan_col0(plan, p);
-  const int64_t rr = r - (int64_t)bt * plan.ST;
-  const int64_t lo = plan_worker(plan, vp * plan.nchunks);
-  const int64_t hi = plan_worker(plan, (vp + 1) * plan.nchunks - 1);
-  double acc = 0.0;
-  for (int64_t b = lo; b <= hi; ++b)
-    acc += (double)partials[(b + vp) * plan.slot_elems + w * plan.ST + rr];
-  C[r + j * ldc] = (T)(acc * scale);
+  panel_reduce_body<T>(plan, partials, scale, C, ldc, blockIdx.y);
 }
 
 template <typename T>

@@ -194,3 +194,53 @@ def spectrum_matrix(seed: int, m: int, n: int, sigma, backend: str = "numpy", de
     if backend == "torch":
         return X.to(torch.float32).t().contiguous().t()
     return np.asfortranarray(X.astype(np.float32))
+
+
+def serving_mix(count: int = 10000, seed: int = None, m_range=(4096, 262144), n_range=(32, 512)):
+    """The request mix of the serving workload: half rsvd, half LSR, in a
+    shuffled order (numpy's Philox bit generator), m and n log-uniform.
+
+    Returns a list of dicts {kind, m, n, seed}.
+    """
+    seed = data_seed(5) if seed is None else seed
+    g = np.random.Generator(np.random.Philox(seed))
+    kinds = np.array(["rsvd"] * (count // 2) + ["lsr"] * (count - count // 2))
+    g.shuffle(kinds)
+    lm = g.uniform(np.log(m_range[0]), np.log(m_range[1]), count)
+    ln = g.uniform(np.log(n_range[0]), np.log(n_range[1]), count)
+    ms = np.floor(np.exp(lm)).astype(np.int64)
+    ns = np.floor(np.exp(ln)).astype(np.int64)
+    seeds = g.integers(1, 2 ** 62, count)
+    return [{"kind": str(k), "m": int(m), "n": int(n), "seed": int(s)}
+            for k, m, n, s in zip(kinds, ms, ns, seeds)]
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = None):
+    """Arrival times (seconds) of a Poisson process of the given rate."""
+    seed = data_seed(5) + 1 if seed is None else seed
+    g = np.random.Generator(np.random.Philox(seed))
+    return np.cumsum(g.exponential(1.0 / rate, count))
+
+
+def serving_request(req, device="cuda"):
+    """The request's matrix on the device, from its own seed.
+
+    A = G + (10 / sqrt(n)) X Y^T with G (m x n), X (m x k), Y (n x k)
+    Gaussian and k = max(1, n // 8) (a spike well above the noise edge);
+    LSR requests also get b = A x* + N(0, 1e-3) noise.  fp32, column-major.
+    Returns (A, b or None).
+    """
+    import torch
+    m, n = req["m"], req["n"]
+    k = max(1, n // 8)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(req["seed"]))
+    A = torch.randn(n, m, generator=gen, device=device, dtype=torch.float32).t()
+    X = torch.randn(m, k, generator=gen, device=device, dtype=torch.float32)
+    Y = torch.randn(n, k, generator=gen, device=device, dtype=torch.float32)
+    A.addmm_(X, Y.t(), alpha=10.0 / np.sqrt(n))
+    b = None
+    if req["kind"] == "lsr":
+        xs = torch.randn(n, generator=gen, device=device, dtype=torch.float32)
+        b = A @ xs + np.sqrt(1e-3) * torch.randn(m, generator=gen, device=device, dtype=torch.float32)
+    return A, b
