@@ -17,8 +17,9 @@ Prints one JSON line.  Extra keys: per-family sketch time and roofline,
 sketch-and-solve p50/p99 latency next to the plain FP64 normal-equation
 solve, rsvd solves/s on the 2048 x 512 fp64 problem, the 65536 x 8192 rsvd
 (sigma_i = 1/i) in fp32, BF16 and FP8 with its error against the known
-spectrum, and the CPU oracle timed on a bounded row sample of the same
-workload.
+spectrum, Nystrom on 200,000 points (c = 128), the serving workload
+(plain one-at-a-time against the grouped, budgeted server), and the CPU
+oracle timed on a bounded row sample of the same workload.
 """
 
 from __future__ import annotations
@@ -210,6 +211,80 @@ def rsvd_spectrum(h, reps, lat):
     return out
 
 
+def serving_leg(count, budget_scale=1.0):
+    """Serving workload: `count` requests (half rsvd, half CountSketch LSR,
+    m log-uniform in [4096, 262144], n in [32, 512], matrices generated on
+    the device from per-request seeds).  First the plain comparator (one
+    request at a time, same library calls) with all requests arriving at
+    once gives the saturation throughput; then both are run with Poisson
+    arrivals at that rate.  The memory budget is 200 GB scaled by
+    count / 10000 (the share of a 10,000-request run)."""
+    import numpy as np
+
+    import synth
+    from paper_1505_07570_amd import serve
+    reqs = synth.serving_mix(count)
+    make = synth.serving_request
+    # warm up workspaces and code paths
+    h0 = serve.Handle()
+    for q in reqs[:4]:
+        A, b = make(q)
+        serve._solve_one(h0, q, A, b)
+    import torch
+    torch.cuda.synchronize()
+    _, _, wall_sat = serve.run_plain(reqs, np.zeros(count), make)
+    rate = count / wall_sat
+    arrivals = synth.poisson_arrivals(count, rate)
+    _, lat_p, wall_p = serve.run_plain(reqs, arrivals, make)
+    budget = int(200e9 * count / 10000 * budget_scale)
+    srv = serve.Server(budget, streams=4)
+    _, lat_s, wall_s = srv.run(reqs, arrivals, make)
+    req_bytes = sum(4 * q["m"] * q["n"] for q in reqs)
+
+    def summary(lat, wall):
+        v = [lat[i] * 1e3 for i in sorted(lat)]
+        return {"p50_ms": serve.percentile(v, 50), "p99_ms": serve.percentile(v, 99),
+                "solves_per_s": len(v) / wall, "hbm_gbs_of_A": req_bytes / wall / 1e9}
+
+    return {"requests": count, "arrival_rate_per_s": rate, "budget_bytes": budget,
+            "peak_admitted_bytes": srv.peak_bytes, "rejected": len(srv.rejected),
+            "plain_one_at_a_time": summary(lat_p, wall_p), "served": summary(lat_s, wall_s),
+            "saturation_solves_per_s_plain": rate}
+
+
+def nystrom_leg(h, reps):
+    """Nystrom on 200,000 Gaussian-mixture points in 32 dimensions with the
+    largest supported column count c = 128 (k = 103): time and the relative
+    error of L L^T against K on 10^6 sampled entries."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1505_07570_amd import serve
+    n, c = 200000, 128
+    X, sigma = synth.gmm_points(n=n)
+    Xd = torch.from_numpy(X).cuda()
+    h.nystrom(Xd, sigma, c, synth.sketch_seed(4))
+    ts = []
+    for _ in range(reps):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        L, idx, C, ev, st = h.nystrom(Xd, sigma, c, synth.sketch_seed(4))
+        z.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(z))
+    g = np.random.default_rng(17)
+    i = torch.from_numpy(g.integers(0, n, 10 ** 6)).cuda()
+    j = torch.from_numpy(g.integers(0, n, 10 ** 6)).cuda()
+    Xi, Xj = Xd[i].double(), Xd[j].double()
+    K = torch.exp(-((Xi - Xj) ** 2).sum(1) / (2 * sigma * sigma))
+    A = (L[i].double() * L[j].double()).sum(1)
+    err = float(torch.linalg.vector_norm(K - A) / torch.linalg.vector_norm(K))
+    return {"n": n, "d": 32, "c": c, "k": L.shape[1], "p50_ms": serve.percentile(ts, 50),
+            "rel_err_LLt_vs_K_sampled_1e6": err, "status": int(st.item()),
+            "C_bytes": n * c * 4}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,8 +296,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip latency / rsvd side measurements")
     ap.add_argument("--rsvd-reps", type=int, default=5)
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--only-rsvd-spectrum", action="store_true",
                     help="run only the 65536 x 8192 rsvd leg (for profiling)")
+    ap.add_argument("--only-extras", action="store_true",
+                    help="run only the Nystrom and serving legs")
     ap.add_argument("--traffic-run", action="store_true",
                     help="run only the dispatches read by the FETCH_SIZE / WRITE_SIZE counter runs")
     ap.add_argument("--traffic-summarize", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -264,6 +342,10 @@ def main():
     h = rmm.handle()
     if args.only_rsvd_spectrum:
         print(json.dumps({"rsvd_65536x8192": rsvd_spectrum(h, args.rsvd_reps, lat)}), flush=True)
+        return
+    if args.only_extras:
+        print(json.dumps({"nystrom_200000x32_c128": nystrom_leg(h, args.rsvd_reps),
+                          "serving": serving_leg(args.serve_requests)}), flush=True)
         return
 
     kinds = [k.strip() for k in args.kinds.split(",") if k.strip()]
@@ -370,6 +452,9 @@ def main():
                                      "solves_per_s": 1e3 / float(np.mean(ts))}
         del A1d
         out["rsvd_65536x8192"] = rsvd_spectrum(h, args.rsvd_reps, lat)
+        out["nystrom_200000x32_c128"] = nystrom_leg(h, args.rsvd_reps)
+        if args.serve_requests > 0:
+            out["serving"] = serving_leg(args.serve_requests)
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(A, b, s, kinds, seed, args.cpu_rows)
