@@ -15,6 +15,7 @@
 //    before the hash generation so the loads are in flight meanwhile;
 //  * at a panel change the accumulators are flushed to a partial slot and a
 //    fixed-order reduction (reduce.hip) sums the slots into C.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -173,8 +174,11 @@ __global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
 // pre-pass records for every row its bucket, its sign and whether a lower
 // lane of its group has the same bucket.  The first lane of every bucket
 // does a plain LDS read-modify-write (those buckets are pairwise distinct);
-// the rare later lanes then add atomically, after it in program order.
-// Entry (16 bits): bits 0-13 bucket, bit 14 "not first", bit 15 sign.
+// the later lanes then add atomically, after it in program order.  (A second
+// plain read-modify-write pass for the later lanes measured slower than the
+// atomics: it adds a dependent LDS round trip per row group.)
+// Entry (16 bits): bits 0-13 bucket, bit 14 "not first", bit 15 sign.  Rows
+// past the end of A read 0x4000 (an atomic +0 into bucket 0).
 
 constexpr int kCsSchedMaxS = 1 << 14;
 
@@ -207,106 +211,189 @@ __global__ __launch_bounds__(256) void cs_schedule_kernel(int64_t m, uint32_t s,
   cs_schedule_body(m, s, seed, table, blockIdx.x);
 }
 
-// worker = one wave; unit = (column, 2048-row chunk); private LDS buckets
-template <typename T, bool VEC>
+// worker = one workgroup of WAVES waves; unit = (panel of WAVES columns,
+// 4096-row chunk).  Wave w owns column (panel start + w) and a private LDS
+// bucket array; the chunk's schedule entries are staged once into LDS and
+// shared by the WAVES columns (so the 2-byte table is read from memory once
+// per WAVES columns instead of once per column).  A and the next chunk's
+// table entries are loaded a unit ahead.
+// rows per chunk: 16 x 16-byte loads per lane in flight per unit
+template <typename T>
+constexpr int sched_chunk() {
+  return sizeof(T) == 4 ? 4096 : 2048;
+}
+
+template <typename T, bool VEC, int WAVES>
 __device__ __forceinline__ void cs_sched_body(const T* __restrict__ A, int64_t lda,
                                               const T* __restrict__ bcol, int n,
                                               const PanelPlan& plan,
                                               const uint16_t* __restrict__ table,
                                               T* __restrict__ partials, int64_t wk) {
-  constexpr int UN = 8;  // 8 x 4 rows per lane = 2048 rows per chunk
+  constexpr int kSchedChunk = sched_chunk<T>();
+  constexpr int UN = kSchedChunk / 256;  // UN x 4 rows per lane per chunk
+  constexpr int NT = 64 * WAVES;
   extern __shared__ __align__(16) unsigned char smem[];
+  const int s = plan.s;
   T* acc = reinterpret_cast<T*>(smem);
-  const int lane = threadIdx.x;
+  uint16_t* tls = reinterpret_cast<uint16_t*>(smem + (((size_t)WAVES * s * sizeof(T) + 15) & ~(size_t)15));
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  T* my = acc + (size_t)wave * s;
   const int64_t u0 = plan_start(plan, wk);
   const int64_t u1 = plan_start(plan, wk + 1);
-  const int s = plan.s;
-  for (int i = lane; i < s; i += 64) acc[i] = T(0);
+  const int64_t nch = plan.nchunks;
+  for (int i = tid; i < WAVES * s; i += NT) acc[i] = T(0);
 
-  auto load = [&](int64_t u, T v[UN][4], uint2 tb[UN]) {
-    const int64_t j = u / plan.nchunks;
-    const int64_t r0 = (u - j * plan.nchunks) * (256 * UN);
-    const T* col = j < n ? A + j * lda : bcol;
-    if (VEC && r0 + 256 * UN <= plan.m) {
+  // this wave's column of panel vp (nullptr when the panel is narrower)
+  auto column = [&](int64_t vp) -> const T* {
+    const int64_t j = plan_col0(plan, (int)vp) + wave;
+    if (j >= plan_col0(plan, (int)vp + 1)) return nullptr;
+    return j < n ? A + j * lda : bcol;
+  };
+  auto load_a = [&](const T* col, int64_t r0, T v[UN][4]) {
+    if (col == nullptr) return;
+    if (VEC && r0 + kSchedChunk <= plan.m) {
 #pragma unroll
       for (int k = 0; k < UN; ++k) {
-        const int64_t row = r0 + 256 * k + 4 * lane;
+        const T* p = col + r0 + 256 * k + 4 * lane;
         if constexpr (sizeof(T) == 4) {
-          const float4 x = *reinterpret_cast<const float4*>(col + row);
+          const float4 x = *reinterpret_cast<const float4*>(p);
           v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
         } else {
-          const double2 x = *reinterpret_cast<const double2*>(col + row);
-          const double2 y = *reinterpret_cast<const double2*>(col + row + 2);
+          const double2 x = *reinterpret_cast<const double2*>(p);
+          const double2 y = *reinterpret_cast<const double2*>(p + 2);
           v[k][0] = x.x; v[k][1] = x.y; v[k][2] = y.x; v[k][3] = y.y;
         }
-        tb[k] = *reinterpret_cast<const uint2*>(table + row);
       }
     } else {
 #pragma unroll
-      for (int k = 0; k < UN; ++k) {
-        uint32_t tw[2] = {0u, 0u};
+      for (int k = 0; k < UN; ++k)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int64_t row = r0 + 256 * k + 4 * lane + e;
-          const bool ok = row < plan.m;
-          v[k][e] = ok ? col[row] : T(0);
-          // rows past the end add +0 into bucket 0 through the atomic path
-          const uint32_t ent = ok ? (uint32_t)table[row] : 0x4000u;
-          tw[e >> 1] |= ent << (16 * (e & 1));
+          v[k][e] = row < plan.m ? col[row] : T(0);
         }
-        tb[k] = make_uint2(tw[0], tw[1]);
+    }
+  };
+  // the chunk's entries in groups of 8; rows past the end get 0x4000
+  constexpr int TG = kSchedChunk / 8;
+  constexpr int TPT = (TG + NT - 1) / NT;
+  auto load_t = [&](int64_t r0, uint4 tr[TPT]) {
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      const int g = tid + q * NT;
+      if (g >= TG) break;
+      const int64_t row = r0 + 8 * g;
+      if (row + 8 <= plan.m) {
+        tr[q] = *reinterpret_cast<const uint4*>(table + row);
+      } else {
+        uint32_t w4[4];
+#pragma unroll
+        for (int h2 = 0; h2 < 4; ++h2) {
+          const uint32_t lo = row + 2 * h2 < plan.m ? (uint32_t)table[row + 2 * h2] : 0x4000u;
+          const uint32_t hi = row + 2 * h2 + 1 < plan.m ? (uint32_t)table[row + 2 * h2 + 1] : 0x4000u;
+          w4[h2] = lo | (hi << 16);
+        }
+        tr[q] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
       }
+    }
+  };
+  auto store_t = [&](int buf, const uint4 tr[TPT]) {
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+      const int g = tid + q * NT;
+      if (g >= TG) break;
+      *reinterpret_cast<uint4*>(tls + buf * kSchedChunk + 8 * g) = tr[q];
     }
   };
 
   T v[UN][4], vn[UN][4];
-  uint2 tb[UN], tbn[UN];
-  int64_t cur = u0 < u1 ? u0 / plan.nchunks : -1;
-  if (u0 < u1) load(u0, v, tb);
+  uint4 tr[TPT];
+  // unit u = (panel vp, chunk c), advanced incrementally (no divisions in the loop)
+  int64_t vp = u0 / nch, c = u0 - (u0 / nch) * nch;
+  int64_t cur = u0 < u1 ? vp : -1;
+  const T* col = u0 < u1 ? column(vp) : nullptr;
+  int buf = 0;
+  if (u0 < u1) {
+    load_a(col, c * kSchedChunk, v);
+    load_t(c * kSchedChunk, tr);
+    store_t(0, tr);
+  }
+  __syncthreads();
   for (int64_t u = u0; u < u1; ++u) {
-    const int64_t j = u / plan.nchunks;
-    if (j != cur) {
-      T* dst = partials + (wk + cur) * plan.slot_elems;
+    if (vp != cur) {
+      T* dst = partials + (wk + cur) * plan.slot_elems + (size_t)wave * s;
       for (int i = lane; i < s; i += 64) {
-        dst[i] = acc[i];
-        acc[i] = T(0);
+        dst[i] = my[i];
+        my[i] = T(0);
       }
-      cur = j;
+      cur = vp;
     }
-    if (u + 1 < u1) load(u + 1, vn, tbn);
+    int64_t vpn = vp, cn = c + 1;
+    if (cn == nch) {
+      cn = 0;
+      ++vpn;
+    }
+    const bool more = u + 1 < u1;
+    const T* coln = col;
+    if (more) {
+      if (vpn != vp) coln = column(vpn);
+      load_a(coln, cn * kSchedChunk, vn);
+      load_t(cn * kSchedChunk, tr);
+    }
+    if (col != nullptr) {
+      const uint16_t* tb = tls + buf * kSchedChunk;
 #pragma unroll
-    for (int k = 0; k < UN; ++k) {
-      const uint32_t tw[2] = {tb[k].x, tb[k].y};
+      for (int k = 0; k < UN; ++k) {
+        const uint2 tk = *reinterpret_cast<const uint2*>(tb + 256 * k + 4 * lane);
+        const uint32_t tw[2] = {tk.x, tk.y};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const uint32_t ent = (tw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-        T* p = acc + (ent & 0x3FFFu);
-        const T x = apply_sign<T>(v[k][e], ent << 16);
-        const bool later = (ent & 0x4000u) != 0u;
-        if (!later) *p += x;
-        if (__builtin_amdgcn_ballot_w64(later)) {
-          if (later) atomicAdd(p, x);
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t ent = (tw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+          T* p = my + (ent & 0x3FFFu);
+          const T x = apply_sign<T>(v[k][e], ent << 16);
+          const bool later = (ent & 0x4000u) != 0u;
+          if (!later) *p += x;
+          if (__builtin_amdgcn_ballot_w64(later)) {
+            if (later) atomicAdd(p, x);
+          }
         }
       }
     }
+    if (more) store_t(buf ^ 1, tr);
+    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < UN; ++k) {
-      tb[k] = tbn[k];
+    for (int k = 0; k < UN; ++k)
 #pragma unroll
       for (int e = 0; e < 4; ++e) v[k][e] = vn[k][e];
-    }
+    buf ^= 1;
+    vp = vpn;
+    c = cn;
+    col = coln;
   }
   if (cur >= 0) {
-    T* dst = partials + (wk + cur) * plan.slot_elems;
-    for (int i = lane; i < s; i += 64) dst[i] = acc[i];
+    T* dst = partials + (wk + cur) * plan.slot_elems + (size_t)wave * s;
+    for (int i = lane; i < s; i += 64) dst[i] = my[i];
   }
 }
 
-template <typename T, bool VEC>
-__global__ __launch_bounds__(64) void countsketch_sched_kernel(
+template <typename T, bool VEC, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void countsketch_sched_kernel(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
     const uint16_t* __restrict__ table, T* __restrict__ partials) {
-  cs_sched_body<T, VEC>(A, lda, bcol, n, plan, table, partials, blockIdx.x);
+  cs_sched_body<T, VEC, WAVES>(A, lda, bcol, n, plan, table, partials, blockIdx.x);
+}
+
+// waves per workgroup of the scheduled kernel for sketch size s
+template <typename T>
+int cs_sched_waves(int64_t s) {
+  int w = 8;
+  while (w > 1 && (size_t)w * s * sizeof(T) + 2 * sched_chunk<T>() * 2 + 16 > 150 * 1024) w /= 2;
+  return w;
+}
+
+template <typename T>
+size_t cs_sched_lds(int64_t s, int waves) {
+  return (((size_t)waves * s * sizeof(T) + 15) & ~(size_t)15) + 2 * sched_chunk<T>() * sizeof(uint16_t);
 }
 
 // ---- grouped execution over a descriptor table ----------------------------------------
@@ -354,16 +441,17 @@ __global__ __launch_bounds__(256) void cs_schedule_group_kernel(const CsGroupDes
                    (int64_t)blockIdx.x - d[p].sblk0);
 }
 
-template <typename T>
-__global__ __launch_bounds__(64) void countsketch_group_kernel(const CsGroupDesc<T>* __restrict__ d,
-                                                               int count) {
-  const int p = group_find(d, count, blockIdx.x, 1);
+template <typename T, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void countsketch_group_kernel(
+    const CsGroupDesc<T>* __restrict__ d, int count, int64_t wk_base) {
+  const int64_t x = wk_base + blockIdx.x;
+  const int p = group_find(d, count, x, 1);
   const CsGroupDesc<T>& g = d[p];
-  const int64_t wk = (int64_t)blockIdx.x - g.wk0;
+  const int64_t wk = x - g.wk0;
   if (g.vec)
-    cs_sched_body<T, true>(g.A, g.lda, g.b, g.n, g.plan, g.table, g.partials, wk);
+    cs_sched_body<T, true, WAVES>(g.A, g.lda, g.b, g.n, g.plan, g.table, g.partials, wk);
   else
-    cs_sched_body<T, false>(g.A, g.lda, g.b, g.n, g.plan, g.table, g.partials, wk);
+    cs_sched_body<T, false, WAVES>(g.A, g.lda, g.b, g.n, g.plan, g.table, g.partials, wk);
 }
 
 template <typename T>
@@ -418,19 +506,41 @@ int launch_cs(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
 
 }  // namespace
 
-constexpr int kSchedChunk = 2048;
-
 bool cs_use_sched(int64_t s, size_t tsize) {
   return s <= kCsSchedMaxS && (size_t)s * tsize <= 64 * 1024;
 }
 
 template <typename T>
 PanelPlan cs_sched_plan(const rmm_ctx* h, int64_t m, int ncols, int s) {
-  const size_t lds = (size_t)s * sizeof(T);
-  int per_cu = (int)(160 * 1024 / (lds > 0 ? lds : 1));
-  if (per_cu > 16) per_cu = 16;
+  const int waves = cs_sched_waves<T>(s);
+  const size_t lds = cs_sched_lds<T>(s, waves);
+  int per_cu = (int)(160 * 1024 / lds);
+  if (per_cu > 8) per_cu = 8;
   if (per_cu < 1) per_cu = 1;
-  return make_plan(m, ncols, 1, s, s, kSchedChunk, h->cus * per_cu);
+  return make_plan(m, ncols, waves, s, s, sched_chunk<T>(), h->cus * per_cu);
+}
+
+template <typename T, bool VEC>
+int launch_cs_sched(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
+                    const PanelPlan& plan, const uint16_t* table, T* partials) {
+  const size_t lds = cs_sched_lds<T>(plan.s, plan.width);
+#define RMM_CSS_CASE(W)                                                                     \
+  case W: {                                                                                 \
+    auto kern = countsketch_sched_kernel<T, VEC, W>;                                        \
+    RMM_HIP(hipFuncSetAttribute((const void*)kern,                                          \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));     \
+    hipLaunchKernelGGL(kern, dim3(plan.G), dim3(64 * W), lds, h->stream, A, lda, b, n, plan, \
+                       table, partials);                                                    \
+    return launch_status();                                                                 \
+  }
+  switch (plan.width) {
+    RMM_CSS_CASE(1)
+    RMM_CSS_CASE(2)
+    RMM_CSS_CASE(4)
+    RMM_CSS_CASE(8)
+  }
+#undef RMM_CSS_CASE
+  return RMM_ERR_UNSUPPORTED;
 }
 
 template <typename T>
@@ -466,13 +576,9 @@ int countsketch_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const
     hipLaunchKernelGGL(cs_schedule_kernel, dim3((unsigned)((blocks256 + 3) / 4)), dim3(256), 0,
                        h->stream, m, (uint32_t)s, seed, table);
     RMM_TRY(launch_status());
-    const size_t lds = (size_t)s * sizeof(T);
-    auto kern = vecs ? countsketch_sched_kernel<T, true> : countsketch_sched_kernel<T, false>;
-    RMM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds));
-    hipLaunchKernelGGL(kern, dim3(plan.G), dim3(64), lds, h->stream, A, lda, b, n, plan, table,
-                       partials);
-    RMM_TRY(launch_status());
+    const int rc = vecs ? launch_cs_sched<T, true>(h, A, lda, b, n, plan, table, partials)
+                        : launch_cs_sched<T, false>(h, A, lda, b, n, plan, table, partials);
+    RMM_TRY(rc);
     return launch_panel_reduce<T>(plan, partials, 1.0, C, ldc, h->stream);
   }
   int waves, ST;
@@ -513,7 +619,13 @@ int cs_batch_layout(const rmm_ctx* h, int count, const rmm_sketch_desc* d, Carve
                     int* max_s) {
   int64_t sb = 0, wk = 0, col = 0;
   int ms = 1;
-  for (int i = 0; i < count; ++i) {
+  // problems of equal workgroup width are contiguous (one launch per width)
+  std::vector<int> order(count);
+  for (int i = 0; i < count; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return cs_sched_waves<T>(d[a].s) > cs_sched_waves<T>(d[b].s);
+  });
+  for (int i : order) {
     const int ncols = (int)d[i].n + (d[i].b ? 1 : 0);
     if (d[i].m == 0 || ncols == 0) continue;
     const int s = (int)d[i].s;
@@ -595,12 +707,40 @@ int countsketch_batch_run(rmm_ctx* h, int count, const rmm_sketch_desc* d, Carve
   hipLaunchKernelGGL(cs_schedule_group_kernel<T>, dim3((unsigned)nsblk), dim3(256), 0, h->stream, dd,
                      gc);
   RMM_TRY(launch_status());
-  const size_t lds = (size_t)ms * sizeof(T);
-  RMM_HIP(hipFuncSetAttribute((const void*)countsketch_group_kernel<T>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(countsketch_group_kernel<T>, dim3((unsigned)nwk), dim3(64), lds, h->stream, dd,
-                     gc);
-  RMM_TRY(launch_status());
+  // one scatter-add launch per workgroup width; problems of the same width
+  // are contiguous in the table (sorted by width on the host)
+  int i0 = 0;
+  while (i0 < gc) {
+    const int w = g[i0].plan.width;
+    int i1 = i0;
+    int s_max = 1;
+    while (i1 < gc && g[i1].plan.width == w) {
+      if (g[i1].plan.s > s_max) s_max = g[i1].plan.s;
+      ++i1;
+    }
+    const int64_t wk_lo = g[i0].wk0;
+    const int64_t wk_hi = (i1 < gc) ? g[i1].wk0 : nwk;
+    const size_t lds = cs_sched_lds<T>(s_max, w);
+#define RMM_CSG_CASE(W)                                                                       \
+  case W: {                                                                                   \
+    RMM_HIP(hipFuncSetAttribute((const void*)countsketch_group_kernel<T, W>,                  \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));       \
+    hipLaunchKernelGGL((countsketch_group_kernel<T, W>), dim3((unsigned)(wk_hi - wk_lo)),      \
+                       dim3(64 * W), lds, h->stream, dd + i0, i1 - i0, wk_lo);                \
+    break;                                                                                    \
+  }
+    switch (w) {
+      RMM_CSG_CASE(1)
+      RMM_CSG_CASE(2)
+      RMM_CSG_CASE(4)
+      RMM_CSG_CASE(8)
+      default:
+        return RMM_ERR_UNSUPPORTED;
+    }
+#undef RMM_CSG_CASE
+    RMM_TRY(launch_status());
+    i0 = i1;
+  }
   hipLaunchKernelGGL(panel_reduce_group_kernel<T>, dim3((unsigned)((ms + 255) / 256), (unsigned)ncol),
                      dim3(256), 0, h->stream, dd, gc);
   return launch_status();
