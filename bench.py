@@ -17,7 +17,7 @@ Prints one JSON line.  Extra keys: per-family sketch time and roofline,
 sketch-and-solve p50/p99 latency next to the plain FP64 normal-equation
 solve, rsvd solves/s on the 2048 x 512 fp64 problem, the 65536 x 8192 rsvd
 (sigma_i = 1/i) in fp32, BF16 and FP8 with its error against the known
-spectrum, Nystrom on 200,000 points (c = 128), the serving workload
+spectrum, Nystrom on 200,000 points (c = 1024), the serving workload
 (plain one-at-a-time against the grouped, budgeted server), and the CPU
 oracle timed on a bounded row sample of the same workload.
 """
@@ -253,15 +253,15 @@ def serving_leg(count, budget_scale=1.0):
 
 
 def nystrom_leg(h, reps):
-    """Nystrom on 200,000 Gaussian-mixture points in 32 dimensions with the
-    largest supported column count c = 128 (k = 103): time and the relative
-    error of L L^T against K on 10^6 sampled entries."""
+    """Nystrom on 200,000 Gaussian-mixture points in 32 dimensions with
+    c = 1024 sampled columns (k = 820): time and the relative error of L L^T
+    against K on 10^6 sampled entries."""
     import numpy as np
     import torch
 
     import synth
     from paper_1505_07570_amd import serve
-    n, c = 200000, 128
+    n, c = 200000, 1024
     X, sigma = synth.gmm_points(n=n)
     Xd = torch.from_numpy(X).cuda()
     h.nystrom(Xd, sigma, c, synth.sketch_seed(4))
@@ -344,7 +344,7 @@ def main():
         print(json.dumps({"rsvd_65536x8192": rsvd_spectrum(h, args.rsvd_reps, lat)}), flush=True)
         return
     if args.only_extras:
-        print(json.dumps({"nystrom_200000x32_c128": nystrom_leg(h, args.rsvd_reps),
+        print(json.dumps({"nystrom_200000x32_c1024": nystrom_leg(h, args.rsvd_reps),
                           "serving": serving_leg(args.serve_requests)}), flush=True)
         return
 
@@ -452,7 +452,7 @@ def main():
                                      "solves_per_s": 1e3 / float(np.mean(ts))}
         del A1d
         out["rsvd_65536x8192"] = rsvd_spectrum(h, args.rsvd_reps, lat)
-        out["nystrom_200000x32_c128"] = nystrom_leg(h, args.rsvd_reps)
+        out["nystrom_200000x32_c1024"] = nystrom_leg(h, args.rsvd_reps)
         if args.serve_requests > 0:
             out["serving"] = serving_leg(args.serve_requests)
 

@@ -208,7 +208,7 @@ int rmm_plain_lsr(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d,
  *   L (n x k fp32, ldl >= n)  C U_k Lam_k^{-1/2}, so that K ~ L L^T =
  *                     C W_k^+ C^T; eigenvalues <= c * 2^-52 * lambda_max give
  *                     zero columns
- * Requires 1 <= k <= c <= n; d <= 64 and c <= 128 (RMM_ERR_UNSUPPORTED
+ * Requires 1 <= k <= c <= n; d <= 64 and c <= 1024 (RMM_ERR_UNSUPPORTED
  * beyond).  status: RMM_STATUS_NOT_CONVERGED from the eigensolver. */
 int rmm_nystrom_workspace(rmm_handle h, int64_t n, int64_t d, int64_t c, int64_t k,
                           size_t* bytes);

@@ -326,7 +326,8 @@ bool kind_ok(rmm_sketch_kind k) { return k == RMM_GAUSSIAN || k == RMM_SRHT || k
 int rsvd_args(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t n, int64_t k,
               int64_t p) {
   if (!h || !dt_ok(dt) || m < 1 || n < 1 || k < 1 || p < 0) return RMM_ERR_INVALID_ARG;
-  if (k + p > (m < n ? m : n) || k + p > 128) return k + p > 128 ? RMM_ERR_UNSUPPORTED : RMM_ERR_INVALID_ARG;
+  if (k + p > (m < n ? m : n)) return RMM_ERR_INVALID_ARG;
+  if (k + p > 1024) return RMM_ERR_UNSUPPORTED;
   if (m >= (1ll << 31) || n >= (1ll << 31)) return RMM_ERR_UNSUPPORTED;
   if (prec != RMM_PREC_NATIVE && prec != RMM_PREC_BF16 && prec != RMM_PREC_FP8)
     return RMM_ERR_INVALID_ARG;

@@ -167,7 +167,7 @@ int nystrom_args(rmm_handle h, int64_t n, int64_t d, int64_t c, int64_t k, doubl
   if (!h || n < 1 || d < 1 || c < 1 || c > n || k < 1 || k > c || !(sigma > 0.0) ||
       !(sigma < 1e300))
     return RMM_ERR_INVALID_ARG;
-  if (d > kRbfMaxD || c > 128 || n >= (1ll << 31)) return RMM_ERR_UNSUPPORTED;
+  if (d > kRbfMaxD || c > 1024 || n >= (1ll << 31)) return RMM_ERR_UNSUPPORTED;
   return RMM_OK;
 }
 

@@ -59,6 +59,16 @@ def test_rsvd_shapes_fp64(h, m, n, k, p, q):
     check_rsvd(host(U), host(s), host(V), Ur, sr, Vr, 1e-12)
 
 
+def test_rsvd_large_sketch_fp64(h):
+    """l = k + p = 200 > 128: blocked Cholesky-inverse and the multi-workgroup
+    eigensolver; sigma_i = 0.97^i leaves a gap at every index."""
+    A, _, _, _ = synth.low_rank(21, 3000, 400, 400, decay=0.97)
+    U, s, V, st = h.rsvd(dev(A), 150, 50, 1, 17)
+    Ur, sr, Vr, _ = orsvd.rsvd(A, 150, 50, 1, 17, fp64=True)
+    assert int(st.item()) == 0
+    check_rsvd(host(U), host(s), host(V), Ur, sr, Vr, 1e-12)
+
+
 def test_rsvd_exact_recovery_rank_deficient(h):
     A, U0, sig0, V0 = synth.low_rank(7, 900, 300, 8, decay=0.7)
     U, s, V, st = h.rsvd(dev(A), 10, 4, 1, 5)
@@ -99,6 +109,9 @@ def test_rsvd_invalid(h):
     A = torch.zeros(10, 8, dtype=torch.float64, device="cuda")
     with pytest.raises(rmm.RmmError):
         h.rsvd(A, 6, 4, 0, 1)  # k + p > min(m, n)
+    B = torch.zeros(2000, 1100, dtype=torch.float64, device="cuda")
+    with pytest.raises(rmm.RmmError):
+        h.rsvd(B, 1000, 30, 0, 1)  # k + p > 1024: eigensolver limit
 
 
 # ---- least squares --------------------------------------------------------------------

@@ -42,7 +42,8 @@ def _check_L(L, Lo, Co, lam, k, c):
 
 
 @pytest.mark.parametrize("n,d,c,k", [(3000, 32, 100, None), (777, 3, 37, 37), (5000, 64, 128, 64),
-                                     (129, 7, 129 - 1, None)])
+                                     (129, 7, 129 - 1, None), (3000, 32, 301, None),
+                                     (6000, 32, 1024, 256)])
 def test_nystrom_parity(h, n, d, c, k):
     X, sigma = synth.gmm_points(seed=n + d, n=n, d=d, pairs=2000)
     Lo, So, Co, Wo, lamo = onys.nystrom(X, sigma, c, seed=41, k=k)
@@ -87,8 +88,9 @@ def test_nystrom_identity_on_sample(h):
 
 def test_nystrom_invalid(h):
     X = torch.zeros(100, 4, dtype=torch.float32, device="cuda")
+    Xb = torch.zeros(2000, 4, dtype=torch.float32, device="cuda")
     with pytest.raises(rmm.RmmError):
-        h.nystrom(X, 1.0, 129, 1)          # c > 128: eigensolver limit
+        h.nystrom(Xb, 1.0, 1025, 1)        # c > 1024: eigensolver limit
     with pytest.raises(rmm.RmmError):
         h.nystrom(X, 1.0, 10, 1, k=11)     # k > c
     with pytest.raises(rmm.RmmError):
