@@ -217,6 +217,19 @@ int rmm_nystrom(rmm_handle h, int64_t n, int64_t d, const float* X, int64_t ldx,
                 float* C, int64_t ldc, float* L, int64_t ldl, double* evals,
                 int32_t* status);
 
+/* Gaussian-projection variant of the Nystrom method (the W = S^T K S form of
+ * Sec. 6.4 with a Gaussian S): C = K Omega (n x c fp32, ldc >= n), Omega
+ * (n x c, i.i.d. N(0,1), stream tag 7) regenerated from the seed,
+ * W = Omega^T C (FP64), W = U Lam U^T, L = C U_k Lam_k^{-1/2} (n x k fp32,
+ * ldl >= n) with the same zero-eigenvalue cut as rmm_nystrom.  K is formed
+ * tile by tile only.  Same limits as rmm_nystrom. */
+int rmm_nystrom_gaussian_workspace(rmm_handle h, int64_t n, int64_t d, int64_t c,
+                                   int64_t k, size_t* bytes);
+int rmm_nystrom_gaussian(rmm_handle h, int64_t n, int64_t d, const float* X,
+                         int64_t ldx, double sigma, int64_t c, int64_t k, uint64_t seed,
+                         float* C, int64_t ldc, float* L, int64_t ldl, double* evals,
+                         int32_t* status);
+
 /* ---- mixed-precision product (test hook for the BF16 / FP8 passes of rsvd) --
  * A (m x n fp32, lda >= m) is quantized per column (scale = max |A_ij| / QMAX,
  * QMAX = 1 for BF16 and 448 for FP8 e4m3, round to nearest even) and the

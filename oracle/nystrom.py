@@ -28,10 +28,16 @@ from . import rng
 
 
 def rbf(X1, X2, sigma: float):
+    """K[i, j] = exp(-||x_i - y_j||^2 / (2 sigma^2)), evaluated in row blocks
+    (each entry independently; the blocks only bound the memory)."""
     X1 = np.asarray(X1, dtype=np.float64)
     X2 = np.asarray(X2, dtype=np.float64)
-    D2 = ((X1[:, None, :] - X2[None, :, :]) ** 2).sum(axis=2)
-    return np.exp(-D2 / (2.0 * sigma * sigma))
+    K = np.empty((X1.shape[0], X2.shape[0]))
+    step = max(1, (1 << 24) // max(1, X2.shape[0] * X1.shape[1]))
+    for i0 in range(0, X1.shape[0], step):
+        D2 = ((X1[i0:i0 + step, None, :] - X2[None, :, :]) ** 2).sum(axis=2)
+        K[i0:i0 + step] = np.exp(-D2 / (2.0 * sigma * sigma))
+    return K
 
 
 def default_rank(c: int) -> int:

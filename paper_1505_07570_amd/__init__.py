@@ -77,6 +77,9 @@ def lib():
             "rmm_nystrom_workspace": [_vp, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_nystrom": [_vp, _i64, _i64, _vp, _i64, ctypes.c_double, _i64, _i64, _u64, _vp, _vp,
                             _i64, _vp, _i64, _vp, _vp],
+            "rmm_nystrom_gaussian_workspace": [_vp, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_nystrom_gaussian": [_vp, _i64, _i64, _vp, _i64, ctypes.c_double, _i64, _i64, _u64, _vp,
+                                     _i64, _vp, _i64, _vp, _vp],
             "rmm_sketch_batch_workspace": [_vp, _i32, _i32, _i64, _vp, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_sketch_batch": [_vp, _i32, _i32, _i64, _vp],
             "rmm_sched_create": [ctypes.c_size_t, ctypes.POINTER(_vp)],
@@ -402,6 +405,25 @@ class Handle:
                                  _ptr(C), _ld(C), _ptr(L), _ld(L), _ptr(evals), _ptr(status)),
                "rmm_nystrom")
         return L, idx, C, evals, status
+
+    def nystrom_gaussian(self, X: torch.Tensor, sigma: float, c: int, seed: int, k: int = None):
+        """Gaussian-projection Nystrom: returns (L (n x k), C = K Omega (n x c), evals, status)."""
+        if X.dtype != torch.float32 or X.dim() != 2 or X.stride(1) != 1:
+            X = X.to(torch.float32).contiguous()
+        n, d = X.shape
+        k = int(math.ceil(0.8 * c)) if k is None else int(k)
+        C = torch.empty(c, n, dtype=torch.float32, device=X.device).t()
+        L = torch.empty(k, n, dtype=torch.float32, device=X.device).t()
+        evals = torch.empty(c, dtype=torch.float64, device=X.device)
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_nystrom_gaussian_workspace(self._h, n, d, c, k, ctypes.byref(ws)),
+               "rmm_nystrom_gaussian_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_nystrom_gaussian(self._h, n, d, _ptr(X), X.stride(0), float(sigma), c, k, seed,
+                                          _ptr(C), _ld(C), _ptr(L), _ld(L), _ptr(evals), _ptr(status)),
+               "rmm_nystrom_gaussian")
+        return L, C, evals, status
 
     # ---- random quantities ---------------------------------------------------
     def sketch_hashes(self, m: int, s: int, seed: int) -> torch.Tensor:

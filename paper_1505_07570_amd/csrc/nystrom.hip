@@ -26,9 +26,11 @@ constexpr int kRbfMaxD = 64;   // point dimension held in registers
 // all c columns in stages of kRbfCols sampled points, stored coordinate-major
 // so that one broadcast 16-byte LDS read serves four columns.  Writes are
 // coalesced along i.
+// Column j is point idx[j] of Y, or point col_base + j when idx is null.
 template <int D>
 __global__ __launch_bounds__(kRbfRows) void rbf_columns_kernel(int64_t n, int d, const float* __restrict__ X,
                                                                int64_t ldx, int c, const int64_t* __restrict__ idx,
+                                                               const float* __restrict__ Y, int64_t col_base,
                                                                float g, float* __restrict__ C, int64_t ldc) {
   __shared__ __align__(16) float ys[D][kRbfCols];
   __shared__ float xs[kRbfRows][D + 1];
@@ -43,7 +45,8 @@ __global__ __launch_bounds__(kRbfRows) void rbf_columns_kernel(int64_t n, int d,
     for (int e = threadIdx.x; e < kRbfCols * D; e += kRbfRows) {
       const int jj = e / D, k = e % D;
       const int j = j0 + jj;
-      ys[k][jj] = (j < c && k < d) ? X[idx[j] * ldx + k] : 0.0f;
+      const int64_t pt = idx ? idx[j < c ? j : 0] : col_base + j;  // sampled or contiguous points
+      ys[k][jj] = (j < c && k < d) ? Y[pt * ldx + k] : 0.0f;
     }
     __syncthreads();
     const int jn = (c - j0) < kRbfCols ? (c - j0) : kRbfCols;
@@ -102,6 +105,18 @@ __global__ void nystrom_scale_kernel(int c, int k, const double* __restrict__ la
 
 namespace {
 
+int launch_rbf(const rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, int c,
+               const int64_t* idx, const float* Y, int64_t col_base, double g, float* C, int64_t ldc) {
+  const unsigned blocks = (unsigned)((n + kRbfRows - 1) / kRbfRows);
+  if (d <= 32)
+    hipLaunchKernelGGL(rbf_columns_kernel<32>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n, d, X,
+                       ldx, c, idx, Y, col_base, (float)g, C, ldc);
+  else
+    hipLaunchKernelGGL(rbf_columns_kernel<kRbfMaxD>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n,
+                       d, X, ldx, c, idx, Y, col_base, (float)g, C, ldc);
+  return launch_status();
+}
+
 struct NysBufs {
   double* W;
   double* V;
@@ -138,17 +153,81 @@ int nystrom_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, doubl
   RMM_TRY(launch_sample_indices_i64(h, (uint64_t)n, ceil_log2((uint64_t)n), c, TAG_NYSTROM_SAMPLE,
                                     seed, idx));
   const double g = 1.0 / (2.0 * sigma * sigma);
-  const unsigned blocks = (unsigned)((n + kRbfRows - 1) / kRbfRows);
-  if (d <= 32)
-    hipLaunchKernelGGL(rbf_columns_kernel<32>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n, d, X,
-                       ldx, c, idx, (float)g, C, ldc);
-  else
-    hipLaunchKernelGGL(rbf_columns_kernel<kRbfMaxD>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n,
-                       d, X, ldx, c, idx, (float)g, C, ldc);
-  RMM_TRY(launch_status());
+  RMM_TRY(launch_rbf(h, n, d, X, ldx, c, idx, X, 0, g, C, ldc));
   hipLaunchKernelGGL(rbf_gram_f64_kernel, dim3((unsigned)((c + 127) / 128), (unsigned)c), dim3(128), 0,
                      h->stream, d, X, ldx, c, idx, g, b.W);
   RMM_TRY(launch_status());
+  RMM_TRY(jacobi_eig(h, c, b.W, c, evals, b.V, status, ws));
+  hipLaunchKernelGGL(nystrom_scale_kernel, dim3((unsigned)((c + 127) / 128), (unsigned)k), dim3(128), 0,
+                     h->stream, c, k, evals, b.V, b.F);
+  RMM_TRY(launch_status());
+  return gemm<float, double, double, float>(h, false, false, (int)n, k, c, C, ldc, b.F, c, 1.0, L, ldl,
+                                            ws);
+}
+
+// ---- Gaussian-projection variant: C = K Omega, W = Omega^T C ----------------------------
+//
+// K (n x n) exists only as tiles of at most kKRows x kKCols entries, written
+// by the RBF kernel into the workspace and multiplied into C by the MFMA
+// GEMM with accumulation (C += K_tile Omega[cols, :]).  Omega (n x c fp32,
+// stream tag 7) is generated once into the workspace.
+constexpr int64_t kKRows = 32768;
+constexpr int64_t kKCols = 8192;
+
+namespace {
+
+size_t nystrom_gauss_layout(const rmm_ctx* h, int64_t n, int c, int k, Carver& ws, float** Om,
+                            float** Kt, NysBufs* b) {
+  const int64_t br = n < kKRows ? n : kKRows, bc = n < kKCols ? n : kKCols;
+  float* o = ws.take<float>((size_t)n * c);
+  float* kt = ws.take<float>((size_t)br * bc);
+  double* W = ws.take<double>((size_t)c * c);
+  double* V = ws.take<double>((size_t)c * c);
+  double* F = ws.take<double>((size_t)c * k);
+  if (Om) *Om = o;
+  if (Kt) *Kt = kt;
+  if (b) *b = NysBufs{W, V, F};
+  size_t scratch = jacobi_workspace(c);
+  scratch = scratch > gemm_workspace<double>(h, (int)n, k, c) ? scratch : gemm_workspace<double>(h, (int)n, k, c);
+  const size_t g1 = gemm_workspace<float>(h, (int)br, c, bc);
+  const size_t g2 = gemm_workspace<double>(h, c, c, n);
+  scratch = scratch > g1 ? scratch : g1;
+  scratch = scratch > g2 ? scratch : g2;
+  return ws.off + scratch + 4 * kAlign;
+}
+
+}  // namespace
+
+size_t nystrom_gauss_workspace(const rmm_ctx* h, int64_t n, int c, int k) {
+  Carver ws(nullptr, 0);
+  return nystrom_gauss_layout(h, n, c, k, ws, nullptr, nullptr, nullptr);
+}
+
+int nystrom_gauss_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, double sigma, int c,
+                      int k, uint64_t seed, float* C, int64_t ldc, float* L, int64_t ldl, double* evals,
+                      int32_t* status) {
+  Carver ws(h->ws, h->ws_bytes);
+  NysBufs b;
+  float *Om, *Kt;
+  const size_t need = nystrom_gauss_layout(h, n, c, k, ws, &Om, &Kt, &b);
+  if (need > h->ws_bytes) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  RMM_TRY(zero_status(h, status));
+  RMM_TRY(launch_gaussian<float>(h, TAG_GAUSS_NYSTROM, n, c, seed, Om, n));
+  const double g = 1.0 / (2.0 * sigma * sigma);
+  const int64_t br = n < kKRows ? n : kKRows, bc = n < kKCols ? n : kKCols;
+  for (int64_t i0 = 0; i0 < n; i0 += br) {
+    const int64_t rows = (n - i0) < br ? (n - i0) : br;
+    for (int64_t l0 = 0; l0 < n; l0 += bc) {
+      const int64_t cols = (n - l0) < bc ? (n - l0) : bc;
+      // K[i0:i0+rows, l0:l0+cols] (rows x cols, ld rows)
+      RMM_TRY(launch_rbf(h, rows, d, X + i0 * ldx, ldx, (int)cols, nullptr, X, l0, g, Kt, rows));
+      // C[i0:, :] (+)= K_tile Omega[l0:l0+cols, :]
+      RMM_TRY((gemm<float, float, float, float>(h, false, false, (int)rows, c, cols, Kt, rows, Om + l0, n,
+                                                1.0, C + i0, ldc, ws, l0 == 0 ? 0.0 : 1.0)));
+    }
+  }
+  // W = Omega^T C (c x c, fp64)
+  RMM_TRY((gemm<float, float, double, double>(h, true, false, c, c, n, Om, n, C, ldc, 1.0, b.W, c, ws)));
   RMM_TRY(jacobi_eig(h, c, b.W, c, evals, b.V, status, ws));
   hipLaunchKernelGGL(nystrom_scale_kernel, dim3((unsigned)((c + 127) / 128), (unsigned)k), dim3(128), 0,
                      h->stream, c, k, evals, b.V, b.F);
@@ -190,6 +269,23 @@ int rmm_nystrom(rmm_handle h, int64_t n, int64_t d, const float* X, int64_t ldx,
   if (!X || !idx || !C || !L || !evals || ldx < d || ldc < n || ldl < n) return RMM_ERR_INVALID_ARG;
   return nystrom_run(h, n, (int)d, X, ldx, sigma, (int)c, (int)k, seed, idx, C, ldc, L, ldl, evals,
                      status);
+}
+
+int rmm_nystrom_gaussian_workspace(rmm_handle h, int64_t n, int64_t d, int64_t c, int64_t k,
+                                   size_t* bytes) {
+  RMM_TRY(nystrom_args(h, n, d, c, k, 1.0));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  *bytes = nystrom_gauss_workspace(h, n, (int)c, (int)k);
+  return RMM_OK;
+}
+
+int rmm_nystrom_gaussian(rmm_handle h, int64_t n, int64_t d, const float* X, int64_t ldx,
+                         double sigma, int64_t c, int64_t k, uint64_t seed, float* C, int64_t ldc,
+                         float* L, int64_t ldl, double* evals, int32_t* status) {
+  RMM_TRY(nystrom_args(h, n, d, c, k, sigma));
+  if (!X || !C || !L || !evals || ldx < d || ldc < n || ldl < n) return RMM_ERR_INVALID_ARG;
+  return nystrom_gauss_run(h, n, (int)d, X, ldx, sigma, (int)c, (int)k, seed, C, ldc, L, ldl, evals,
+                           status);
 }
 
 }  // extern "C"

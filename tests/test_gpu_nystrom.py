@@ -98,3 +98,21 @@ def test_nystrom_invalid(h):
     Xw = torch.zeros(100, 65, dtype=torch.float32, device="cuda")
     with pytest.raises(rmm.RmmError):
         h.nystrom(Xw, 1.0, 10, 1)          # d > 64
+
+
+@pytest.mark.parametrize("n,d,c,k", [(3000, 32, 64, 8), (9000, 8, 32, 6), (2500, 16, 200, 12)])
+def test_nystrom_gaussian_parity(h, n, d, c, k):
+    """C = K Omega and W = Omega^T C against the oracle (fp32 Omega on both
+    sides); W is formed from the fp32 C, so its eigenvalues carry C's
+    rounding (relative 1e-6 of lambda_max); L on the well separated top k."""
+    X, sigma = synth.gmm_points(seed=n + c, n=n, d=d, pairs=2000)
+    Lo, Om, Co, Wo, lamo = onys.nystrom_gaussian(X, sigma, c, 61, k=k, fp64=False)
+    L, C, ev, st = h.nystrom_gaussian(torch.from_numpy(X).cuda(), sigma, c, 61, k=k)
+    assert int(st.item()) == 0
+    assert rel(host(C), Co) < 1e-5
+    assert np.abs(host(ev) - lamo).max() <= 1e-5 * lamo[0]
+    gaps = -np.diff(lamo[:k + 1]) / lamo[0]
+    assert gaps.min() > 1e-3                   # the compared columns are well defined
+    # eigenvector perturbation: relative error of W (fp32 rounding of C,
+    # 64 * 2^-24 allowed) over the smallest relative gap
+    assert rel(_align(host(L), Lo), Lo) < 64 * 2.0 ** -24 / gaps.min() + 1e-6
