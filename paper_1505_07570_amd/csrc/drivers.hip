@@ -86,7 +86,7 @@ int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t ld
   size_t scratch = orth_scratch<T>(h, m, l);
   scratch = smax(scratch, orth_scratch<T>(h, n, l));
   scratch = smax(scratch, gemm_workspace<T>(h, (int)m, l, n));
-  scratch = smax(scratch, gemm_workspace<T>(h, (int)n, l, m));
+  scratch = smax(scratch, gauss_sketch_workspace<T>(h, m, (int)n, l));
   scratch = smax(scratch, gemm_workspace<double>(h, l, l, n));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, l));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, l));
@@ -104,13 +104,13 @@ int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t ld
   RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, l, n, A, lda, Om, n, 1.0, Y, m, ws)));
   RMM_TRY(orth<T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
   for (int t = 0; t < q; ++t) {
-    RMM_TRY((gemm<T, T, T, T>(h, true, false, (int)n, l, m, A, lda, Q, m, 1.0, Z, n, ws)));
+    RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Q, m, l, Z, n, ws));
     RMM_TRY(orth<T>(h, n, l, Z, n, Qz, n, ob, tau_n, status, ws));
     RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, l, n, A, lda, Qz, n, 1.0, Y, m, ws)));
     RMM_TRY(orth<T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
   }
   // projection: Z = A^T Q = B^T, and the small SVD of B through B B^T = Z^T Z
-  RMM_TRY((gemm<T, T, T, T>(h, true, false, (int)n, l, m, A, lda, Q, m, 1.0, Z, n, ws)));
+  RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Q, m, l, Z, n, ws));
   RMM_TRY((gemm<T, T, double, double>(h, true, false, l, l, n, Z, n, Z, n, 1.0, ob.G, l, ws)));
   RMM_TRY(jacobi_eig(h, l, ob.G, l, evals, Vr, status, ws));
   RMM_TRY(svd_from_eig<T>(h, l, k, evals, Vr, W, sigma));

@@ -52,10 +52,13 @@ __device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c) {
 __device__ __forceinline__ int mfma_row(float, int g, int v) { return 4 * g + v; }
 __device__ __forceinline__ int mfma_row(double, int g, int v) { return g + 4 * v; }
 
-template <typename T, int NT, bool VEC>
+// MAT: the left operand is a stored matrix Qm (m x s, column-major, ld ldq)
+// instead of generated Gaussians, i.e. the kernel computes Qm^T [A | b].
+template <typename T, int NT, bool VEC, bool MAT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gauss_sketch_kernel(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, int ncols,
-    int64_t m, int s, int64_t kchunk, uint32_t tag, uint64_t seed, T* __restrict__ partials) {
+    int64_t m, int s, int64_t kchunk, uint32_t tag, uint64_t seed, const T* __restrict__ Qm,
+    int64_t ldq, T* __restrict__ partials) {
   using Cfg = GaussCfg<T>;
   using acc_t = typename Cfg::acc_t;
   constexpr int KS = Cfg::KS;
@@ -130,6 +133,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     }
   };
+  // stored left operand: thread = (column c, 4 consecutive rows), 16-byte
+  // loads along a column when aligned
+  constexpr int QG = 128 * (KS / 4);         // (column, 4-row group) pairs per stage
+  constexpr int QPT = (QG + 255) / 256;
+  T qv[QPT][4];
+  auto load_q = [&](int64_t r0) {
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+      const int gi = tid + 256 * u;
+      const int c = gi / (KS / 4), kg = gi - c * (KS / 4);
+      const int64_t row = r0 + 4 * kg;
+      const int col = mblk + c;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) qv[u][e] = T(0);
+      if (gi < QG && col < s) {
+        const T* qc = Qm + (int64_t)col * ldq;
+        if (VEC && row + 4 <= k1) {
+          if constexpr (sizeof(T) == 4) {
+            const float4 x = *reinterpret_cast<const float4*>(qc + row);
+            qv[u][0] = x.x; qv[u][1] = x.y; qv[u][2] = x.z; qv[u][3] = x.w;
+          } else {
+            const double2 x = *reinterpret_cast<const double2*>(qc + row);
+            const double2 y = *reinterpret_cast<const double2*>(qc + row + 2);
+            qv[u][0] = x.x; qv[u][1] = x.y; qv[u][2] = y.x; qv[u][3] = y.y;
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (row + e < k1) qv[u][e] = qc[row + e];
+        }
+      }
+    }
+  };
+  auto store_q = [&](int b) {
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+      const int gi = tid + 256 * u;
+      if (gi < QG) {
+        const int c = gi / (KS / 4), kg = gi - c * (KS / 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) om[b][(4 * kg + e) * 128 + c] = qv[u][e];
+      }
+    }
+  };
   // Omega[r0 + k, mblk + c] for k < KS, c < 128, written to om[b][k * 128 + c]
   auto gen_omega = [&](int64_t r0, int b) {
 #pragma unroll
@@ -163,7 +210,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int64_t nst = (k1 - k0 + KS - 1) / KS;
   if (nst > 0) {
     load_stage(k0);
-    gen_omega(k0, 0);
+    if constexpr (MAT) {
+      load_q(k0);
+      store_q(0);
+    } else {
+      gen_omega(k0, 0);
+    }
     store_stage(0);
   }
   __syncthreads();
@@ -172,7 +224,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int b = (int)(st & 1);
     const int64_t r0 = k0 + st * KS;
     const bool more = st + 1 < nst;
-    if (more) load_stage(r0 + KS);
+    if (more) {
+      load_stage(r0 + KS);
+      if constexpr (MAT) load_q(r0 + KS);
+    }
 #pragma unroll
     for (int ks = 0; ks < KS / 4; ++ks) {
       const T a0 = om[b][(4 * ks + kk) * 128 + arow];
@@ -186,7 +241,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     }
     if (more) {
-      gen_omega(r0 + KS, b ^ 1);
+      if constexpr (MAT) store_q(b ^ 1);
+      else gen_omega(r0 + KS, b ^ 1);
       store_stage(b ^ 1);
     }
     __syncthreads();
@@ -205,7 +261,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
-template <typename T>
+// TRANS: write C^T (C[j + r * ldc]) instead of C
+template <typename T, bool TRANS>
 __global__ void splitk_reduce_kernel(const T* __restrict__ partials, int splits, int64_t plane,
                                      double scale, int s, T* __restrict__ C, int64_t ldc) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,7 +270,8 @@ __global__ void splitk_reduce_kernel(const T* __restrict__ partials, int splits,
   if (r >= s) return;
   double acc = 0.0;
   for (int p = 0; p < splits; ++p) acc += (double)partials[p * plane + j * s + r];
-  C[r + j * ldc] = (T)(acc * scale);
+  if (TRANS) C[j + r * ldc] = (T)(acc * scale);
+  else C[r + j * ldc] = (T)(acc * scale);
 }
 
 namespace {
@@ -253,15 +311,22 @@ GaussShape gauss_shape(const rmm_ctx* h, int64_t m, int ncols, int s) {
 
 template <typename T, int NT>
 int launch_gauss(const rmm_ctx* h, const GaussShape& g, const T* A, int64_t lda, const T* b,
-                 int n, int ncols, int64_t m, int s, uint32_t tag, uint64_t seed, T* partials) {
+                 int n, int ncols, int64_t m, int s, uint32_t tag, uint64_t seed, const T* Qm,
+                 int64_t ldq, T* partials) {
   dim3 grid((unsigned)g.mtiles, (unsigned)g.ntiles, (unsigned)g.splits);
-  const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) && (b == nullptr || (uintptr_t)b % 16 == 0);
-  if (vec)
-    hipLaunchKernelGGL((gauss_sketch_kernel<T, NT, true>), grid, dim3(256), 0, h->stream, A, lda, b,
-                       n, ncols, m, s, g.kchunk, tag, seed, partials);
-  else
-    hipLaunchKernelGGL((gauss_sketch_kernel<T, NT, false>), grid, dim3(256), 0, h->stream, A, lda, b,
-                       n, ncols, m, s, g.kchunk, tag, seed, partials);
+  bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) && (b == nullptr || (uintptr_t)b % 16 == 0);
+  if (Qm) vec = vec && ((uintptr_t)Qm % 16 == 0) && (ldq % 4 == 0);
+#define RMM_GS_LAUNCH(V, M)                                                                    \
+  hipLaunchKernelGGL((gauss_sketch_kernel<T, NT, V, M>), grid, dim3(256), 0, h->stream, A, lda, b, \
+                     n, ncols, m, s, g.kchunk, tag, seed, Qm, ldq, partials)
+  if (Qm) {
+    if (vec) RMM_GS_LAUNCH(true, true);
+    else RMM_GS_LAUNCH(false, true);
+  } else {
+    if (vec) RMM_GS_LAUNCH(true, false);
+    else RMM_GS_LAUNCH(false, false);
+  }
+#undef RMM_GS_LAUNCH
   return launch_status();
 }
 
@@ -275,34 +340,61 @@ size_t gauss_sketch_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s)
   return c.off;
 }
 
-// Y (s x ncols) = Omega^T [A | b] * scale with Omega of stream `tag`.
+namespace {
+
+// C (s x ncols, or its transpose) = scale * L^T [A | b], L = Qm (m x s) when
+// given, else Omega of stream `tag`.
 template <typename T>
-int gauss_project(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b,
-                  int64_t s, uint32_t tag, uint64_t seed, double scale, T* C, int64_t ldc,
-                  Carver& ws) {
+int project_any(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b, int64_t s,
+                uint32_t tag, uint64_t seed, const T* Qm, int64_t ldq, double scale, T* C,
+                int64_t ldc, bool trans, Carver& ws) {
   const int ncols = n + (b ? 1 : 0);
   if (ncols == 0) return RMM_OK;
   if (m == 0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
   const GaussShape g = gauss_shape<T>(h, m, ncols, (int)s);
+  const size_t mark = ws.off;  // the partials are released on return
   T* partials = ws.take<T>((size_t)g.splits * ncols * s);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
   int rc;
   switch (g.NT) {
     case 17:
       if constexpr (sizeof(T) == 4) {
-        rc = launch_gauss<T, 17>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials);
+        rc = launch_gauss<T, 17>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, Qm, ldq, partials);
         break;
       }
       return RMM_ERR_UNSUPPORTED;
-    case 8: rc = launch_gauss<T, 8>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials); break;
-    case 4: rc = launch_gauss<T, 4>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials); break;
-    default: rc = launch_gauss<T, 1>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, partials); break;
+    case 8: rc = launch_gauss<T, 8>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, Qm, ldq, partials); break;
+    case 4: rc = launch_gauss<T, 4>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, Qm, ldq, partials); break;
+    default: rc = launch_gauss<T, 1>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, Qm, ldq, partials); break;
   }
   RMM_TRY(rc);
   dim3 grid((unsigned)((s + 255) / 256), (unsigned)ncols);
-  hipLaunchKernelGGL(splitk_reduce_kernel<T>, grid, dim3(256), 0, h->stream, partials, g.splits,
-                     (int64_t)ncols * s, scale, (int)s, C, ldc);
+  if (trans)
+    hipLaunchKernelGGL((splitk_reduce_kernel<T, true>), grid, dim3(256), 0, h->stream, partials, g.splits,
+                       (int64_t)ncols * s, scale, (int)s, C, ldc);
+  else
+    hipLaunchKernelGGL((splitk_reduce_kernel<T, false>), grid, dim3(256), 0, h->stream, partials, g.splits,
+                       (int64_t)ncols * s, scale, (int)s, C, ldc);
+  ws.off = mark;
   return launch_status();
+}
+
+}  // namespace
+
+// Y (s x ncols) = Omega^T [A | b] * scale with Omega of stream `tag`.
+template <typename T>
+int gauss_project(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b,
+                  int64_t s, uint32_t tag, uint64_t seed, double scale, T* C, int64_t ldc,
+                  Carver& ws) {
+  return project_any<T>(h, m, n, A, lda, b, s, tag, seed, nullptr, 0, scale, C, ldc, false, ws);
+}
+
+// Z (ncols x s, ld ldz) = A^T Qm for A (m x ncols) and Qm (m x s): the same
+// kernel with the stored matrix as its left operand, written transposed.
+template <typename T>
+int project_tn(rmm_ctx* h, int64_t m, int ncols, const T* A, int64_t lda, const T* Qm, int64_t ldq,
+               int64_t s, T* Z, int64_t ldz, Carver& ws) {
+  return project_any<T>(h, m, ncols, A, lda, nullptr, s, 0, 0, Qm, ldq, 1.0, Z, ldz, true, ws);
 }
 
 template <typename T>
@@ -318,6 +410,10 @@ template int gauss_sketch_run<float>(rmm_ctx*, int64_t, int, const float*, int64
                                      int64_t, uint64_t, float*, int64_t, Carver&);
 template int gauss_sketch_run<double>(rmm_ctx*, int64_t, int, const double*, int64_t,
                                       const double*, int64_t, uint64_t, double*, int64_t, Carver&);
+template int project_tn<float>(rmm_ctx*, int64_t, int, const float*, int64_t, const float*, int64_t,
+                               int64_t, float*, int64_t, Carver&);
+template int project_tn<double>(rmm_ctx*, int64_t, int, const double*, int64_t, const double*, int64_t,
+                                int64_t, double*, int64_t, Carver&);
 template int gauss_project<float>(rmm_ctx*, int64_t, int, const float*, int64_t, const float*,
                                   int64_t, uint32_t, uint64_t, double, float*, int64_t, Carver&);
 template int gauss_project<double>(rmm_ctx*, int64_t, int, const double*, int64_t, const double*,

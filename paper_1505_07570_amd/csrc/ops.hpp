@@ -33,6 +33,18 @@ size_t countsketch_batch_workspace(const rmm_ctx* h, int count, const rmm_sketch
 template <typename T>
 int countsketch_batch_run(rmm_ctx* h, int count, const rmm_sketch_desc* d, Carver& ws);
 
+// C = scale * Omega^T [A | b] with Omega of stream `tag` (the Gaussian-sketch
+// kernel with another stream and scale); workspace gauss_sketch_workspace.
+template <typename T>
+int gauss_project(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b,
+                  int64_t s, uint32_t tag, uint64_t seed, double scale, T* C, int64_t ldc,
+                  Carver& ws);
+// Z (ncols x s, ld ldz) = A^T Qm (A m x ncols, Qm m x s): the same kernel with a
+// stored left operand; workspace gauss_sketch_workspace<T>(h, m, ncols, s).
+template <typename T>
+int project_tn(rmm_ctx* h, int64_t m, int ncols, const T* A, int64_t lda, const T* Qm, int64_t ldq,
+               int64_t s, T* Z, int64_t ldz, Carver& ws);
+
 int launch_sample_indices_u32(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
                               uint32_t tag, uint64_t seed, uint32_t* out);
 int launch_sample_indices_i64(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
