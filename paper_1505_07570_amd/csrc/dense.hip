@@ -8,6 +8,8 @@
 //  * the K dimension is split over gridDim.z; each split writes a partial
 //    tile and a fixed-order reduction adds them in fp64 and converts to the
 //    output type, so results do not depend on scheduling.
+#include <type_traits>
+
 #include "common.hpp"
 #include "dense.hpp"
 
@@ -113,6 +115,134 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int64_t K, cons
     }
 }
 
+// Fast path for C = A B (no transposes, inputs already in the compute type,
+// 16-byte aligned columns): 128 x 128 tiles, 4 waves of 64 x 64, operands
+// staged with 16-byte loads (A along its columns, B along k) one stage ahead
+// in registers, double-buffered LDS, one barrier per 16-wide K stage.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_nn_kernel(int M, int N, int64_t K, const T* __restrict__ A,
+                                                      int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                                      T* __restrict__ P, int64_t kchunk) {
+  using F = Mfma<T>;
+  using acc_t = typename F::acc;
+  constexpr int BM = 128, BN = 128, BK = kBK;
+  constexpr int V = 16 / (int)sizeof(T);        // elements per 16-byte load
+  constexpr int AL = BM * BK / V / 256;          // A loads per thread per stage
+  constexpr int BL = BN * BK / V / 256;          // B loads per thread per stage
+  __shared__ __align__(16) T As[2][BK][BM + 4];
+  __shared__ __align__(16) T Bs[2][BK][BN + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+  int64_t k1 = k0 + kchunk;
+  if (k1 > K) k1 = K;
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  T ra[AL][V], rb[BL][V];
+  auto load = [&](int64_t kb) {
+    const bool fa = (m0 + BM <= M) && (kb + BK <= k1);
+    const bool fb = (n0 + BN <= N) && (kb + BK <= k1);
+#pragma unroll
+    for (int u = 0; u < AL; ++u) {
+      const int e = tid + 256 * u;             // (k, i-group)
+      const int kk = e / (BM / V), ig = e % (BM / V);
+      const int64_t gk = kb + kk;
+      const int64_t gi = m0 + ig * V;
+      if (fa) {
+        const T* src = A + gi + gk * lda;
+        if constexpr (sizeof(T) == 4) {
+          const float4 x = *reinterpret_cast<const float4*>(src);
+          ra[u][0] = x.x; ra[u][1] = x.y; ra[u][2] = x.z; ra[u][3] = x.w;
+        } else {
+          const double2 x = *reinterpret_cast<const double2*>(src);
+          ra[u][0] = x.x; ra[u][1] = x.y;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) ra[u][v] = (gi + v < M && gk < k1) ? A[gi + v + gk * lda] : T(0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < BL; ++u) {
+      const int e = tid + 256 * u;             // (j, k-group)
+      const int j = e / (BK / V), kg = e % (BK / V);
+      const int64_t gj = n0 + j;
+      const int64_t gk = kb + kg * V;
+      if (fb) {
+        const T* src = B + gk + gj * ldb;
+        if constexpr (sizeof(T) == 4) {
+          const float4 x = *reinterpret_cast<const float4*>(src);
+          rb[u][0] = x.x; rb[u][1] = x.y; rb[u][2] = x.z; rb[u][3] = x.w;
+        } else {
+          const double2 x = *reinterpret_cast<const double2*>(src);
+          rb[u][0] = x.x; rb[u][1] = x.y;
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) rb[u][v] = (gj < N && gk + v < k1) ? B[gk + v + gj * ldb] : T(0);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < AL; ++u) {
+      const int e = tid + 256 * u;
+      const int kk = e / (BM / V), ig = e % (BM / V);
+#pragma unroll
+      for (int v = 0; v < V; ++v) As[buf][kk][ig * V + v] = ra[u][v];
+    }
+#pragma unroll
+    for (int u = 0; u < BL; ++u) {
+      const int e = tid + 256 * u;
+      const int j = e / (BK / V), kg = e % (BK / V);
+#pragma unroll
+      for (int v = 0; v < V; ++v) Bs[buf][kg * V + v][j] = rb[u][v];
+    }
+  };
+  const int g = lane >> 4, c16 = lane & 15;
+  const int64_t nst = (k1 - k0 + BK - 1) / BK;
+  if (nst > 0) {
+    load(k0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nst; ++st) {
+    const int buf = (int)(st & 1);
+    const bool more = st + 1 < nst;
+    if (more) load(k0 + (st + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) av[a] = As[buf][ks + g][wm * 64 + a * 16 + c16];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[buf][ks + g][wn * 64 + b * 16 + c16];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = F::run(av[a], bv[b], acc[a][b]);
+    }
+    if (more) store(buf ^ 1);
+    __syncthreads();
+  }
+  T* dst = P + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int j = n0 + wn * 64 + b * 16 + c16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = m0 + wm * 64 + a * 16 + F::row(g, v);
+        if (i < M && j < N) dst[i + (int64_t)j * M] = acc[a][b][v];
+      }
+    }
+}
+
 template <typename TC, typename TO>
 __global__ void gemm_reduce_kernel(int M, int N, const TC* __restrict__ P, int splits, double alpha,
                                    double beta, TO* __restrict__ C, int64_t ldc) {
@@ -183,6 +313,22 @@ int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, in
   TC* P = ws.take<TC>((size_t)g.splits * M * N);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
   int rc;
+  constexpr bool same = std::is_same<TAI, TC>::value && std::is_same<TBI, TC>::value;
+  const int64_t va = 16 / sizeof(TC);
+  if constexpr (same) {
+    if (!ta && !tb && N > 64 && (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 && lda % va == 0 &&
+        ldb % va == 0) {
+      dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 127) / 128), (unsigned)g.splits);
+      hipLaunchKernelGGL((gemm_nn_kernel<TC>), grid, dim3(256), 0, h->stream, M, N, K,
+                         (const TC*)A, lda, (const TC*)B, ldb, P, g.kchunk);
+      RMM_TRY(launch_status());
+      dim3 rgrid((unsigned)((M + 255) / 256), (unsigned)N);
+      hipLaunchKernelGGL((gemm_reduce_kernel<TC, TO>), rgrid, dim3(256), 0, h->stream, M, N, P,
+                         g.splits, alpha, beta, C, ldc);
+      ws.off = mark;
+      return launch_status();
+    }
+  }
   if (!ta && !tb) rc = launch_gemm_t<TAI, TBI, TC, false, false>(h, g, M, N, K, A, lda, B, ldb, P);
   else if (ta && !tb) rc = launch_gemm_t<TAI, TBI, TC, true, false>(h, g, M, N, K, A, lda, B, ldb, P);
   else if (!ta && tb) rc = launch_gemm_t<TAI, TBI, TC, false, true>(h, g, M, N, K, A, lda, B, ldb, P);
