@@ -59,14 +59,31 @@ __device__ __forceinline__ floatx4 qmfma<Fp8Fmt>(uint64_t a, uint64_t b, floatx4
 
 // ---- quantization ----------------------------------------------------------------
 
-// sc[j] = max_i |A_ij| / QMAX (1 for an all-zero column); one workgroup per column
+// four values encoded and packed into consecutive elements (little-endian)
+template <typename F>
+__device__ __forceinline__ void enc4(const float v[4], typename F::store_t out[4]) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) out[e] = F::enc(v[e]);
+}
+
+// sc[j] = max_i |A_ij| / QMAX (1 for an all-zero column); one workgroup per
+// column, 16-byte loads when the column is aligned
 template <typename F>
 __global__ __launch_bounds__(256) void colscale_kernel(int64_t m, const float* __restrict__ A,
                                                        int64_t lda, float* __restrict__ sc) {
   __shared__ float red[256];
   const float* col = A + (int64_t)blockIdx.x * lda;
   float mx = 0.f;
-  for (int64_t i = threadIdx.x; i < m; i += 256) mx = fmaxf(mx, fabsf(col[i]));
+  int64_t i0 = 0;
+  if ((uintptr_t)col % 16 == 0) {
+    const int64_t m4 = m / 4 * 4;
+    for (int64_t i = 4 * (int64_t)threadIdx.x; i < m4; i += 1024) {
+      const float4 x = *reinterpret_cast<const float4*>(col + i);
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
+    }
+    i0 = m4;
+  }
+  for (int64_t i = i0 + threadIdx.x; i < m; i += 256) mx = fmaxf(mx, fabsf(col[i]));
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
@@ -76,8 +93,10 @@ __global__ __launch_bounds__(256) void colscale_kernel(int64_t m, const float* _
   if (threadIdx.x == 0) sc[blockIdx.x] = red[0] > 0.f ? red[0] / F::QMAX : 1.f;
 }
 
-// Aq (column-major, ld m) and Aq_t (row-major = n x m column-major, ld n) from a
-// 64 x 64 tile of A staged through LDS
+// Aq (column-major, ld ldq) and Aq_t (A^T column-major, ld ldqt) of a 64 x 64
+// tile of A.  Thread (tx, ty) loads rows 4 tx .. 4 tx + 3 of columns
+// ty + 16 r with 16-byte loads, writes them packed into Aq, and through an
+// LDS transpose writes 16 consecutive entries of one row of A into Aq_t.
 template <typename F>
 __global__ __launch_bounds__(256) void quantize_tile_kernel(int64_t m, int64_t n,
                                                             const float* __restrict__ A, int64_t lda,
@@ -87,20 +106,65 @@ __global__ __launch_bounds__(256) void quantize_tile_kernel(int64_t m, int64_t n
                                                             typename F::store_t* __restrict__ Aqt,
                                                             int64_t ldqt) {
   using S = typename F::store_t;
-  __shared__ S tile[64][65];
+  __shared__ __align__(16) S tile[64][64 + 16 / sizeof(S)];
   const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int jj = ty; jj < 64; jj += 4) {
-    const int64_t i = i0 + tx, j = j0 + jj;
-    S v = 0;
-    if (i < m && j < n) v = F::enc(A[i + j * lda] / sc[j]);
-    if (i < ldq && j < n) Aq[i + j * ldq] = v;  // rows m .. ldq-1 are zero padding
-    tile[jj][tx] = v;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const bool full = (i0 + 64 <= m) && (j0 + 64 <= n) && ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int jj = ty + 16 * r;
+    const int64_t j = j0 + jj, i = i0 + 4 * tx;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (full) {
+      const float4 x = *reinterpret_cast<const float4*>(A + i + j * lda);
+      const float s = sc[j];
+      v[0] = x.x / s; v[1] = x.y / s; v[2] = x.z / s; v[3] = x.w / s;
+    } else if (j < n) {
+      const float s = sc[j];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i + e < m) v[e] = A[i + e + j * lda] / s;
+    }
+    S q[4];
+    enc4<F>(v, q);
+    if (!full) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (!(i + e < m && j < n)) q[e] = (S)0;  // padding rows and columns are zero
+    }
+    if (i < ldq && j < n) {
+      if constexpr (sizeof(S) == 1) {
+        const uint32_t w = (uint32_t)q[0] | ((uint32_t)q[1] << 8) | ((uint32_t)q[2] << 16) | ((uint32_t)q[3] << 24);
+        *reinterpret_cast<uint32_t*>(Aq + i + j * ldq) = w;
+      } else {
+        const uint2 w = make_uint2((uint32_t)q[0] | ((uint32_t)q[1] << 16), (uint32_t)q[2] | ((uint32_t)q[3] << 16));
+        *reinterpret_cast<uint2*>(Aq + i + j * ldq) = w;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) tile[4 * tx + e][jj] = q[e];
   }
   __syncthreads();
-  for (int ii = ty; ii < 64; ii += 4) {
-    const int64_t i = i0 + ii, j = j0 + tx;
-    if (i < m && j < ldqt) Aqt[j + i * ldqt] = tile[tx][ii];
+  // row ii of the tile: 16 consecutive columns per thread
+  const int ii = threadIdx.x >> 2, jg = threadIdx.x & 3;
+  const int64_t i = i0 + ii, j = j0 + 16 * jg;
+  if (i < m && j < ldqt) {
+    S* dst = Aqt + j + i * ldqt;
+    const S* srcl = &tile[ii][16 * jg];
+    if constexpr (sizeof(S) == 1) {
+      uint32_t w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        w[q] = (uint32_t)srcl[4 * q] | ((uint32_t)srcl[4 * q + 1] << 8) | ((uint32_t)srcl[4 * q + 2] << 16) |
+               ((uint32_t)srcl[4 * q + 3] << 24);
+      *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+    } else {
+      uint32_t w[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) w[q] = (uint32_t)srcl[2 * q] | ((uint32_t)srcl[2 * q + 1] << 16);
+      *reinterpret_cast<uint4*>(dst) = make_uint4(w[0], w[1], w[2], w[3]);
+      *reinterpret_cast<uint4*>(dst + 8) = make_uint4(w[4], w[5], w[6], w[7]);
+    }
   }
 }
 
