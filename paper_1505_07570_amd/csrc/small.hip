@@ -262,9 +262,22 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
   const int rp = tid >> 5, w = tid & 31;
   int sweep = 0, rounds = 0;
   for (; sweep < max_sweeps; ++sweep) {
+    // a sweep rotates nothing exactly when no pair passes the rotation test
+    // now (the matrix cannot change before the first rotation), so the sweep
+    // that would only confirm convergence is replaced by this scan
     lds_barrier();
     if (tid == 0) done = 1;
     lds_barrier();
+    for (int e = tid; e < l * l; e += blockDim.x) {
+      const int a = e % l, b = e / l;
+      if (a < b) {
+        const double gpq = S[a + b * lds];
+        if (fabs(gpq) > abs_tol && fabs(gpq) > 0x1p-52 * sqrt(fabs(S[a + a * lds] * S[b + b * lds])))
+          done = 0;
+      }
+    }
+    lds_barrier();
+    if (done) break;
     for (int r = 0; r < L - 1; ++r, ++rounds) {
       // the log stores are not waited for at the barriers below
       if (tid < npairs) {
@@ -275,7 +288,6 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
           const double gpq = S[p + q * lds];
           const double gpp = S[p + p * lds], gqq = S[q + q * lds];
           if (fabs(gpq) > abs_tol && fabs(gpq) > 0x1p-52 * sqrt(fabs(gpp * gqq))) {
-            done = 0;
             const double theta = (gqq - gpp) / (2.0 * gpq);
             tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
             c = 1.0 / sqrt(tt * tt + 1.0);
@@ -350,7 +362,6 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
       }
       lds_barrier();
     }
-    if (done) break;
   }
   if (tid == 0) {
     *nrounds = rounds;
@@ -442,20 +453,20 @@ __global__ __launch_bounds__(256) void jacobi_vectors_kernel(int l, const double
 // each take a 32 x 32 tile of the (i <= j) pair grid, compute the rotations
 // of their tile's pairs from the matrix of the previous round (two buffers,
 // read one, write the other) and write every element of their blocks.
-// After each sweep a one-thread kernel decides convergence (a sweep without
-// rotations) and later launches return at once; the sweep's rotation log is
-// applied to the rows of V (row-major in the workspace) by a row-parallel
-// kernel.  A final kernel sorts the eigenvalues and writes V's columns.
+// Before each sweep a scan of the matrix decides convergence (no pair passes
+// the rotation test, i.e. the sweep would rotate nothing) and later launches
+// return at once; the sweep's rotation log is applied to the rows of V
+// (row-major in the workspace) by a row-parallel kernel.  A final kernel sorts the eigenvalues and writes V's columns.
 constexpr int kBigTile = 32;
 constexpr int kBigMaxL = 1024;
 constexpr int kBigMaxSweeps = 30;
 
 struct BigState {
   double abs_tol;  // 1e-17 * max |G_ii|, the absolute rotation threshold
-  int rotated;     // a rotation happened in the current sweep
-  int converged;   // a sweep without rotations has been seen
+  int pending;     // some pair of the current matrix passes the rotation test
+  int converged;   // no pair passes: the next sweep would rotate nothing
   int parity;      // buffer holding the current matrix
-  int sweeps;      // sweeps with rotations
+  int sweeps;      // sweeps run
 };
 
 __global__ void big_tol_kernel(int l, const double* __restrict__ G, int64_t ldg, BigState* st) {
@@ -509,10 +520,7 @@ __global__ __launch_bounds__(256) void big_round_kernel(int l, int L, int r, con
   const int tj = ti + rem;
   __shared__ double cs[2][kBigTile], sn[2][kBigTile], tn[2][kBigTile];
   __shared__ int pp[2][kBigTile], qq[2][kBigTile];
-  __shared__ int any;
   const int tid = threadIdx.x;
-  if (tid == 0) any = 0;
-  __syncthreads();
   if (tid < 2 * kBigTile) {
     const int side = tid / kBigTile, k = tid % kBigTile;
     const int pair = (side == 0 ? ti : tj) * kBigTile + k;
@@ -531,10 +539,7 @@ __global__ __launch_bounds__(256) void big_round_kernel(int l, int L, int r, con
           s = tt * c;
         }
       }
-      if (side == 0 && ti == tj) {
-        rlog[pair] = make_double2(c, s);
-        if (s != 0.0) any = 1;
-      }
+      if (side == 0 && ti == tj) rlog[pair] = make_double2(c, s);
     }
     pp[side][k] = p;
     qq[side][k] = q;
@@ -543,7 +548,6 @@ __global__ __launch_bounds__(256) void big_round_kernel(int l, int L, int r, con
     tn[side][k] = tt;
   }
   __syncthreads();
-  if (tid == 0 && any) atomicOr(&st->rotated, 1);
   if (blockIdx.x == 0 && tid == 0) st->parity = out_parity;
   for (int b = tid; b < kBigTile * kBigTile; b += blockDim.x) {
     const int ii = b / kBigTile, jj = b % kBigTile;
@@ -579,11 +583,28 @@ __global__ __launch_bounds__(256) void big_round_kernel(int l, int L, int r, con
   }
 }
 
-__global__ void big_sweep_end_kernel(BigState* st) {
+// pending |= some upper off-diagonal element of the current matrix passes the
+// rotation test (then the next sweep rotates something)
+__global__ void big_scan_kernel(int l, int L, const double* __restrict__ G0,
+                                const double* __restrict__ G1, BigState* st) {
   if (st->converged) return;
-  if (st->rotated == 0) st->converged = 1;
+  const double* G = st->parity ? G1 : G0;
+  const double abs_tol = st->abs_tol;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)l * l) return;
+  const int a = (int)(e % l), b = (int)(e / l);
+  if (a >= b) return;
+  const double gpq = G[a + (int64_t)b * L];
+  if (fabs(gpq) > abs_tol &&
+      fabs(gpq) > 0x1p-52 * sqrt(fabs(G[a + (int64_t)a * L] * G[b + (int64_t)b * L])))
+    atomicOr(&st->pending, 1);
+}
+
+__global__ void big_decide_kernel(BigState* st) {
+  if (st->converged) return;
+  if (st->pending == 0) st->converged = 1;
   else st->sweeps += 1;
-  st->rotated = 0;
+  st->pending = 0;
 }
 
 // Apply one sweep's logged rotations to rows of V (row-major L x L): wave =
@@ -594,7 +615,7 @@ __global__ __launch_bounds__(256) void big_vectors_kernel(int L, const double2* 
                                                           const uint16_t* __restrict__ ptab,
                                                           const uint16_t* __restrict__ qtab,
                                                           double* __restrict__ Vr, const BigState* st) {
-  if (st->converged) return;  // the sweep rotated nothing
+  if (st->converged) return;  // the sweep's rounds did not run
   extern __shared__ double vs[];  // 4 waves x kBigVecRows x L
   const int npairs = L / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -702,7 +723,12 @@ static int jacobi_eig_big(const rmm_ctx* h, int l, const double* G, int64_t ldg,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
   const unsigned vgroups = (unsigned)((L + 4 * kBigVecRows - 1) / (4 * kBigVecRows));
   int parity = 0;
-  for (int sweep = 0; sweep < kBigMaxSweeps; ++sweep) {
+  const unsigned sgroups = (unsigned)(((int64_t)l * l + 255) / 256);
+  for (int sweep = 0; sweep <= kBigMaxSweeps; ++sweep) {
+    hipLaunchKernelGGL(big_scan_kernel, dim3(sgroups), dim3(256), 0, h->stream, l, L, G0, G1, st);
+    hipLaunchKernelGGL(big_decide_kernel, dim3(1), dim3(1), 0, h->stream, st);
+    RMM_TRY(launch_status());
+    if (sweep == kBigMaxSweeps) break;  // the last scan only decides convergence
     for (int r = 0; r < L - 1; ++r) {
       const double* gin = parity ? G1 : G0;
       double* gout = parity ? G0 : G1;
@@ -711,7 +737,6 @@ static int jacobi_eig_big(const rmm_ctx* h, int l, const double* G, int64_t ldg,
       parity ^= 1;
     }
     RMM_TRY(launch_status());
-    hipLaunchKernelGGL(big_sweep_end_kernel, dim3(1), dim3(1), 0, h->stream, st);
     hipLaunchKernelGGL(big_vectors_kernel, dim3(vgroups), dim3(256), vlds, h->stream, L, rlog, ptab,
                        qtab, Vr, st);
     RMM_TRY(launch_status());
