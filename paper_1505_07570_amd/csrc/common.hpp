@@ -65,6 +65,13 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Orders the LDS accesses of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 inline bool dt_ok(rmm_dtype dt) { return dt == RMM_F32 || dt == RMM_F64; }
 inline size_t dt_size(rmm_dtype dt) { return dt == RMM_F64 ? 8 : 4; }
 

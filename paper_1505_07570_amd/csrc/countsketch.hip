@@ -168,60 +168,97 @@ __global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
 
 // ---- scheduled variant (s <= 16384) ------------------------------------------------
 //
-// LDS float atomics are slow, so the scatter-add is made conflict free
-// ahead of time.  A wave instruction of the consumer handles one row group:
-// lane l of group (k, e) of a 256-row block holds row 256 k + 4 l + e.  A
-// pre-pass records for every row its bucket, its sign and whether a lower
-// lane of its group has the same bucket.  The first lane of every bucket
-// does a plain LDS read-modify-write (those buckets are pairwise distinct);
-// the later lanes then add atomically, after it in program order.  (A second
-// plain read-modify-write pass for the later lanes measured slower than the
-// atomics: it adds a dependent LDS round trip per row group.)
-// Entry (16 bits): bits 0-13 bucket, bit 14 "not first", bit 15 sign.  Rows
-// past the end of A read 0x4000 (an atomic +0 into bucket 0).
+// LDS float atomics are slow and a dependent read-modify-write per row
+// leaves the LDS idle for a round trip each time, so the scatter-add is made
+// conflict free ahead of time and issued in batches.  Rows are taken in
+// windows of 256 consecutive rows; lane l of a wave holds rows 4 l + e
+// (e = 0..3) of each window.  A pre-pass records for every row its bucket,
+// its sign and whether a row of smaller index in its window has the same
+// bucket ("later").  The first row of every bucket in a window does a plain
+// LDS read-modify-write: those buckets are pairwise distinct, so the four
+// reads of a lane go out together, then the four writes.  A later row sends
+// its plain read-modify-write to a scratch slot after the buckets instead and
+// then adds its value atomically into its bucket, after the plain writes in
+// program order (the LDS executes a wave's instructions in order).
+// Entry (16 bits): bits 0-13 bucket, bit 14 later, bit 15 sign.  The table is
+// padded to whole row chunks; rows past the end of A read 0x4000 (their
+// values are zero).  Within a chunk of UN windows the entries are stored
+// lane-major: the 4 UN entries that lane l uses (rows 256 k + 4 l + e) are
+// contiguous, so a lane fetches them with a few 16-byte loads.
 
 constexpr int kCsSchedMaxS = 1 << 14;
+constexpr int kCsWindow = 256;
 
-__device__ __forceinline__ void cs_schedule_body(int64_t m, uint32_t s, uint64_t seed,
-                                                 uint16_t* __restrict__ table, int64_t bx) {
-  const int lane = threadIdx.x & 63;
-  const int64_t blk = bx * 4 + (threadIdx.x >> 6);  // 256-row block
-  const int64_t row0 = blk * 256;
-  if (row0 >= m) return;
-  const Words4 w = philox_at((uint64_t)(row0 >> 2) + lane, TAG_COUNTSKETCH, 0, seed);
-  uint16_t o[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const uint32_t b = cs_bucket(w.w[e], s);
-    uint32_t dup = 0;
-    for (int off = 1; off < 64; ++off) {
-      const int src = lane - off;
-      const uint32_t ob = (uint32_t)__shfl(b, src & 63);
-      dup |= (src >= 0 && ob == b) ? 1u : 0u;
-    }
-    o[e] = (uint16_t)(b | (dup << 14) | ((w.w[e] & 1u) << 15));
-  }
-  const int64_t row = row0 + 4 * lane;
-  for (int e = 0; e < 4; ++e)
-    if (row + e < m) table[row + e] = o[e];
-}
-
-__global__ __launch_bounds__(256) void cs_schedule_kernel(int64_t m, uint32_t s, uint64_t seed,
-                                                          uint16_t* __restrict__ table) {
-  cs_schedule_body(m, s, seed, table, blockIdx.x);
-}
-
-// worker = one workgroup of WAVES waves; unit = (panel of WAVES columns,
-// 4096-row chunk).  Wave w owns column (panel start + w) and a private LDS
-// bucket array; the chunk's schedule entries are staged once into LDS and
-// shared by the WAVES columns (so the 2-byte table is read from memory once
-// per WAVES columns instead of once per column).  A and the next chunk's
-// table entries are loaded a unit ahead.
-// rows per chunk: 16 x 16-byte loads per lane in flight per unit
+// rows per chunk (the unit of work): 8 windows, one 16-byte (fp32) or two
+// (fp64) loads of A per lane and window.  Smaller units measured faster:
+// three of them in flight per wave, each issued as one burst of loads.
 template <typename T>
 constexpr int sched_chunk() {
-  return sizeof(T) == 4 ? 4096 : 2048;
+  return 2048;
 }
+
+// table entries (rows) for m rows: whole chunks of the widest type
+__host__ __device__ inline int64_t cs_table_rows(int64_t m) {
+  const int64_t c = sched_chunk<float>();
+  return (m + c - 1) / c * c;
+}
+// the table is followed by kCsZeroBytes zero bytes, the load target of rows past m
+constexpr int kCsZeroBytes = 256;
+inline size_t cs_table_elems(int64_t m) { return (size_t)cs_table_rows(m) + kCsZeroBytes / 2; }
+
+// one wave per 256-row window; un: windows per chunk; owner: this wave's s LDS words
+__device__ __forceinline__ void cs_schedule_body(int64_t m, uint32_t s, uint64_t seed, int un,
+                                                 uint16_t* __restrict__ table, int64_t win,
+                                                 uint32_t* __restrict__ owner) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row0 = win * kCsWindow + 4 * lane;
+  const Words4 w = philox_at((uint64_t)(row0 >> 2), TAG_COUNTSKETCH, 0, seed);
+  uint32_t b[4];
+  bool ok[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    b[e] = cs_bucket(w.w[e], s);
+    ok[e] = row0 + e < m;
+  }
+  // the smallest window position per bucket wins: set, min, read back
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (ok[e]) owner[b[e]] = 0xFFFFFFFFu;
+  wave_lds_sync();
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (ok[e]) atomicMin(owner + b[e], (uint32_t)(4 * lane + e));
+  wave_lds_sync();
+  uint32_t o[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t later = owner[b[e]] != (uint32_t)(4 * lane + e) ? 1u : 0u;
+    o[e] = ok[e] ? (b[e] | (later << 14) | ((w.w[e] & 1u) << 15)) : 0x4000u;
+  }
+  if (win == 0 && lane < kCsZeroBytes / 16)
+    reinterpret_cast<uint4*>(table + cs_table_rows(m))[lane] = make_uint4(0u, 0u, 0u, 0u);
+  const int64_t c = win / un;
+  const int64_t pos = c * kCsWindow * un + 4 * ((int64_t)lane * un + (win - c * un));
+  *reinterpret_cast<uint2*>(table + pos) = make_uint2(o[0] | (o[1] << 16), o[2] | (o[3] << 16));
+}
+
+__global__ __launch_bounds__(64) void cs_schedule_kernel(int64_t m, uint32_t s, uint64_t seed,
+                                                         int un, uint16_t* __restrict__ table) {
+  extern __shared__ uint32_t cs_owner[];
+  cs_schedule_body(m, s, seed, un, table, blockIdx.x, cs_owner);
+}
+
+// worker = one workgroup of WAVES waves; unit = (panel of up to WAVES
+// columns, chunk of rows).  Wave w owns column (panel start + w) and a
+// private LDS accumulator of s buckets plus the scratch slot; it loads its
+// own copy of the chunk's table entries (the WAVES waves of a workgroup read
+// the same entries at about the same time, mostly from cache), so the waves
+// never wait for each other.  A and the entries are loaded one unit ahead.
+template <typename T>
+struct CsUnit {
+  T v[sched_chunk<T>() / kCsWindow][4];
+  uint4 t[sched_chunk<T>() / kCsWindow / 2];  // entries of windows 2 j and 2 j + 1
+};
 
 template <typename T, bool VEC, int WAVES>
 __device__ __forceinline__ void cs_sched_body(const T* __restrict__ A, int64_t lda,
@@ -229,148 +266,159 @@ __device__ __forceinline__ void cs_sched_body(const T* __restrict__ A, int64_t l
                                               const PanelPlan& plan,
                                               const uint16_t* __restrict__ table,
                                               T* __restrict__ partials, int64_t wk) {
-  constexpr int kSchedChunk = sched_chunk<T>();
-  constexpr int UN = kSchedChunk / 256;  // UN x 4 rows per lane per chunk
-  constexpr int NT = 64 * WAVES;
+  constexpr int CH = sched_chunk<T>();
+  constexpr int UN = CH / kCsWindow;
   extern __shared__ __align__(16) unsigned char smem[];
   const int s = plan.s;
-  T* acc = reinterpret_cast<T*>(smem);
-  uint16_t* tls = reinterpret_cast<uint16_t*>(smem + (((size_t)WAVES * s * sizeof(T) + 15) & ~(size_t)15));
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  T* my = acc + (size_t)wave * s;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T* my = reinterpret_cast<T*>(smem) + (size_t)wave * (s + 4);
   const int64_t u0 = plan_start(plan, wk);
   const int64_t u1 = plan_start(plan, wk + 1);
   const int64_t nch = plan.nchunks;
-  for (int i = tid; i < WAVES * s; i += NT) acc[i] = T(0);
+  const int64_t m = plan.m;
+  for (int i = lane; i < s + 4; i += 64) my[i] = T(0);
 
-  // this wave's column of panel vp (nullptr when the panel is narrower)
+  // this wave's column of panel vp.  A wave without a column in a narrower
+  // panel streams the panel's first column along with wave 0 (cache hits)
+  // and adds it into its accumulator, which lands in a partial slot that no
+  // reduction reads: every wave then runs the same loads and LDS work.
   auto column = [&](int64_t vp) -> const T* {
-    const int64_t j = plan_col0(plan, (int)vp) + wave;
-    if (j >= plan_col0(plan, (int)vp + 1)) return nullptr;
+    const int64_t j0 = plan_col0(plan, (int)vp);
+    int64_t j = j0 + wave;
+    if (j >= plan_col0(plan, (int)vp + 1)) j = j0;
     return j < n ? A + j * lda : bcol;
   };
-  auto load_a = [&](const T* col, int64_t r0, T v[UN][4]) {
-    if (col == nullptr) return;
-    if (VEC && r0 + kSchedChunk <= plan.m) {
-#pragma unroll
-      for (int k = 0; k < UN; ++k) {
-        const T* p = col + r0 + 256 * k + 4 * lane;
-        if constexpr (sizeof(T) == 4) {
-          const float4 x = *reinterpret_cast<const float4*>(p);
-          v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
-        } else {
-          const double2 x = *reinterpret_cast<const double2*>(p);
-          const double2 y = *reinterpret_cast<const double2*>(p + 2);
-          v[k][0] = x.x; v[k][1] = x.y; v[k][2] = y.x; v[k][3] = y.y;
-        }
-      }
+  // Rows past m load zeros from the bytes after the table.  Both branches
+  // issue the same loads and no load result is touched here, so the wait
+  // before a value's first use covers that value's own load only.
+  const T* const zeros = reinterpret_cast<const T*>(table + cs_table_rows(m));
+  // entries of windows 2 j and 2 j + 1 of the chunk at row r0
+  auto load_tab = [&](int64_t r0, int j, CsUnit<T>& x) {
+    x.t[j] = reinterpret_cast<const uint4*>(table + r0 + 4 * UN * lane)[j];
+  };
+  // A values of window k of column col, chunk at row r0
+  auto load_win = [&](const T* col, int64_t r0, bool full, int k, CsUnit<T>& x) {
+    const T* q = col + r0 + kCsWindow * k + 4 * lane;
+    if (!full) {
+      // VEC implies m % 4 == 0: a lane's 4 rows are all in range or all out
+      if (VEC) q = r0 + kCsWindow * k + 4 * lane < m ? q : zeros;
+    }
+    if constexpr (VEC && sizeof(T) == 4) {
+      const float4 v4 = *reinterpret_cast<const float4*>(q);
+      x.v[k][0] = v4.x; x.v[k][1] = v4.y; x.v[k][2] = v4.z; x.v[k][3] = v4.w;
+    } else if constexpr (VEC) {
+      const double2 q0 = *reinterpret_cast<const double2*>(q);
+      const double2 q1 = *reinterpret_cast<const double2*>(q + 2);
+      x.v[k][0] = q0.x; x.v[k][1] = q0.y; x.v[k][2] = q1.x; x.v[k][3] = q1.y;
     } else {
 #pragma unroll
-      for (int k = 0; k < UN; ++k)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t row = r0 + 256 * k + 4 * lane + e;
-          v[k][e] = row < plan.m ? col[row] : T(0);
-        }
-    }
-  };
-  // the chunk's entries in groups of 8; rows past the end get 0x4000
-  constexpr int TG = kSchedChunk / 8;
-  constexpr int TPT = (TG + NT - 1) / NT;
-  auto load_t = [&](int64_t r0, uint4 tr[TPT]) {
-#pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-      const int g = tid + q * NT;
-      if (g >= TG) break;
-      const int64_t row = r0 + 8 * g;
-      if (row + 8 <= plan.m) {
-        tr[q] = *reinterpret_cast<const uint4*>(table + row);
-      } else {
-        uint32_t w4[4];
-#pragma unroll
-        for (int h2 = 0; h2 < 4; ++h2) {
-          const uint32_t lo = row + 2 * h2 < plan.m ? (uint32_t)table[row + 2 * h2] : 0x4000u;
-          const uint32_t hi = row + 2 * h2 + 1 < plan.m ? (uint32_t)table[row + 2 * h2 + 1] : 0x4000u;
-          w4[h2] = lo | (hi << 16);
-        }
-        tr[q] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+      for (int e = 0; e < 4; ++e) {
+        const T* qe = q + e;
+        if (!full) qe = r0 + kCsWindow * k + 4 * lane + e < m ? qe : zeros;
+        x.v[k][e] = *qe;
       }
     }
   };
-  auto store_t = [&](int buf, const uint4 tr[TPT]) {
+  auto scatter_win = [&](const CsUnit<T>& x, int k) {
+    const uint32_t w0 = (k & 1) ? x.t[k >> 1].z : x.t[k >> 1].x;
+    const uint32_t w1 = (k & 1) ? x.t[k >> 1].w : x.t[k >> 1].y;
+    const uint32_t ent[4] = {w0 & 0xFFFFu, w0 >> 16, w1 & 0xFFFFu, w1 >> 16};
+    T val[4], old[4];
+    uint32_t f[4];
 #pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-      const int g = tid + q * NT;
-      if (g >= TG) break;
-      *reinterpret_cast<uint4*>(tls + buf * kSchedChunk + 8 * g) = tr[q];
+    for (int e = 0; e < 4; ++e) {
+      val[e] = apply_sign<T>(x.v[k][e], ent[e] << 16);
+      f[e] = ent[e] & 0x7FFFu;  // bucket, plus 0x4000 for a later row
     }
+    // the bucket, or the scratch slot s for a later row (0x4000 >= s)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) old[e] = my[min(f[e], (uint32_t)s)];
+    // all four reads go out before the first wait for their data
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) my[min(f[e], (uint32_t)s)] = old[e] + val[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (f[e] >= 0x4000u) atomicAdd(my + (f[e] - 0x4000u), val[e]);
+  };
+  auto scatter = [&](const CsUnit<T>& x) {
+#pragma unroll
+    for (int k = 0; k < UN; ++k) scatter_win(x, k);
   };
 
-  T v[UN][4], vn[UN][4];
-  uint4 tr[TPT];
-  // unit u = (panel vp, chunk c), advanced incrementally (no divisions in the loop)
-  int64_t vp = u0 / nch, c = u0 - (u0 / nch) * nch;
-  int64_t cur = u0 < u1 ? vp : -1;
-  const T* col = u0 < u1 ? column(vp) : nullptr;
-  int buf = 0;
-  if (u0 < u1) {
-    load_a(col, c * kSchedChunk, v);
-    load_t(c * kSchedChunk, tr);
-    store_t(0, tr);
-  }
-  __syncthreads();
-  for (int64_t u = u0; u < u1; ++u) {
-    if (vp != cur) {
+  // all loads of a unit, issued together (a burst keeps more bytes in flight
+  // than loads spread over the unit's additions, measured)
+  auto load = [&](const T* lcol, int64_t r0, CsUnit<T>& x) {
+#pragma unroll
+    for (int k = 0; k < UN; ++k) {
+      if ((k & 1) == 0) load_tab(r0, k >> 1, x);
+      load_win(lcol, r0, r0 + CH <= m, k, x);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // Units u = (panel, chunk) are loaded two ahead of their addition, into
+  // three register buffers used in rotation.  Every step issues the same
+  // loads in the same order, so the wait before a value's first use only
+  // covers that value's own load.  Both cursors advance without divisions.
+  int64_t lp = u0 / nch, lc = u0 - (u0 / nch) * nch;  // next unit to load
+  const T* lcol = column(lp);
+  int64_t ap = lp, ac = lc;  // next unit to add
+  int64_t cur = ap;          // panel of the accumulator contents
+  auto load_next = [&](CsUnit<T>& x) {
+    load(lcol, lc * CH, x);
+    if (++lc == nch) {
+      lc = 0;
+      lcol = column(++lp);
+    }
+  };
+  auto add_next = [&](const CsUnit<T>& x) {
+    if (ap != cur) {
       T* dst = partials + (wk + cur) * plan.slot_elems + (size_t)wave * s;
       for (int i = lane; i < s; i += 64) {
         dst[i] = my[i];
         my[i] = T(0);
       }
-      cur = vp;
+      cur = ap;
     }
-    int64_t vpn = vp, cn = c + 1;
-    if (cn == nch) {
-      cn = 0;
-      ++vpn;
+    scatter(x);
+    if (++ac == nch) {
+      ac = 0;
+      ++ap;
     }
-    const bool more = u + 1 < u1;
-    const T* coln = col;
-    if (more) {
-      if (vpn != vp) coln = column(vpn);
-      load_a(coln, cn * kSchedChunk, vn);
-      load_t(cn * kSchedChunk, tr);
+  };
+  const int64_t nu = u1 - u0;
+  if (nu > 0) {
+    CsUnit<T> xa, xb, xc;
+    load_next(xa);
+    if (nu > 1) load_next(xb);
+    int64_t i = 0;  // units added
+    for (; i + 5 <= nu; i += 3) {
+      load_next(xc);
+      add_next(xa);
+      load_next(xa);
+      add_next(xb);
+      load_next(xb);
+      add_next(xc);
     }
-    if (col != nullptr) {
-      const uint16_t* tb = tls + buf * kSchedChunk;
-#pragma unroll
-      for (int k = 0; k < UN; ++k) {
-        const uint2 tk = *reinterpret_cast<const uint2*>(tb + 256 * k + 4 * lane);
-        const uint32_t tw[2] = {tk.x, tk.y};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const uint32_t ent = (tw[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-          T* p = my + (ent & 0x3FFFu);
-          const T x = apply_sign<T>(v[k][e], ent << 16);
-          const bool later = (ent & 0x4000u) != 0u;
-          if (!later) *p += x;
-          if (__builtin_amdgcn_ballot_w64(later)) {
-            if (later) atomicAdd(p, x);
-          }
-        }
-      }
+    const int64_t r = nu - i;  // 1..4 units left; xa (and xb if r > 1) loaded
+    if (r == 1) {
+      add_next(xa);
+    } else if (r == 2) {
+      add_next(xa);
+      add_next(xb);
+    } else if (r == 3) {
+      load_next(xc);
+      add_next(xa);
+      add_next(xb);
+      add_next(xc);
+    } else {
+      load_next(xc);
+      add_next(xa);
+      load_next(xa);
+      add_next(xb);
+      add_next(xc);
+      add_next(xa);
     }
-    if (more) store_t(buf ^ 1, tr);
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < UN; ++k)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[k][e] = vn[k][e];
-    buf ^= 1;
-    vp = vpn;
-    c = cn;
-    col = coln;
-  }
-  if (cur >= 0) {
     T* dst = partials + (wk + cur) * plan.slot_elems + (size_t)wave * s;
     for (int i = lane; i < s; i += 64) dst[i] = my[i];
   }
@@ -387,13 +435,13 @@ __global__ __launch_bounds__(64 * WAVES) void countsketch_sched_kernel(
 template <typename T>
 int cs_sched_waves(int64_t s) {
   int w = 8;
-  while (w > 1 && (size_t)w * s * sizeof(T) + 2 * sched_chunk<T>() * 2 + 16 > 150 * 1024) w /= 2;
+  while (w > 1 && (size_t)w * (s + 4) * sizeof(T) > 150 * 1024) w /= 2;
   return w;
 }
 
 template <typename T>
 size_t cs_sched_lds(int64_t s, int waves) {
-  return (((size_t)waves * s * sizeof(T) + 15) & ~(size_t)15) + 2 * sched_chunk<T>() * sizeof(uint16_t);
+  return (size_t)waves * (s + 4) * sizeof(T);
 }
 
 // ---- grouped execution over a descriptor table ----------------------------------------
@@ -412,7 +460,7 @@ struct CsGroupDesc {
   T* partials;
   int64_t lda, ldc, m;
   uint64_t seed;
-  int64_t sblk0;  // first schedule block of this problem
+  int64_t sblk0;  // first schedule window of this problem
   int64_t wk0;    // first scatter-add worker
   int64_t col0;   // first reduction column
   PanelPlan plan;
@@ -434,11 +482,12 @@ __device__ __forceinline__ int group_find(const CsGroupDesc<T>* __restrict__ d, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void cs_schedule_group_kernel(const CsGroupDesc<T>* __restrict__ d,
-                                                                int count) {
+__global__ __launch_bounds__(64) void cs_schedule_group_kernel(const CsGroupDesc<T>* __restrict__ d,
+                                                               int count) {
+  extern __shared__ uint32_t cs_owner[];
   const int p = group_find(d, count, blockIdx.x, 0);
-  cs_schedule_body(d[p].m, (uint32_t)d[p].plan.s, d[p].seed, d[p].table,
-                   (int64_t)blockIdx.x - d[p].sblk0);
+  cs_schedule_body(d[p].m, (uint32_t)d[p].plan.s, d[p].seed, sched_chunk<T>() / kCsWindow,
+                   d[p].table, (int64_t)blockIdx.x - d[p].sblk0, cs_owner);
 }
 
 template <typename T, int WAVES>
@@ -548,7 +597,7 @@ size_t countsketch_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s) 
   Carver c(nullptr, 0);
   if (cs_use_sched(s, sizeof(T))) {
     const PanelPlan plan = cs_sched_plan<T>(h, m, ncols, (int)s);
-    c.take<uint16_t>((size_t)(m > 0 ? m : 1));
+    c.take<uint16_t>(cs_table_elems(m > 0 ? m : 1));
     c.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
     return c.off;
   }
@@ -565,16 +614,16 @@ int countsketch_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const
   const int ncols = n + (b ? 1 : 0);
   if (ncols == 0) return RMM_OK;
   if (m == 0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
-  const bool vecs = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) &&
-                    (b == nullptr || (uintptr_t)b % 16 == 0);
   if (cs_use_sched(s, sizeof(T))) {
+    const bool vecs = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) && (m % 4 == 0) &&
+                      (b == nullptr || (uintptr_t)b % 16 == 0);
     const PanelPlan plan = cs_sched_plan<T>(h, m, ncols, (int)s);
-    uint16_t* table = ws.take<uint16_t>((size_t)m);
+    uint16_t* table = ws.take<uint16_t>(cs_table_elems(m));
     T* partials = ws.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
     if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
-    const int64_t blocks256 = (m + 255) / 256;
-    hipLaunchKernelGGL(cs_schedule_kernel, dim3((unsigned)((blocks256 + 3) / 4)), dim3(256), 0,
-                       h->stream, m, (uint32_t)s, seed, table);
+    hipLaunchKernelGGL(cs_schedule_kernel, dim3((unsigned)(cs_table_rows(m) / kCsWindow)),
+                       dim3(64), (size_t)s * sizeof(uint32_t), h->stream, m, (uint32_t)s, seed,
+                       sched_chunk<T>() / kCsWindow, table);
     RMM_TRY(launch_status());
     const int rc = vecs ? launch_cs_sched<T, true>(h, A, lda, b, n, plan, table, partials)
                         : launch_cs_sched<T, false>(h, A, lda, b, n, plan, table, partials);
@@ -630,7 +679,7 @@ int cs_batch_layout(const rmm_ctx* h, int count, const rmm_sketch_desc* d, Carve
     if (d[i].m == 0 || ncols == 0) continue;
     const int s = (int)d[i].s;
     const PanelPlan plan = cs_sched_plan<T>(h, d[i].m, ncols, s);
-    uint16_t* table = ws.take<uint16_t>((size_t)d[i].m);
+    uint16_t* table = ws.take<uint16_t>(cs_table_elems(d[i].m));
     T* partials = ws.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
     if (out) {
       CsGroupDesc<T> g{};
@@ -648,11 +697,11 @@ int cs_batch_layout(const rmm_ctx* h, int count, const rmm_sketch_desc* d, Carve
       g.col0 = col;
       g.plan = plan;
       g.n = (int)d[i].n;
-      g.vec = ((uintptr_t)d[i].A % 16 == 0) && (d[i].lda % 4 == 0) &&
+      g.vec = ((uintptr_t)d[i].A % 16 == 0) && (d[i].lda % 4 == 0) && (d[i].m % 4 == 0) &&
               (d[i].b == nullptr || (uintptr_t)d[i].b % 16 == 0);
       out->push_back(g);
     }
-    sb += ((d[i].m + 255) / 256 + 3) / 4;
+    sb += cs_table_rows(d[i].m) / kCsWindow;
     wk += plan.G;
     col += ncols;
     if (s > ms) ms = s;
@@ -704,8 +753,8 @@ int countsketch_batch_run(rmm_ctx* h, int count, const rmm_sketch_desc* d, Carve
   std::memcpy(h->table_host.data(), g.data(), h->table_host.size());
   RMM_HIP(hipMemcpyAsync(dd, h->table_host.data(), h->table_host.size(), hipMemcpyHostToDevice,
                          h->stream));
-  hipLaunchKernelGGL(cs_schedule_group_kernel<T>, dim3((unsigned)nsblk), dim3(256), 0, h->stream, dd,
-                     gc);
+  hipLaunchKernelGGL(cs_schedule_group_kernel<T>, dim3((unsigned)nsblk), dim3(64),
+                     (size_t)ms * sizeof(uint32_t), h->stream, dd, gc);
   RMM_TRY(launch_status());
   // one scatter-add launch per workgroup width; problems of the same width
   // are contiguous in the table (sorted by width on the host)

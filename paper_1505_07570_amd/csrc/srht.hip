@@ -45,12 +45,6 @@ __device__ __forceinline__ double flip<double>(double x, uint32_t bit) {
   return __longlong_as_double((long long)u);
 }
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <typename T>
 __device__ __forceinline__ void bfly(T& a, T& b) {
   const T x = a + b;

@@ -39,7 +39,7 @@ def test_hashes_and_signs_bit_exact(h, m, s, seed):
 
 @pytest.mark.parametrize("m,s,seed", [(1, 1, 3), (2048, 256, 75700001), (1 << 20, 4096, 75700002),
                                       (3000, 4096, 7), (5000, 1, 8), (8192, 8192, 9),
-                                      (1000, 513, 10)])
+                                      (1000, 513, 10), ((1 << 20) + 5, 300, 11)])
 def test_srht_indices_bit_exact(h, m, s, seed):
     got = h.srht_indices(m, s, seed).cpu().numpy()
     np.testing.assert_array_equal(got, osk.srht_indices(m, s, seed))
