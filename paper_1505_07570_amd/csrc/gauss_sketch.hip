@@ -177,7 +177,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     }
   };
-  // Omega[r0 + k, mblk + c] for k < KS, c < 128, written to om[b][k * 128 + c]
+  // Omega[r0 + k, mblk + c] for k < KS, c < 128, written to om[b][k * 128 + c].
+  // Entries of rows past the K range are generated too (always finite): they
+  // meet zero rows of the A tile.  Columns past s are zero without generation.
   auto gen_omega = [&](int64_t r0, int b) {
 #pragma unroll
     for (int u = 0; u < CPT; ++u) {
@@ -186,24 +188,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int cq = call - k * (128 / PER);
       const int64_t i = r0 + k;
       const int c0 = mblk + PER * cq;
-      const bool ok = i < k1;
-      if constexpr (sizeof(T) == 4) {
-        float z[4];
-        gauss4_f32((uint64_t)i, (uint32_t)(c0 >> 2), tag, seed, z);
-        float4 o;
-        o.x = (ok && c0 + 0 < s) ? z[0] : 0.f;
-        o.y = (ok && c0 + 1 < s) ? z[1] : 0.f;
-        o.z = (ok && c0 + 2 < s) ? z[2] : 0.f;
-        o.w = (ok && c0 + 3 < s) ? z[3] : 0.f;
-        *reinterpret_cast<float4*>(&om[b][k * 128 + PER * cq]) = o;
-      } else {
-        double z[2];
-        gauss2_f64((uint64_t)i, (uint32_t)(c0 >> 1), tag, seed, z);
-        double2 o;
-        o.x = (ok && c0 < s) ? z[0] : 0.0;
-        o.y = (ok && c0 + 1 < s) ? z[1] : 0.0;
-        *reinterpret_cast<double2*>(&om[b][k * 128 + PER * cq]) = o;
+      T z[PER];
+#pragma unroll
+      for (int e = 0; e < PER; ++e) z[e] = T(0);
+      if (c0 < s) {
+        if constexpr (sizeof(T) == 4) gauss4_f32((uint64_t)i, (uint32_t)(c0 >> 2), tag, seed, z);
+        else gauss2_f64((uint64_t)i, (uint32_t)(c0 >> 1), tag, seed, z);
       }
+      T* o = &om[b][k * 128 + PER * cq];
+      if constexpr (sizeof(T) == 4)
+        *reinterpret_cast<float4*>(o) = make_float4(z[0], z[1], z[2], z[3]);
+      else
+        *reinterpret_cast<double2*>(o) = make_double2(z[0], z[1]);
     }
   };
 
@@ -220,6 +216,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
   __syncthreads();
   const int arow = 32 * wave + mi;
+  const bool wave_rows = mblk + 32 * wave < s;  // uniform per wave
   for (int64_t st = 0; st < nst; ++st) {
     const int b = (int)(st & 1);
     const int64_t r0 = k0 + st * KS;
@@ -228,16 +225,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       load_stage(r0 + KS);
       if constexpr (MAT) load_q(r0 + KS);
     }
+    // a wave whose 32 sketch rows all lie past s skips the MFMAs
+    if (wave_rows) {
 #pragma unroll
-    for (int ks = 0; ks < KS / 4; ++ks) {
-      const T a0 = om[b][(4 * ks + kk) * 128 + arow];
-      const T a1 = om[b][(4 * ks + kk) * 128 + arow + 16];
-      const T* tb = &tile[b][mi * LDT + 4 * ks + kk];
+      for (int ks = 0; ks < KS / 4; ++ks) {
+        const T a0 = om[b][(4 * ks + kk) * 128 + arow];
+        const T a1 = om[b][(4 * ks + kk) * 128 + arow + 16];
+        const T* tb = &tile[b][mi * LDT + 4 * ks + kk];
 #pragma unroll
-      for (int q = 0; q < NT; ++q) {
-        const T bv = tb[q * 16 * LDT];
-        acc[0][q] = mfma16(a0, bv, acc[0][q]);
-        acc[1][q] = mfma16(a1, bv, acc[1][q]);
+        for (int q = 0; q < NT; ++q) {
+          const T bv = tb[q * 16 * LDT];
+          acc[0][q] = mfma16(a0, bv, acc[0][q]);
+          acc[1][q] = mfma16(a1, bv, acc[1][q]);
+        }
       }
     }
     if (more) {
@@ -294,9 +294,11 @@ GaussShape gauss_shape(const rmm_ctx* h, int64_t m, int ncols, int s) {
   g.mtiles = (s + 127) / 128;
   const int64_t KS = GaussCfg<T>::KS;
   // enough K splits for about four workgroups per CU, each at most KMAX rows
+  // and at least 16 stages (a short problem is latency bound: its stages run
+  // one after another inside a workgroup)
   int64_t want = (4ll * h->cus + (int64_t)g.mtiles * g.ntiles - 1) / ((int64_t)g.mtiles * g.ntiles);
   const int64_t minsplit = (m + GaussCfg<T>::KMAX - 1) / GaussCfg<T>::KMAX;
-  const int64_t maxsplit = (m + 1023) / 1024;
+  const int64_t maxsplit = (m + 16 * KS - 1) / (16 * KS);
   if (want > maxsplit) want = maxsplit;
   if (want < minsplit) want = minsplit;
   if (want < 1) want = 1;

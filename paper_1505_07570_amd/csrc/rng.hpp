@@ -37,10 +37,6 @@ struct Words4 {
   uint32_t w[4];
 };
 
-__host__ __device__ __forceinline__ uint32_t mul_hi32(uint32_t a, uint32_t b) {
-  return (uint32_t)(((uint64_t)a * (uint64_t)b) >> 32);
-}
-
 __host__ __device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1,
                                                   uint32_t c2, uint32_t c3,
                                                   uint64_t seed) {
@@ -48,13 +44,13 @@ __host__ __device__ __forceinline__ Words4 philox(uint32_t c0, uint32_t c1,
   uint32_t k1 = (uint32_t)(seed >> 32);
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t a = c0, b = c2;
-    const uint32_t hi_a = mul_hi32(0xD2511F53u, a);
-    const uint32_t hi_b = mul_hi32(0xCD9E8D57u, b);
-    c0 = hi_b ^ c1 ^ k0;
-    c1 = 0xCD9E8D57u * b;
-    c2 = hi_a ^ c3 ^ k1;
-    c3 = 0xD2511F53u * a;
+    // both halves of each 64-bit product come from one v_mad_u64_u32
+    const uint64_t pa = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t pb = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    c0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+    c1 = (uint32_t)pb;
+    c2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+    c3 = (uint32_t)pa;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;
   }

@@ -27,8 +27,10 @@ __device__ __forceinline__ void or_status(int32_t* status, int32_t flag) {
 // c <= j (inverse part); there it loses f_i r_c with f_i = W[j][i] / p_j and
 // r = row j of W with r_j = 1.
 //
-// W lives in registers: thread (r0, c0) of the 32 x 32 thread grid owns rows
-// r0 + 32a and columns c0 + 32b (a, b < 4).  Step j only needs row j: its
+// W lives in registers: thread (r0, c0) of the TR x TC thread grid owns rows
+// r0 + TR a and columns c0 + TC b (a < NA, b < NB): 32 x 32 threads with
+// 4 x 4 entries each up to 128, 8 x 32 threads with 4 x 1 entries up to 32
+// (fewer waves make the per-step barrier cheaper).  Step j only needs row j: its
 // owners publish it, with 1 / p_j, into one of two LDS row buffers right
 // after their step j - 1 update, so one barrier per step suffices.  All LDS
 // reads of a step are issued together, and the per-entry condition is a
@@ -36,7 +38,8 @@ __device__ __forceinline__ void or_status(int32_t* status, int32_t flag) {
 // The drop test of pivot j compares against orig[j * ostride] (the diagonal
 // of the matrix the caller considers original), or G_jj when orig is null;
 // a dropped pivot eliminates nothing and gives a zero column of R^{-1}.
-__global__ __launch_bounds__(kSmallThreads) void cholinv_reg_kernel(
+template <int TR, int TC, int NA, int NB>
+__global__ __launch_bounds__(TR * TC) void cholinv_reg_kernel(
     int l, const double* __restrict__ G, int64_t ldg, double tau, const double* orig,
     int64_t ostride, double* __restrict__ Rinv, int64_t ldr, double* __restrict__ diag,
     int32_t* status) {
@@ -45,28 +48,28 @@ __global__ __launch_bounds__(kSmallThreads) void cholinv_reg_kernel(
   __shared__ double sorig[kLdsMaxL];
   __shared__ double piv[kLdsMaxL];
   const int tid = threadIdx.x;
-  const int c0 = tid & 31, r0 = tid >> 5;
-  double w[4][4];
+  const int c0 = tid % TC, r0 = tid / TC;
+  double w[NA][NB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = r0 + 32 * a, c = c0 + 32 * b;
+    for (int b = 0; b < NB; ++b) {
+      const int i = r0 + TR * a, c = c0 + TC * b;
       w[a][b] = (i < l && c < l && i <= c) ? G[i + (int64_t)c * ldg] : 0.0;
     }
   if (tid < l) sorig[tid] = orig ? orig[tid * ostride] : G[tid + (int64_t)tid * ldg];
   __syncthreads();
-  // publish row j (held by the threads with r0 == j % 32, a == j / 32)
+  // publish row j (held by the threads with r0 == j % TR, a == j / TR)
   auto publish = [&](int j) {
-    if (j >= l || r0 != (j & 31)) return;
-    const int a = j >> 5;
+    if (j >= l || r0 != (j % TR)) return;
+    const int a = j / TR;
     double* rb = rowbuf[j & 1];
 #pragma unroll
-    for (int aa = 0; aa < 4; ++aa) {
+    for (int aa = 0; aa < NA; ++aa) {
       if (aa != a) continue;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int c = c0 + 32 * b;
+      for (int b = 0; b < NB; ++b) {
+        const int c = c0 + TC * b;
         rb[c] = w[aa][b];
         if (c == j) {
           const double p = w[aa][b];
@@ -83,22 +86,22 @@ __global__ __launch_bounds__(kSmallThreads) void cholinv_reg_kernel(
     __syncthreads();
     const double inv = invbuf[j & 1];
     const double* rb = rowbuf[j & 1];
-    double rc[4], fr[4];
+    double rc[NB], fr[NA];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rc[b] = rb[c0 + 32 * b];
+    for (int b = 0; b < NB; ++b) rc[b] = rb[c0 + TC * b];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) fr[a] = rb[r0 + 32 * a];
+    for (int a = 0; a < NA; ++a) fr[a] = rb[r0 + TR * a];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if (c0 + 32 * b == j) rc[b] = 1.0;
+    for (int b = 0; b < NB; ++b)
+      if (c0 + TC * b == j) rc[b] = 1.0;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = r0 + 32 * a;
-      if (i <= j) continue;  // uniform over half-waves
+    for (int a = 0; a < NA; ++a) {
+      const int i = r0 + TR * a;
+      if (i <= j) continue;  // uniform over runs of TC lanes
       const double f = fr[a] * inv;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int c = c0 + 32 * b;
+      for (int b = 0; b < NB; ++b) {
+        const int c = c0 + TC * b;
         const double d = (c >= i || c <= j) ? f * rc[b] : 0.0;
         w[a][b] -= d;
       }
@@ -107,10 +110,10 @@ __global__ __launch_bounds__(kSmallThreads) void cholinv_reg_kernel(
   }
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int j = r0 + 32 * a, c = c0 + 32 * b;  // W[j][c]
+    for (int b = 0; b < NB; ++b) {
+      const int j = r0 + TR * a, c = c0 + TC * b;  // W[j][c]
       if (j >= l || c >= l) continue;
       const double pj = piv[j];
       double v = 0.0;
@@ -158,8 +161,12 @@ static int cholinv_rec(rmm_ctx* h, int l, const double* G, int64_t ldg, double t
                        const double* orig, int64_t ostride, double* Rinv, int64_t ldr, double* diag,
                        int32_t* status, Carver& ws) {
   if (l <= kLdsMaxL) {
-    hipLaunchKernelGGL(cholinv_reg_kernel, dim3(1), dim3(kSmallThreads), 0, h->stream, l, G, ldg,
-                       tau, orig, ostride, Rinv, ldr, diag, status);
+    if (l <= 32)
+      hipLaunchKernelGGL((cholinv_reg_kernel<8, 32, 4, 1>), dim3(1), dim3(256), 0, h->stream, l, G,
+                         ldg, tau, orig, ostride, Rinv, ldr, diag, status);
+    else
+      hipLaunchKernelGGL((cholinv_reg_kernel<32, 32, 4, 4>), dim3(1), dim3(1024), 0, h->stream, l,
+                         G, ldg, tau, orig, ostride, Rinv, ldr, diag, status);
     return launch_status();
   }
   const int l1 = (l + 1) / 2, l2 = l - l1;
@@ -763,7 +770,12 @@ int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* ev
                      2 * (size_t)npairs * sizeof(int);
   RMM_HIP(hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kSmallThreads), lds, h->stream, l, G, ldg, evals,
+  // 32 threads per row pair of the pair grid: no more waves than that, since
+  // every round ends in two workgroup barriers whose cost grows with the waves
+  int threads = (npairs + 1) / 2 * 32;
+  threads = (threads + 63) / 64 * 64;
+  if (threads > kSmallThreads) threads = kSmallThreads;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(threads), lds, h->stream, l, G, ldg, evals,
                      perm, rlog, nr, status, kJacobiMaxSweeps);
   RMM_TRY(launch_status());
   const size_t vlds = (size_t)4 * kVecRows * L * sizeof(double) + 2 * (size_t)(L - 1) * npairs;
