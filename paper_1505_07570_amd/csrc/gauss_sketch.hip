@@ -54,7 +54,11 @@ __device__ __forceinline__ int mfma_row(double, int g, int v) { return g + 4 * v
 
 // MAT: the left operand is a stored matrix Qm (m x s, column-major, ld ldq)
 // instead of generated Gaussians, i.e. the kernel computes Qm^T [A | b].
-template <typename T, int NT, bool VEC, bool MAT>
+// XC: the last column tile carries one more column (ncols = 16 NT t + 1, the
+// sketch of [A | b] with n a multiple of 256); its 128 dot products per stage
+// run on the VALU (two threads per sketch row, 8 of the 16 rows of K each)
+// instead of padding a whole 16-column MFMA tile.
+template <typename T, int NT, bool VEC, bool MAT, bool XC = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gauss_sketch_kernel(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, int ncols,
     int64_t m, int s, int64_t kchunk, uint32_t tag, uint64_t seed, const T* __restrict__ Qm,
@@ -63,13 +67,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   using acc_t = typename Cfg::acc_t;
   constexpr int KS = Cfg::KS;
   constexpr int LDT = Cfg::LDT;
-  constexpr int NCOL = NT * 16;              // columns of the tile
-  constexpr int GROUPS = NCOL * (KS / 4);    // 4-row groups of A per stage
+  constexpr int NCOL = NT * 16;              // columns of the MFMA tiles
+  constexpr int NSTG = NCOL + (XC ? 1 : 0);  // columns staged per stage
+  constexpr int GROUPS = NSTG * (KS / 4);    // 4-row groups of A per stage
   constexpr int GPT = (GROUPS + 255) / 256;  // groups per thread
   constexpr int PER = sizeof(T) == 4 ? 4 : 2;            // normals per Philox block
   constexpr int CALLS = KS * 128 / PER;                  // Philox blocks per stage
   constexpr int CPT = CALLS / 256;                       // per thread
-  __shared__ T tile[2][NCOL * LDT];
+  __shared__ T tile[2][NSTG * LDT];
   __shared__ T om[2][KS * 128];
 
   const int tid = threadIdx.x;
@@ -216,6 +221,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
   __syncthreads();
   const int arow = 32 * wave + mi;
+  // extra column: this thread's sketch row and half of the stage's K rows
+  const bool has_xc = XC && blockIdx.y + 1 == gridDim.y;
+  const int xr = tid & 127, xh = tid >> 7;
+  T xacc = T(0);
   const bool wave_rows = mblk + 32 * wave < s;  // uniform per wave
   for (int64_t st = 0; st < nst; ++st) {
     const int b = (int)(st & 1);
@@ -224,6 +233,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     if (more) {
       load_stage(r0 + KS);
       if constexpr (MAT) load_q(r0 + KS);
+    }
+    if constexpr (XC) {
+      if (has_xc) {
+        const T* tx = &tile[b][NCOL * LDT + 8 * xh];
+        const T* ox = &om[b][8 * xh * 128 + xr];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) xacc += ox[k * 128] * tx[k];
+      }
     }
     // a wave whose 32 sketch rows all lie past s skips the MFMAs
     if (wave_rows) {
@@ -248,6 +265,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     __syncthreads();
   }
   T* dst = partials + (int64_t)sp * ncols * s;
+  if constexpr (XC) {
+    if (has_xc) {
+      // the two halves of each row meet in LDS (free after the last barrier)
+      if (xh == 1) om[0][xr] = xacc;
+      __syncthreads();
+      const int r = mblk + xr;
+      if (xh == 0 && r < s) dst[(int64_t)(nbase + NCOL) * s + r] = xacc + om[0][xr];
+    }
+  }
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
@@ -278,6 +304,7 @@ namespace {
 
 struct GaussShape {
   int NT;
+  bool xc;  // one extra column in the last tile
   int ntiles;
   int mtiles;
   int splits;
@@ -290,7 +317,13 @@ GaussShape gauss_shape(const rmm_ctx* h, int64_t m, int ncols, int s) {
   // fp64 accumulators for 17 column tiles do not fit two waves per SIMD
   const int ntmax = sizeof(T) == 4 ? 17 : 8;
   g.NT = ncols > 128 ? ntmax : ncols > 64 ? 8 : ncols > 16 ? 4 : 1;
-  g.ntiles = (ncols + g.NT * 16 - 1) / (g.NT * 16);
+  g.xc = false;
+  // fp32: 256-column tiles without padding when ncols is 256 t or 256 t + 1
+  if (sizeof(T) == 4 && ncols > 128 && (ncols % 256 == 0 || ncols % 256 == 1)) {
+    g.NT = 16;
+    g.xc = ncols % 256 == 1;
+  }
+  g.ntiles = (ncols - (g.xc ? 1 : 0) + g.NT * 16 - 1) / (g.NT * 16);
   g.mtiles = (s + 127) / 128;
   const int64_t KS = GaussCfg<T>::KS;
   // enough K splits for about four workgroups per CU, each at most KMAX rows
@@ -311,7 +344,7 @@ GaussShape gauss_shape(const rmm_ctx* h, int64_t m, int ncols, int s) {
   return g;
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool XC = false>
 int launch_gauss(const rmm_ctx* h, const GaussShape& g, const T* A, int64_t lda, const T* b,
                  int n, int ncols, int64_t m, int s, uint32_t tag, uint64_t seed, const T* Qm,
                  int64_t ldq, T* partials) {
@@ -319,7 +352,7 @@ int launch_gauss(const rmm_ctx* h, const GaussShape& g, const T* A, int64_t lda,
   bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) && (b == nullptr || (uintptr_t)b % 16 == 0);
   if (Qm) vec = vec && ((uintptr_t)Qm % 16 == 0) && (ldq % 4 == 0);
 #define RMM_GS_LAUNCH(V, M)                                                                    \
-  hipLaunchKernelGGL((gauss_sketch_kernel<T, NT, V, M>), grid, dim3(256), 0, h->stream, A, lda, b, \
+  hipLaunchKernelGGL((gauss_sketch_kernel<T, NT, V, M, XC>), grid, dim3(256), 0, h->stream, A, lda, b, \
                      n, ncols, m, s, g.kchunk, tag, seed, Qm, ldq, partials)
   if (Qm) {
     if (vec) RMM_GS_LAUNCH(true, true);
@@ -362,6 +395,15 @@ int project_any(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* 
     case 17:
       if constexpr (sizeof(T) == 4) {
         rc = launch_gauss<T, 17>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, Qm, ldq, partials);
+        break;
+      }
+      return RMM_ERR_UNSUPPORTED;
+    case 16:
+      if constexpr (sizeof(T) == 4) {
+        rc = g.xc ? launch_gauss<T, 16, true>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed, Qm,
+                                              ldq, partials)
+                  : launch_gauss<T, 16, false>(h, g, A, lda, b, n, ncols, m, (int)s, tag, seed,
+                                               Qm, ldq, partials);
         break;
       }
       return RMM_ERR_UNSUPPORTED;

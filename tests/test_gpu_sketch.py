@@ -104,6 +104,24 @@ def test_sketch_with_b_column_and_padded_lda(h, dtype, name, kind):
         assert rel(host(C)[:, j], ref[:, j]) < 10 * TOL[dtype]
 
 
+@pytest.mark.parametrize("n,with_b", [(256, True), (256, False), (512, True), (255, True)])
+def test_gaussian_column_tilings(h, n, with_b):
+    """fp32 Gaussian sketch at column counts that select 256-column tiles
+    (with and without one extra column handled outside the MFMA tiles), two
+    tiles, and the padded 272-column tile; every column against the oracle."""
+    m, s = 3000, 200
+    r = np.random.default_rng(n + 7 * with_b)
+    A = r.standard_normal((m, n)).astype(np.float32)
+    b = r.standard_normal(m).astype(np.float32)
+    C = h.sketch(dev(A, torch.float32), s, "gaussian", 91, b=dev(b, torch.float32) if with_b else None)
+    full = np.column_stack([A, b]) if with_b else A
+    ref = osk.sketch(full.astype(np.float64), s, osk.GAUSSIAN, 91, fp64=False)
+    got = host(C)
+    assert got.shape == ref.shape
+    for j in range(full.shape[1]):
+        assert rel(got[:, j], ref[:, j]) < 10 * TOL[torch.float32], j
+
+
 @pytest.mark.parametrize("name,kind", KINDS)
 def test_sketch_unaligned_views(h, name, kind):
     # odd leading dimension and a 4-byte offset force the scalar load path
