@@ -192,3 +192,46 @@ def test_nystrom_rows_and_zero_eigenvalues():
     Lr, _, Wr, lamr = nystrom.nystrom_rows(X, sigma, c, 9, rows, k=c)
     np.testing.assert_array_equal(Wr, W)
     np.testing.assert_allclose(Lr, L[rows], rtol=0, atol=1e-13)
+
+
+# ---- machine-precision LSR (Alg. 4.1) -----------------------------------------
+
+@pytest.mark.parametrize("kind", [sk.GAUSSIAN, sk.SRHT, sk.COUNTSKETCH])
+def test_precise_lsr_consistent_system_recovers_x(kind):
+    """b = A x*: the iteration reaches x* to near machine precision, far below
+    the sketch-and-solve start (Alg. 4.1 returns a machine-precision answer)."""
+    r = np.random.default_rng(11)
+    m, d = 3000, 24
+    A = r.standard_normal((m, d)) * np.exp(r.standard_normal(d))  # column scaling: kappa ~ 10s
+    xs = r.standard_normal(d)
+    b = A @ xs
+    x, resid, hist = lsr.precise_lsr(A, b, 4 * d, kind, 5, iters=40)
+    assert np.linalg.norm(x - xs) <= 1e-11 * np.linalg.norm(xs)
+    assert resid <= 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("kind", [sk.GAUSSIAN, sk.SRHT, sk.COUNTSKETCH])
+def test_precise_lsr_matches_lstsq_and_converges_fast(kind):
+    """Noisy right-hand side: the limit is the least-squares solution (numpy's
+    SVD-based lstsq, an independent route), and the preconditioned gradient
+    norm falls geometrically (kappa(A T) is a small constant for s >> d)."""
+    r = np.random.default_rng(12)
+    m, d = 4000, 20
+    A = r.standard_normal((m, d)) * np.abs(r.standard_t(2, size=(m, 1)))
+    b = A @ r.standard_normal(d) + 1e-2 * r.standard_normal(m)
+    x, resid, hist = lsr.precise_lsr(A, b, 16 * d, kind, 6, iters=30)
+    xl = np.linalg.lstsq(A, b, rcond=None)[0]
+    assert np.linalg.norm(x - xl) <= 1e-10 * np.linalg.norm(xl)
+    assert abs(resid - np.linalg.norm(A @ xl - b)) <= 1e-12 * resid
+    # ten iterations gain at least six orders of magnitude in the gradient
+    assert hist[10] <= 1e-6 * hist[0]
+
+
+def test_precise_lsr_zero_iterations_is_sketch_and_solve():
+    """With no iterations Alg. 4.1 returns x0 = T z0, the sketch-and-solve x~."""
+    r = np.random.default_rng(13)
+    A = r.standard_normal((500, 6))
+    b = r.standard_normal(500)
+    x0, _, _ = lsr.precise_lsr(A, b, 40, sk.COUNTSKETCH, 9, iters=0)
+    xs, _, _, _ = lsr.sketched_lsr(A, b, 40, sk.COUNTSKETCH, 9)
+    assert np.allclose(x0, xs, rtol=1e-12, atol=1e-13)
