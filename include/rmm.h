@@ -177,6 +177,23 @@ int rmm_sketched_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,
                      int64_t m, int64_t d, const void* A, int64_t lda,
                      const void* b, int64_t s, uint64_t seed, double* x,
                      double* resid, int32_t* status);
+/* Machine-precision least squares (Alg. 4.1, Sec. 4.3): the sketch of [A | b]
+ * gives the preconditioner T = R^{-1} (R from the FP64 CholeskyQR2 of S^T A)
+ * and the start x0 (the sketch-and-solve solution of rmm_sketched_lsr); then
+ * `iters` conjugate-gradient steps on the normal equations of A T (the
+ * reading of the printed gradient step, whose step size the paper leaves
+ * open), each one pass over A in FP64 arithmetic.  With s a small multiple
+ * of d, A T is well conditioned and each step gains a constant factor, so a
+ * few tens of steps reach x* = A^+ b to machine precision.  Arguments as for
+ * rmm_sketched_lsr plus iters >= 0 (0 returns x0); d <= 1024
+ * (RMM_ERR_UNSUPPORTED above).  x and resid = ||A x - b||_2 (if non-NULL)
+ * are FP64 device buffers. */
+int rmm_precise_lsr_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,
+                              int64_t m, int64_t d, int64_t s, size_t* bytes);
+int rmm_precise_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m,
+                    int64_t d, const void* A, int64_t lda, const void* b, int64_t s,
+                    uint64_t seed, int64_t iters, double* x, double* resid,
+                    int32_t* status);
 /* The two halves of rmm_sketched_lsr, for callers that sketch once and
  * solve separately.  rmm_lsr_solve: x = argmin ||Cs[:, :d] x - Cs[:, d]||_2
  * for an s x (d+1) sketched system Cs (ldc >= s, dtype dt, device), solved

@@ -66,6 +66,10 @@ def lib():
                          _vp, _i64, _vp, _vp, _i64, _vp],
             "rmm_lsr_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_sketched_lsr": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _vp, _vp],
+            "rmm_precise_lsr_workspace": [_vp, _i32, _i32, _i64, _i64, _i64,
+                                          ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_precise_lsr": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _i64, _vp,
+                                _vp, _vp],
             "rmm_plain_lsr_workspace": [_vp, _i32, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_plain_lsr": [_vp, _i32, _i64, _i64, _vp, _i64, _vp, _vp, _vp, _vp],
             "rmm_lsr_solve_workspace": [_vp, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -304,6 +308,24 @@ class Handle:
                                       seed, _ptr(x), _ptr(res), _ptr(status)), "rmm_sketched_lsr")
         return x, res, status
 
+    def precise_lsr(self, A: torch.Tensor, b: torch.Tensor, s: int, kind, seed: int, iters: int,
+                    residual: bool = True):
+        """Alg. 4.1: sketch-and-solve start, then `iters` preconditioned CG steps."""
+        A = colmajor(A)
+        m, d = A.shape
+        dt = _dt(A)
+        x = torch.empty(d, dtype=torch.float64, device=A.device)
+        res = torch.empty(1, dtype=torch.float64, device=A.device) if residual else None
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_precise_lsr_workspace(self._h, dt, _kind(kind), m, d, s, ctypes.byref(ws)),
+               "rmm_precise_lsr_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_precise_lsr(self._h, dt, _kind(kind), m, d, _ptr(A), _ld(A), _ptr(b), s,
+                                     seed, iters, _ptr(x), _ptr(res), _ptr(status)),
+               "rmm_precise_lsr")
+        return x, res, status
+
     def lsr_solve(self, Cs: torch.Tensor, d: int):
         """x = argmin ||Cs[:, :d] x - Cs[:, d]|| for a sketched system Cs."""
         s = Cs.shape[0]
@@ -475,6 +497,10 @@ def rsvd(A, k, p, q, seed, prec=PREC_NATIVE):
 
 def sketched_lsr(A, b, s, kind, seed, residual=True):
     return handle(A.device).sketched_lsr(A, b, s, kind, seed, residual)
+
+
+def precise_lsr(A, b, s, kind, seed, iters, residual=True):
+    return handle(A.device).precise_lsr(A, b, s, kind, seed, iters, residual)
 
 
 def plain_lsr(A, b, residual=True):

@@ -288,6 +288,58 @@ int lsr_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind, int64_t m, int d, const
   return RMM_OK;
 }
 
+// Alg. 4.1: the sketch-and-solve start x0 = T Q_Y^T (S^T b) and T = R_Y^{-1}
+// (T = R1 R2, the two inverse factors of CholeskyQR2), then `iters` steps of
+// preconditioned CG on A^T A x = A^T b with M = T T^T (refine.hip), each one
+// fused pass over A.  resid = ||A x - b|| from one more pass.
+template <typename T>
+int lsr_precise_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind, int64_t m, int d, const T* A,
+                     int64_t lda, const T* b, int64_t s, uint64_t seed, int64_t iters, double* x,
+                     double* resid, int32_t* status, size_t* bytes) {
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  T* Cs = ws.take<T>((size_t)s * (d + 1));
+  double* Csd = ws.take<double>((size_t)s * (d + 1));
+  LsBufs lb = take_ls(ws, s, d);
+  double* Tm = ws.take<double>((size_t)d * d);
+  double* M = ws.take<double>((size_t)d * d);
+  double* g = ws.take<double>((size_t)d);
+  double* y = ws.take<double>((size_t)d);
+  double* p = ws.take<double>((size_t)d);
+  double* sc = ws.take<double>(4);
+  double* part = ws.take<double>(refine_part_elems(h, d));
+  size_t scratch = sketch_scratch<T>(h, kind, m, d + 1, s);
+  scratch = smax(scratch, ls_scratch(h, s, d));
+  scratch = smax(scratch, gemm_workspace<double>(h, d, d, d));
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  RMM_TRY(zero_status(h, status));
+  {
+    const size_t mark = ws.off;
+    RMM_TRY(run_sketch<T>(h, kind, m, d, A, lda, b, s, seed, Cs, s, ws));
+    ws.off = mark;
+  }
+  RMM_TRY((copy_cast<T, double>(h, s, d + 1, Cs, s, Csd, s)));
+  RMM_TRY(ls_solve(h, s, d, Csd, lb, x, status, ws));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, d, d, d, lb.R1, d, lb.R2, d, 1.0,
+                                                Tm, d, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, false, true, d, d, d, Tm, d, Tm, d, 1.0, M, d,
+                                                ws)));
+  RMM_TRY(normal_pass<T>(h, m, d, A, lda, b, x, part));
+  RMM_TRY(pcg_init(h, d, part, M, g, y, p, sc));
+  for (int64_t t = 0; t < iters; ++t) {
+    RMM_TRY(normal_pass<T>(h, m, d, A, lda, nullptr, p, part));
+    RMM_TRY(pcg_step(h, d, part, M, x, g, y, p, sc));
+  }
+  if (resid) {
+    RMM_TRY(normal_pass<T>(h, m, d, A, lda, b, x, part));
+    RMM_TRY(pass_resid(h, d, part, resid));
+  }
+  return RMM_OK;
+}
+
 // exact solution by the normal equations in fp64: (A^T A) x = A^T b
 template <typename T>
 int plain_impl(rmm_ctx* h, bool run, int64_t m, int d, const T* A, int64_t lda, const T* b,
@@ -404,6 +456,35 @@ int rmm_sketched_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m
                            x, resid, status, nullptr);
   return lsr_impl<double>(h, true, kind, m, (int)d, (const double*)A, lda, (const double*)b, s, seed,
                           x, resid, status, nullptr);
+}
+
+int rmm_precise_lsr_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m,
+                              int64_t d, int64_t s, size_t* bytes) {
+  if (!bytes || !kind_ok(kind)) return RMM_ERR_INVALID_ARG;
+  RMM_TRY(lsr_args(h, dt, m, d, s));
+  if (d > 1024) return RMM_ERR_UNSUPPORTED;
+  if (dt == RMM_F32)
+    return lsr_precise_impl<float>(h, false, kind, m, (int)d, nullptr, m, nullptr, s, 0, 0,
+                                   nullptr, nullptr, nullptr, bytes);
+  return lsr_precise_impl<double>(h, false, kind, m, (int)d, nullptr, m, nullptr, s, 0, 0,
+                                  nullptr, nullptr, nullptr, bytes);
+}
+
+int rmm_precise_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m, int64_t d,
+                    const void* A, int64_t lda, const void* b, int64_t s, uint64_t seed,
+                    int64_t iters, double* x, double* resid, int32_t* status) {
+  RMM_TRY(lsr_args(h, dt, m, d, s));
+  if (!kind_ok(kind) || !A || !b || !x || ld_bad(lda, m) || iters < 0) return RMM_ERR_INVALID_ARG;
+  if (kind == RMM_SRHT) {
+    const int k = ceil_log2((uint64_t)m);
+    if (s > (1ll << k)) return RMM_ERR_INVALID_ARG;
+  }
+  if (d > 1024) return RMM_ERR_UNSUPPORTED;
+  if (dt == RMM_F32)
+    return lsr_precise_impl<float>(h, true, kind, m, (int)d, (const float*)A, lda,
+                                   (const float*)b, s, seed, iters, x, resid, status, nullptr);
+  return lsr_precise_impl<double>(h, true, kind, m, (int)d, (const double*)A, lda,
+                                  (const double*)b, s, seed, iters, x, resid, status, nullptr);
 }
 
 int rmm_lsr_solve_workspace(rmm_handle h, int64_t s, int64_t d, size_t* bytes) {

@@ -45,6 +45,20 @@ template <typename T>
 int project_tn(rmm_ctx* h, int64_t m, int ncols, const T* A, int64_t lda, const T* Qm, int64_t ldq,
                int64_t s, T* Z, int64_t ldz, Carver& ws);
 
+// Machine-precision LSR iterations (refine.hip): one fused pass over A giving
+// per-workgroup partials of A^T r and ||r||^2 for r = [b] - A p (G = refine_groups
+// partial rows of d + 1 doubles), and the one-workgroup CG steps.
+int refine_groups(const rmm_ctx* h);
+size_t refine_part_elems(const rmm_ctx* h, int d);  // doubles of the `part` buffer
+template <typename T>
+int normal_pass(const rmm_ctx* h, int64_t m, int d, const T* A, int64_t lda, const T* b,
+                const double* p, double* part);
+int pcg_init(const rmm_ctx* h, int d, const double* part, const double* M, double* g, double* y,
+             double* p, double* sc);
+int pcg_step(const rmm_ctx* h, int d, const double* part, const double* M, double* x, double* g,
+             double* y, double* p, double* sc);
+int pass_resid(const rmm_ctx* h, int d, const double* part, double* out);
+
 int launch_sample_indices_u32(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
                               uint32_t tag, uint64_t seed, uint32_t* out);
 int launch_sample_indices_i64(const rmm_ctx* h, uint64_t domain, int k, int64_t s,

@@ -187,3 +187,74 @@ def test_lsr_config_full_size(h, lsr_config, name, kind):
     xp, rp, stp = h.plain_lsr(Ad, bd)
     ratio = (res.item() / rp.item()) ** 2
     assert 1.0 - 1e-6 <= ratio < 1.5, ratio
+
+
+# ---- machine-precision LSR (Alg. 4.1) -----------------------------------------
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name,kind", KINDS)
+def test_precise_lsr_parity(h, dtype, name, kind):
+    """x after the iterations against the oracle's Alg. 4.1 and against the
+    least-squares solution of the same (FP32-stored, exactly promoted) data."""
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    A, b, xs = synth.lsr_fp32(seed=21, m=7000, d=24, dtype=npdt)
+    A64, b64 = A.astype(np.float64), b.astype(np.float64)
+    x, res, st = h.precise_lsr(dev(A), dev(b), 96, name, 5, 30)
+    assert int(st.item()) == 0
+    xo, ro, _ = olsr.precise_lsr(A64, b64, 96, kind, 5, 30, fp64=(dtype == torch.float64))
+    xl = np.linalg.lstsq(A64, b64, rcond=None)[0]
+    k = kappa(A64)
+    assert rel(host(x), xl) <= 1e-12 * k
+    assert rel(host(x), xo) <= 1e-12 * k
+    rl = np.linalg.norm(A64 @ xl - b64)
+    assert abs(res.item() - rl) <= 1e-12 * rl
+
+
+@pytest.mark.parametrize("name,kind", KINDS)
+def test_precise_lsr_zero_iterations_is_sketch_and_solve(h, name, kind):
+    A, b, xs = synth.lsr_fp32(seed=22, m=3000, d=12, dtype=np.float64)
+    x0, r0, _ = h.precise_lsr(dev(A), dev(b), 64, name, 8, 0)
+    xt, rt, _ = h.sketched_lsr(dev(A), dev(b), 64, name, 8)
+    assert rel(host(x0), host(xt)) < 1e-13
+    assert abs(r0.item() - rt.item()) <= 1e-12 * rt.item()
+
+
+@pytest.mark.parametrize("name,kind", KINDS)
+def test_precise_lsr_consistent_system(h, name, kind):
+    r = np.random.default_rng(23)
+    A = r.standard_normal((5000, 32)) * np.exp(r.standard_normal(32))
+    xs = r.standard_normal(32)
+    b = A @ xs
+    x, res, st = h.precise_lsr(dev(A), dev(b), 128, name, 4, 40)
+    assert rel(host(x), xs) < 1e-12 * kappa(A)
+    assert res.item() < 1e-11 * np.linalg.norm(b)
+
+
+def test_precise_lsr_invalid(h):
+    A = torch.randn(100, 4, dtype=torch.float64, device="cuda")
+    b = torch.randn(100, dtype=torch.float64, device="cuda")
+    with pytest.raises(rmm.RmmError):
+        h.precise_lsr(A, b, 16, "gaussian", 1, -1)
+    with pytest.raises(rmm.RmmError):
+        h.precise_lsr(A, b, 2, "gaussian", 1, 5)  # s < d
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,kind", KINDS)
+def test_precise_lsr_config_full_size(h, lsr_config, name, kind):
+    """2^20 x 256 fp32, s = 4096, 30 steps: the optimality condition of least
+    squares holds to FP64 level (||A^T r|| tiny against ||A||_F ||r||, checked
+    with an independent FP64 torch product), the residual reaches the exact
+    one, and the sketch-and-solve start was (1+eps)^2 above it."""
+    A, b = lsr_config
+    seed = synth.sketch_seed(2)
+    Ad, bd = dev(A), dev(b)
+    x, res, st = h.precise_lsr(Ad, bd, 4096, name, seed, 30)
+    assert int(st.item()) == 0
+    A64 = Ad.double()
+    r = bd.double() - A64 @ x
+    g = A64.t().contiguous() @ r
+    assert (g.norm() / (A64.norm() * r.norm())).item() < 1e-12
+    assert abs(res.item() - r.norm().item()) <= 1e-12 * r.norm().item()
+    x0, r0, _ = h.sketched_lsr(Ad, bd, 4096, name, seed)
+    assert res.item() <= r0.item()
