@@ -457,6 +457,20 @@ def main():
         out["plain_lsr"] = {"p50_ms": percentile(ts, 50), "p99_ms": percentile(ts, 99),
                             "method": "fp64 normal equations on the GPU"}
         out["objective_ratio"] = {k: (float(res[k].item()) / float(rp.item())) ** 2 for k in kinds}
+        # machine-precision LSR (Alg. 4.1): sketch-and-solve start, 20 CG steps
+        # (one fused FP64 pass over A each); objective ratio against the
+        # normal-equation solve, and per-step time from the 0- and 20-step runs
+        prec = {}
+        for k in ("countsketch", "srht"):
+            ts0 = lat(lambda: h.precise_lsr(Ad, bd, s, k, seed, 0), R)
+            ts = lat(lambda: h.precise_lsr(Ad, bd, s, k, seed, 20), R)
+            _, rr, _ = h.precise_lsr(Ad, bd, s, k, seed, 20)
+            step_ms = (percentile(ts, 50) - percentile(ts0, 50)) / 20
+            prec[k] = {"iters": 20, "p50_ms": percentile(ts, 50), "p99_ms": percentile(ts, 99),
+                       "ms_per_step": step_ms,
+                       "step_hbm_gbs": m * d * 4 / (step_ms * 1e-3) / 1e9,
+                       "objective_ratio": (float(rr.item()) / float(rp.item())) ** 2}
+        out["precise_lsr"] = prec
         A1, _ = synth.rsvd_fp64()
         A1d = torch.from_numpy(A1.T.copy()).cuda().t()
         h.rsvd(A1d, 20, 10, 2, synth.sketch_seed(1))
