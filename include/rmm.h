@@ -80,6 +80,24 @@ typedef enum {
 /* Creates a handle bound to HIP device `device`.  Allocates host memory only. */
 int rmm_create(rmm_handle* h, int device);
 int rmm_destroy(rmm_handle h);
+/* Autotuning of the dense products inside the drivers (rsvd, the LSR solves,
+ * Nystrom): with autotune on, the first product of each new shape (types,
+ * transposes, M, N, K) runs every candidate launch plan (column tile,
+ * workgroups per CU of the K split, 128 x 128 fast path or not) twice on the
+ * caller's operands, timed on the handle's stream, and the fastest is kept in
+ * the handle for that shape; later calls use it whether or not autotune is
+ * on.  Tuning synchronizes the stream: off by default, not during graph
+ * capture.  The plans can be saved to and loaded from a text file (one
+ * "key<TAB>plan" line per shape); rmm_create loads the file named by the
+ * environment variable RMM_TUNE_CACHE when it is set.  A tuned plan changes
+ * only the order of the FP64/FP32 partial sums, within the stated
+ * tolerances; the same handle state gives bitwise-identical results.
+ * count: the number of shapes with a kept plan. */
+int rmm_set_autotune(rmm_handle h, int on);
+int rmm_autotune_count(rmm_handle h, int64_t* count);
+int rmm_autotune_save(rmm_handle h, const char* path);
+int rmm_autotune_load(rmm_handle h, const char* path);
+
 /* Sets the hipStream_t (passed as void*) on which later calls enqueue work. */
 int rmm_set_stream(rmm_handle h, void* hip_stream);
 /* Registers caller-owned device scratch memory (256-byte aligned). */

@@ -59,6 +59,10 @@ def lib():
             "rmm_set_stream": [_vp, _vp],
             "rmm_set_workspace": [_vp, _vp, ctypes.c_size_t],
             "rmm_device_cus": [_vp, ctypes.POINTER(_i32)],
+            "rmm_set_autotune": [_vp, _i32],
+            "rmm_autotune_count": [_vp, ctypes.POINTER(_i64)],
+            "rmm_autotune_save": [_vp, ctypes.c_char_p],
+            "rmm_autotune_load": [_vp, ctypes.c_char_p],
             "rmm_sketch_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_sketch": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _i64],
             "rmm_rsvd_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -290,6 +294,21 @@ class Handle:
         _check(lib().rmm_rsvd(self._h, dt, prec, m, n, _ptr(A), _ld(A), k, p, q, seed, _ptr(U),
                               _ld(U), _ptr(sig), _ptr(V), _ld(V), _ptr(status)), "rmm_rsvd")
         return U, sig, V, status
+
+    # ---- autotuning of the dense products (rmm_set_autotune) -------------------
+    def set_autotune(self, on: bool = True):
+        _check(lib().rmm_set_autotune(self._h, 1 if on else 0), "rmm_set_autotune")
+
+    def autotune_count(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib().rmm_autotune_count(self._h, ctypes.byref(n)), "rmm_autotune_count")
+        return n.value
+
+    def autotune_save(self, path: str):
+        _check(lib().rmm_autotune_save(self._h, path.encode()), "rmm_autotune_save")
+
+    def autotune_load(self, path: str):
+        _check(lib().rmm_autotune_load(self._h, path.encode()), "rmm_autotune_load")
 
     # ---- least squares -------------------------------------------------------
     def sketched_lsr(self, A: torch.Tensor, b: torch.Tensor, s: int, kind, seed: int,

@@ -2,6 +2,10 @@
 #include <math.h>
 #include <new>
 
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
 #include "common.hpp"
 #include "ops.hpp"
 #include "rng.hpp"
@@ -104,7 +108,44 @@ int rmm_create(rmm_handle* h, int device) {
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess &&
       v > 0)
     c->lds_bytes = (size_t)v;
+  if (const char* path = getenv("RMM_TUNE_CACHE")) (void)rmm_autotune_load(c, path);
   *h = c;
+  return RMM_OK;
+}
+
+int rmm_set_autotune(rmm_handle h, int on) {
+  if (!h) return RMM_ERR_INVALID_ARG;
+  h->autotune = on != 0;
+  return RMM_OK;
+}
+
+int rmm_autotune_count(rmm_handle h, int64_t* count) {
+  if (!h || !count) return RMM_ERR_INVALID_ARG;
+  *count = (int64_t)h->plans.size();
+  return RMM_OK;
+}
+
+int rmm_autotune_save(rmm_handle h, const char* path) {
+  if (!h || !path) return RMM_ERR_INVALID_ARG;
+  FILE* f = fopen(path, "w");
+  if (!f) return RMM_ERR_INVALID_ARG;
+  for (const auto& kv : h->plans) fprintf(f, "%s\t%d\n", kv.first.c_str(), kv.second);
+  return fclose(f) == 0 ? RMM_OK : RMM_ERR_INVALID_ARG;
+}
+
+int rmm_autotune_load(rmm_handle h, const char* path) {
+  if (!h || !path) return RMM_ERR_INVALID_ARG;
+  FILE* f = fopen(path, "r");
+  if (!f) return RMM_ERR_INVALID_ARG;
+  char line[512];
+  while (fgets(line, sizeof(line), f)) {
+    char* tab = strchr(line, '\t');
+    if (!tab) continue;
+    *tab = '\0';
+    const int plan = atoi(tab + 1);
+    if (plan >= 0) h->plans[std::string(line)] = plan;
+  }
+  fclose(f);
   return RMM_OK;
 }
 

@@ -7,6 +7,8 @@
 
 #include "../../include/rmm.h"
 
+#include <map>
+#include <string>
 #include <vector>
 
 struct rmm_ctx {
@@ -17,6 +19,8 @@ struct rmm_ctx {
   int cus = 256;
   size_t lds_bytes = 65536;  // usable LDS per workgroup
   std::vector<unsigned char> table_host;  // staging of the last batch descriptor table
+  bool autotune = false;                  // time the candidate plans of new shapes
+  std::map<std::string, int> plans;       // tuned plan per kernel shape key
 };
 
 namespace rmm {

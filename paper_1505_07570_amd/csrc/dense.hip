@@ -261,14 +261,30 @@ namespace {
 struct GemmShape {
   int BM, BN, splits;
   int64_t kchunk;
+  bool nn;  // the 128 x 128 kernel may be used (untransposed, same types, aligned)
 };
 
-GemmShape gemm_shape(const rmm_ctx* h, int M, int N, int64_t K) {
+// Candidate launch plans of a product: column tile (0 = 128 above N = 64),
+// workgroups per CU targeted by the K split, and whether the 128 x 128 fast
+// path may be taken.  Plan 0 is the default; rmm_set_autotune times the
+// others on the first call of a shape and keeps the fastest per handle.
+struct GemmPlan {
+  int bn, per_cu;
+  bool nn;
+};
+constexpr GemmPlan kGemmPlans[] = {{0, 2, true}, {0, 1, true}, {0, 4, true}, {64, 2, true},
+                                   {0, 2, false}, {64, 4, false}};
+constexpr int kNumGemmPlans = sizeof(kGemmPlans) / sizeof(kGemmPlans[0]);
+constexpr int kMaxPlanPerCu = 4;
+
+GemmShape gemm_shape(const rmm_ctx* h, int M, int N, int64_t K, int plan = 0) {
+  const GemmPlan& pl = kGemmPlans[plan];
   GemmShape g;
   g.BM = 64;
-  g.BN = N > 64 ? 128 : 64;
+  g.BN = pl.bn ? pl.bn : (N > 64 ? 128 : 64);
+  g.nn = pl.nn;
   const int64_t tiles = (int64_t)((M + g.BM - 1) / g.BM) * ((N + g.BN - 1) / g.BN);
-  int64_t want = (2ll * h->cus + tiles - 1) / tiles;
+  int64_t want = ((int64_t)pl.per_cu * h->cus + tiles - 1) / tiles;
   const int64_t maxsplit = (K + 255) / 256;  // at least 256 K per split
   if (want > maxsplit) want = maxsplit;
   if (want < 1) want = 1;
@@ -296,19 +312,25 @@ int launch_gemm_t(const rmm_ctx* h, const GemmShape& g, int M, int N, int64_t K,
 
 }  // namespace
 
+// the partials of every candidate plan fit (any tuned plan can run)
 template <typename TC>
 size_t gemm_workspace(const rmm_ctx* h, int M, int N, int64_t K) {
-  const GemmShape g = gemm_shape(h, M, N, K);
+  size_t most = 0;
+  for (int p = 0; p < kNumGemmPlans; ++p) {
+    const GemmShape g = gemm_shape(h, M, N, K, p);
+    const size_t e = (size_t)g.splits * M * N;
+    if (e > most) most = e;
+  }
   Carver c(nullptr, 0);
-  c.take<TC>((size_t)g.splits * M * N);
+  c.take<TC>(most);
   return c.off;
 }
 
 template <typename TAI, typename TBI, typename TC, typename TO>
-int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, int64_t lda,
-         const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc, Carver& ws, double beta) {
-  if (M == 0 || N == 0) return RMM_OK;
-  const GemmShape g = gemm_shape(h, M, N, K);
+int gemm_plan(rmm_ctx* h, int plan, bool ta, bool tb, int M, int N, int64_t K, const TAI* A,
+              int64_t lda, const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc,
+              Carver& ws, double beta) {
+  const GemmShape g = gemm_shape(h, M, N, K, plan);
   const size_t mark = ws.off;
   TC* P = ws.take<TC>((size_t)g.splits * M * N);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
@@ -316,8 +338,8 @@ int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, in
   constexpr bool same = std::is_same<TAI, TC>::value && std::is_same<TBI, TC>::value;
   const int64_t va = 16 / sizeof(TC);
   if constexpr (same) {
-    if (!ta && !tb && N > 64 && (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 && lda % va == 0 &&
-        ldb % va == 0) {
+    if (g.nn && !ta && !tb && N > 64 && (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 &&
+        lda % va == 0 && ldb % va == 0) {
       dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 127) / 128), (unsigned)g.splits);
       hipLaunchKernelGGL((gemm_nn_kernel<TC>), grid, dim3(256), 0, h->stream, M, N, K,
                          (const TC*)A, lda, (const TC*)B, ldb, P, g.kchunk);
@@ -339,6 +361,59 @@ int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, in
                      alpha, beta, C, ldc);
   ws.off = mark;  // the partials are dead once the reduction is enqueued
   return launch_status();
+}
+
+// Tuning (rmm_set_autotune): each candidate plan runs twice on the caller's
+// operands, timed with events on the handle's stream (this synchronizes, so
+// it is off by default and not for graph capture); the fastest is kept for
+// the shape.  Products that accumulate into C (beta != 0) are not tuned.
+template <typename TAI, typename TBI, typename TC, typename TO>
+int gemm(rmm_ctx* h, bool ta, bool tb, int M, int N, int64_t K, const TAI* A, int64_t lda,
+         const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc, Carver& ws, double beta) {
+  if (M == 0 || N == 0) return RMM_OK;
+  const std::string key = "gemm " + std::to_string(sizeof(TAI)) + std::to_string(sizeof(TBI)) +
+                          std::to_string(sizeof(TC)) + std::to_string(sizeof(TO)) +
+                          (ta ? "t" : "n") + (tb ? "t" : "n") + " " + std::to_string(M) + " " +
+                          std::to_string(N) + " " + std::to_string(K);
+  const auto it = h->plans.find(key);
+  if (it != h->plans.end() && it->second >= 0 && it->second < kNumGemmPlans)
+    return gemm_plan<TAI, TBI, TC, TO>(h, it->second, ta, tb, M, N, K, A, lda, B, ldb, alpha, C,
+                                       ldc, ws, beta);
+  if (!h->autotune || beta != 0.0)
+    return gemm_plan<TAI, TBI, TC, TO>(h, 0, ta, tb, M, N, K, A, lda, B, ldb, alpha, C, ldc, ws,
+                                       beta);
+  hipEvent_t e0, e1;
+  RMM_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return RMM_ERR_HIP;
+  }
+  int best = 0;
+  float best_ms = 0.f;
+  int rc = RMM_OK;
+  for (int p = 0; p < kNumGemmPlans && rc == RMM_OK; ++p) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && rc == RMM_OK; ++rep) {
+      (void)hipEventRecord(e0, h->stream);
+      rc = gemm_plan<TAI, TBI, TC, TO>(h, p, ta, tb, M, N, K, A, lda, B, ldb, alpha, C, ldc, ws,
+                                       beta);
+      (void)hipEventRecord(e1, h->stream);
+      if (hipEventSynchronize(e1) != hipSuccess) rc = RMM_ERR_HIP;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+    }
+    if (rc == RMM_OK && (p == 0 || ms < best_ms)) {
+      best = p;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  RMM_TRY(rc);
+  h->plans[key] = best;
+  // C holds the last candidate's result; the kept plan writes it again so the
+  // output always comes from the plan later calls will use
+  return gemm_plan<TAI, TBI, TC, TO>(h, best, ta, tb, M, N, K, A, lda, B, ldb, alpha, C, ldc, ws,
+                                     beta);
 }
 
 // ---- elementwise helpers ---------------------------------------------------------

@@ -258,3 +258,29 @@ def test_precise_lsr_config_full_size(h, lsr_config, name, kind):
     assert abs(res.item() - r.norm().item()) <= 1e-12 * r.norm().item()
     x0, r0, _ = h.sketched_lsr(Ad, bd, 4096, name, seed)
     assert res.item() <= r0.item()
+
+
+# ---- autotuning of the dense products -------------------------------------------
+
+def test_autotune_plans_kept_saved_and_loaded(h, tmp_path):
+    """Tuning picks a plan per product shape; results stay at the untuned
+    ones' accuracy, repeat bitwise with the kept plans, and a handle that
+    loads the saved plans reproduces them bitwise."""
+    A, _ = synth.rsvd_fp64(seed=5, m=1024, n=256)
+    Ad = dev(A)
+    Ur, sr, Vr, _ = h.rsvd(Ad, 10, 6, 1, 3)
+    t = rmm.Handle()
+    t.set_autotune(True)
+    U1, s1, V1, st = t.rsvd(Ad, 10, 6, 1, 3)
+    assert int(st.item()) == 0 and t.autotune_count() > 0
+    assert rel(host(s1), host(sr)) < 1e-12
+    t.set_autotune(False)
+    U2, s2, V2, _ = t.rsvd(Ad, 10, 6, 1, 3)
+    assert torch.equal(s1, s2) and torch.equal(U1, U2) and torch.equal(V1, V2)
+    path = str(tmp_path / "plans.txt")
+    t.autotune_save(path)
+    u = rmm.Handle()
+    u.autotune_load(path)
+    assert u.autotune_count() == t.autotune_count()
+    U3, s3, V3, _ = u.rsvd(Ad, 10, 6, 1, 3)
+    assert torch.equal(s3, s2) and torch.equal(U3, U2) and torch.equal(V3, V2)
