@@ -40,6 +40,16 @@ struct Mfma<double> {
 
 constexpr int kBK = 16;
 
+// Epilogue: a partial tile of a split product is stored as is (alpha = 1,
+// beta = 0); an unsplit product whose output type is the compute type is
+// finished in place, with the arithmetic of gemm_reduce_kernel for one split.
+template <typename TC>
+__device__ __forceinline__ void gemm_store(TC* p, TC acc, double alpha, double beta) {
+  double v = alpha * (double)acc;
+  if (beta != 0.0) v += beta * (double)*p;
+  *p = (TC)v;
+}
+
 // op(X)[i, k] for a column-major X: X[i + k*ld] or, transposed, X[k + i*ld]
 template <typename T, bool TR>
 __device__ __forceinline__ T opget(const T* __restrict__ X, int64_t ld, int64_t i, int64_t k) {
@@ -49,7 +59,8 @@ __device__ __forceinline__ T opget(const T* __restrict__ X, int64_t ld, int64_t 
 template <typename TAI, typename TBI, typename TC, bool TA, bool TB, int BM, int BN>
 __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int64_t K, const TAI* __restrict__ A,
                                                    int64_t lda, const TBI* __restrict__ B, int64_t ldb,
-                                                   TC* __restrict__ P, int64_t kchunk) {
+                                                   TC* __restrict__ P, int64_t kchunk, int64_t ldp,
+                                                   double alpha, double beta) {
   using F = Mfma<TC>;
   using acc_t = typename F::acc;
   constexpr int WM = BM / 2, WN = BN / 2;  // wave tile
@@ -69,24 +80,49 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int64_t K, cons
     for (int b = 0; b < TN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
   const int g = lane >> 4, c16 = lane & 15;
-  for (int64_t kb = k0; kb < k1; kb += kBK) {
-    // stage op(A)[m0 .. m0+BM, kb .. kb+BK] and op(B)[kb .., n0 ..]
-    for (int e = tid; e < BM * kBK; e += 256) {
+  // operands of the next K stage are loaded into registers while the
+  // current one is multiplied (one LDS buffer, two barriers per stage)
+  constexpr int AE = BM * kBK / 256, BE = BN * kBK / 256;
+  TC ra[AE], rb[BE];
+  auto load = [&](int64_t kb) {
+#pragma unroll
+    for (int u = 0; u < AE; ++u) {
+      const int e = tid + 256 * u;
       int i, kk;
       if (TA) { kk = e % kBK; i = e / kBK; } else { i = e % BM; kk = e / BM; }
       const int64_t gi = m0 + i, gk = kb + kk;
-      As[kk][i] = (gi < M && gk < k1) ? (TC)opget<TAI, TA>(A, lda, gi, gk) : TC(0);
+      ra[u] = (gi < M && gk < k1) ? (TC)opget<TAI, TA>(A, lda, gi, gk) : TC(0);
     }
-    for (int e = tid; e < BN * kBK; e += 256) {
+#pragma unroll
+    for (int u = 0; u < BE; ++u) {
+      const int e = tid + 256 * u;
       int j, kk;
       // op(B)[k, j]: B[k + j*ldb] (k fastest) or, transposed, B[j + k*ldb]
       if (TB) { j = e % BN; kk = e / BN; } else { kk = e % kBK; j = e / kBK; }
       const int64_t gj = n0 + j, gk = kb + kk;
       TC v = TC(0);
       if (gj < N && gk < k1) v = (TC)(TB ? B[gj + gk * ldb] : B[gk + gj * ldb]);
-      Bs[kk][j] = v;
+      rb[u] = v;
+    }
+  };
+  if (k0 < k1) load(k0);
+  for (int64_t kb = k0; kb < k1; kb += kBK) {
+#pragma unroll
+    for (int u = 0; u < AE; ++u) {
+      const int e = tid + 256 * u;
+      int i, kk;
+      if (TA) { kk = e % kBK; i = e / kBK; } else { i = e % BM; kk = e / BM; }
+      As[kk][i] = ra[u];
+    }
+#pragma unroll
+    for (int u = 0; u < BE; ++u) {
+      const int e = tid + 256 * u;
+      int j, kk;
+      if (TB) { j = e % BN; kk = e / BN; } else { kk = e % kBK; j = e / kBK; }
+      Bs[kk][j] = rb[u];
     }
     __syncthreads();
+    if (kb + kBK < k1) load(kb + kBK);
 #pragma unroll
     for (int ks = 0; ks < kBK; ks += 4) {
       TC av[TM], bv[TN];
@@ -110,7 +146,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int64_t K, cons
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = m0 + wm * WM + a * 16 + F::row(g, v);
-        if (i < M && j < N) dst[i + (int64_t)j * M] = acc[a][b][v];
+        if (i < M && j < N) gemm_store(dst + i + (int64_t)j * ldp, acc[a][b][v], alpha, beta);
       }
     }
 }
@@ -122,7 +158,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int64_t K, cons
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_nn_kernel(int M, int N, int64_t K, const T* __restrict__ A,
                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
-                                                      T* __restrict__ P, int64_t kchunk) {
+                                                      T* __restrict__ P, int64_t kchunk, int64_t ldp,
+                                                      double alpha, double beta) {
   using F = Mfma<T>;
   using acc_t = typename F::acc;
   constexpr int BM = 128, BN = 128, BK = kBK;
@@ -238,9 +275,55 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(int M, int N, int64_t K, c
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = m0 + wm * 64 + a * 16 + F::row(g, v);
-        if (i < M && j < N) dst[i + (int64_t)j * M] = acc[a][b][v];
+        if (i < M && j < N) gemm_store(dst + i + (int64_t)j * ldp, acc[a][b][v], alpha, beta);
       }
     }
+}
+
+// y = op(A)^T x for one right-hand column (N = 1, A transposed): a wave
+// per output, lanes striding along K with 16-byte loads when the columns
+// allow them; the K range may be split over gridDim.y like the products.
+// Lane sums are combined by a fixed butterfly, so results are reproducible.
+template <typename TAI, typename TBI, typename TC, bool VEC>
+__global__ __launch_bounds__(256) void gemv_tn_kernel(int M, int64_t K, const TAI* __restrict__ A,
+                                                      int64_t lda, const TBI* __restrict__ x,
+                                                      TC* __restrict__ P, int64_t kchunk,
+                                                      double alpha, double beta) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= M) return;  // whole waves
+  const int64_t k0 = (int64_t)blockIdx.y * kchunk;
+  const int64_t k1 = k0 + kchunk < K ? k0 + kchunk : K;
+  const TAI* a = A + (int64_t)i * lda;
+  TC acc = TC(0);
+  if constexpr (VEC && sizeof(TAI) == sizeof(TBI)) {
+    constexpr int V = 16 / (int)sizeof(TAI);
+    for (int64_t k = k0 + (int64_t)lane * V; k < k1; k += 64 * V) {
+      TAI av[V];
+      TBI xv[V];
+      *reinterpret_cast<uint4*>(av) = *reinterpret_cast<const uint4*>(a + k);
+      *reinterpret_cast<uint4*>(xv) = *reinterpret_cast<const uint4*>(x + k);
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc = fma((TC)av[v], (TC)xv[v], acc);
+    }
+  } else {
+    for (int64_t k = k0 + lane; k < k1; k += 64) acc = fma((TC)a[k], (TC)x[k], acc);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) gemm_store(P + (int64_t)blockIdx.y * M + i, acc, alpha, beta);
+}
+
+// K split of the one-column product: enough waves to cover the CUs a few
+// times, at least 1024 elements per split, split boundaries on 256
+static int64_t gemv_kchunk(const rmm_ctx* h, int M, int64_t K) {
+  int64_t want = (4LL * h->cus + M - 1) / M;
+  const int64_t most = (K + 1023) / 1024;
+  if (want > most) want = most;
+  if (want < 1) want = 1;
+  int64_t kc = (K + want - 1) / want;
+  kc = (kc + 255) / 256 * 256;
+  return kc < 256 ? 256 : kc;
 }
 
 template <typename TC, typename TO>
@@ -298,15 +381,16 @@ GemmShape gemm_shape(const rmm_ctx* h, int M, int N, int64_t K, int plan = 0) {
 
 template <typename TAI, typename TBI, typename TC, bool TA, bool TB>
 int launch_gemm_t(const rmm_ctx* h, const GemmShape& g, int M, int N, int64_t K, const TAI* A,
-                  int64_t lda, const TBI* B, int64_t ldb, TC* P) {
+                  int64_t lda, const TBI* B, int64_t ldb, TC* P, int64_t ldp, double alpha,
+                  double beta) {
   dim3 grid((unsigned)((M + g.BM - 1) / g.BM), (unsigned)((N + g.BN - 1) / g.BN),
             (unsigned)g.splits);
   if (g.BN == 128)
     hipLaunchKernelGGL((gemm_kernel<TAI, TBI, TC, TA, TB, 64, 128>), grid, dim3(256), 0, h->stream,
-                       M, N, K, A, lda, B, ldb, P, g.kchunk);
+                       M, N, K, A, lda, B, ldb, P, g.kchunk, ldp, alpha, beta);
   else
     hipLaunchKernelGGL((gemm_kernel<TAI, TBI, TC, TA, TB, 64, 64>), grid, dim3(256), 0, h->stream,
-                       M, N, K, A, lda, B, ldb, P, g.kchunk);
+                       M, N, K, A, lda, B, ldb, P, g.kchunk, ldp, alpha, beta);
   return launch_status();
 }
 
@@ -321,6 +405,11 @@ size_t gemm_workspace(const rmm_ctx* h, int M, int N, int64_t K) {
     const size_t e = (size_t)g.splits * M * N;
     if (e > most) most = e;
   }
+  if (N == 1 && K > 0) {
+    const int64_t kc = gemv_kchunk(h, M, K);
+    const size_t e = (size_t)((K + kc - 1) / kc) * M;
+    if (e > most) most = e;
+  }
   Carver c(nullptr, 0);
   c.take<TC>(most);
   return c.off;
@@ -330,32 +419,73 @@ template <typename TAI, typename TBI, typename TC, typename TO>
 int gemm_plan(rmm_ctx* h, int plan, bool ta, bool tb, int M, int N, int64_t K, const TAI* A,
               int64_t lda, const TBI* B, int64_t ldb, double alpha, TO* C, int64_t ldc,
               Carver& ws, double beta) {
+  if (ta && !tb && N == 1 && K > 0) {
+    const int64_t kc = gemv_kchunk(h, M, K);
+    const int splits = (int)((K + kc - 1) / kc);
+    const size_t mark = ws.off;
+    bool direct = false;
+    if constexpr (std::is_same<TO, TC>::value) direct = splits == 1;
+    TC* P = direct ? (TC*)C : ws.take<TC>((size_t)splits * M);
+    if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+    const double pa = direct ? alpha : 1.0, pb = direct ? beta : 0.0;
+    constexpr int V = 16 / (int)sizeof(TAI);
+    const bool vec = sizeof(TAI) == sizeof(TBI) && (uintptr_t)A % 16 == 0 &&
+                     (uintptr_t)B % 16 == 0 && lda % V == 0 && K % V == 0;
+    dim3 grid((unsigned)((M + 3) / 4), (unsigned)splits);
+    if (vec && sizeof(TAI) == sizeof(TBI))
+      hipLaunchKernelGGL((gemv_tn_kernel<TAI, TBI, TC, sizeof(TAI) == sizeof(TBI)>), grid, dim3(256),
+                         0, h->stream, M, K, A, lda, B, P, kc, pa, pb);
+    else
+      hipLaunchKernelGGL((gemv_tn_kernel<TAI, TBI, TC, false>), grid, dim3(256), 0, h->stream, M, K,
+                         A, lda, B, P, kc, pa, pb);
+    RMM_TRY(launch_status());
+    if (!direct) {
+      dim3 rgrid((unsigned)((M + 255) / 256), 1u);
+      hipLaunchKernelGGL((gemm_reduce_kernel<TC, TO>), rgrid, dim3(256), 0, h->stream, M, 1, P,
+                         splits, alpha, beta, C, ldc);
+    }
+    ws.off = mark;
+    return launch_status();
+  }
   const GemmShape g = gemm_shape(h, M, N, K, plan);
   const size_t mark = ws.off;
-  TC* P = ws.take<TC>((size_t)g.splits * M * N);
+  // one split with the output in the compute type: the product kernel
+  // finishes C itself and no partials or reduction are needed
+  bool direct = false;
+  if constexpr (std::is_same<TO, TC>::value) direct = g.splits == 1;
+  TC* P = direct ? (TC*)C : ws.take<TC>((size_t)g.splits * M * N);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const int64_t ldp = direct ? ldc : M;
+  const double pa = direct ? alpha : 1.0, pb = direct ? beta : 0.0;
   int rc;
   constexpr bool same = std::is_same<TAI, TC>::value && std::is_same<TBI, TC>::value;
   const int64_t va = 16 / sizeof(TC);
+  bool fast = false;
   if constexpr (same) {
     if (g.nn && !ta && !tb && N > 64 && (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 &&
         lda % va == 0 && ldb % va == 0) {
       dim3 grid((unsigned)((M + 127) / 128), (unsigned)((N + 127) / 128), (unsigned)g.splits);
       hipLaunchKernelGGL((gemm_nn_kernel<TC>), grid, dim3(256), 0, h->stream, M, N, K,
-                         (const TC*)A, lda, (const TC*)B, ldb, P, g.kchunk);
+                         (const TC*)A, lda, (const TC*)B, ldb, P, g.kchunk, ldp, pa, pb);
       RMM_TRY(launch_status());
-      dim3 rgrid((unsigned)((M + 255) / 256), (unsigned)N);
-      hipLaunchKernelGGL((gemm_reduce_kernel<TC, TO>), rgrid, dim3(256), 0, h->stream, M, N, P,
-                         g.splits, alpha, beta, C, ldc);
-      ws.off = mark;
-      return launch_status();
+      fast = true;
     }
   }
-  if (!ta && !tb) rc = launch_gemm_t<TAI, TBI, TC, false, false>(h, g, M, N, K, A, lda, B, ldb, P);
-  else if (ta && !tb) rc = launch_gemm_t<TAI, TBI, TC, true, false>(h, g, M, N, K, A, lda, B, ldb, P);
-  else if (!ta && tb) rc = launch_gemm_t<TAI, TBI, TC, false, true>(h, g, M, N, K, A, lda, B, ldb, P);
-  else rc = launch_gemm_t<TAI, TBI, TC, true, true>(h, g, M, N, K, A, lda, B, ldb, P);
-  RMM_TRY(rc);
+  if (!fast) {
+    if (!ta && !tb)
+      rc = launch_gemm_t<TAI, TBI, TC, false, false>(h, g, M, N, K, A, lda, B, ldb, P, ldp, pa, pb);
+    else if (ta && !tb)
+      rc = launch_gemm_t<TAI, TBI, TC, true, false>(h, g, M, N, K, A, lda, B, ldb, P, ldp, pa, pb);
+    else if (!ta && tb)
+      rc = launch_gemm_t<TAI, TBI, TC, false, true>(h, g, M, N, K, A, lda, B, ldb, P, ldp, pa, pb);
+    else
+      rc = launch_gemm_t<TAI, TBI, TC, true, true>(h, g, M, N, K, A, lda, B, ldb, P, ldp, pa, pb);
+    RMM_TRY(rc);
+  }
+  if (direct) {
+    ws.off = mark;
+    return RMM_OK;
+  }
   dim3 grid((unsigned)((M + 255) / 256), (unsigned)N);
   hipLaunchKernelGGL((gemm_reduce_kernel<TC, TO>), grid, dim3(256), 0, h->stream, M, N, P, g.splits,
                      alpha, beta, C, ldc);

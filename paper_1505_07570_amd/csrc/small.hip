@@ -1,8 +1,8 @@
 // Small FP64 factorizations that run in a single workgroup: the Cholesky
 // step of CholeskyQR2 with the triangular inverse, and the cyclic Jacobi
 // eigensolver used for the small SVD of the projected matrix.  These sit on
-// the latency path of every driver call; the matrices are at most 128 x 128
-// in LDS (larger Cholesky factors are worked on in global memory).
+// the latency path of every driver call; a Cholesky leaf is at most
+// 128 x 128 and lives in registers (larger factors are split recursively).
 #include "common.hpp"
 #include "dense.hpp"
 
@@ -25,102 +25,153 @@ __device__ __forceinline__ void or_status(int32_t* status, int32_t flag) {
 //   R = D^{1/2} L~^T,   R^{-1}[c][j] = L~^{-1}[j][c] / sqrt(p_j)   (c <= j).
 // Entry (i, c) changes in step j < i only for c >= i (Schur complement) or
 // c <= j (inverse part); there it loses f_i r_c with f_i = W[j][i] / p_j and
-// r = row j of W with r_j = 1.
+// r = row j of W with r_j = 1.  The multiplier f_i depends on row j alone,
+// so the updates a row receives from a run of pivots can be applied
+// together once those pivot rows are final.
 //
-// W lives in registers: thread (r0, c0) of the TR x TC thread grid owns rows
-// r0 + TR a and columns c0 + TC b (a < NA, b < NB): 32 x 32 threads with
-// 4 x 4 entries each up to 128, 8 x 32 threads with 4 x 1 entries up to 32
-// (fewer waves make the per-step barrier cheaper).  Step j only needs row j: its
-// owners publish it, with 1 / p_j, into one of two LDS row buffers right
-// after their step j - 1 update, so one barrier per step suffices.  All LDS
-// reads of a step are issued together, and the per-entry condition is a
-// select, so a step has a single LDS wait and no branches per entry.
+// Blocked by panels of 8 rows: wave q holds rows 8q .. 8q+7 in registers,
+// lane t columns t and t + 64.  Panel p is eliminated within wave p (pivots
+// and multipliers broadcast with readlane, no barrier); the wave then
+// publishes the 8 pivot rows and the rows scaled by 1/p_j (the multipliers
+// of every later row, stored column-major so a row's 8 multipliers are
+// contiguous) to LDS, and after one barrier every later wave subtracts the
+// 8 rank-one terms from its rows.  Wave p + 1 does that before factoring its
+// own panel, while the waves behind it are still updating; the LDS panel
+// buffers alternate, so one barrier per panel suffices.
 // The drop test of pivot j compares against orig[j * ostride] (the diagonal
 // of the matrix the caller considers original), or G_jj when orig is null;
 // a dropped pivot eliminates nothing and gives a zero column of R^{-1}.
-template <int TR, int TC, int NA, int NB>
-__global__ __launch_bounds__(TR * TC) void cholinv_reg_kernel(
+constexpr int kPanel = 8;
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int NH>
+__global__ __launch_bounds__(1024) void cholinv_panel_kernel(
     int l, const double* __restrict__ G, int64_t ldg, double tau, const double* orig,
     int64_t ostride, double* __restrict__ Rinv, int64_t ldr, double* __restrict__ diag,
     int32_t* status) {
-  __shared__ double rowbuf[2][kLdsMaxL];
-  __shared__ double invbuf[2];
-  __shared__ double sorig[kLdsMaxL];
+  // pivot rows (r_j = 1) and multipliers [i][jj] = W[j][i] / p_j; a
+  // multiplier row is padded to 9 doubles so the column-wise stores of a
+  // panel do not collide in the LDS banks
+  __shared__ double prow[2][kPanel][kLdsMaxL];
+  __shared__ double pmul[2][kLdsMaxL][kPanel + 1];
   __shared__ double piv[kLdsMaxL];
-  const int tid = threadIdx.x;
-  const int c0 = tid % TC, r0 = tid / TC;
-  double w[NA][NB];
+  const int lane = threadIdx.x & 63;
+  const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int np = (l + kPanel - 1) / kPanel;  // one wave per panel
+  double w[kPanel][NH];
 #pragma unroll
-  for (int a = 0; a < NA; ++a)
+  for (int r = 0; r < kPanel; ++r)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int i = r0 + TR * a, c = c0 + TC * b;
-      w[a][b] = (i < l && c < l && i <= c) ? G[i + (int64_t)c * ldg] : 0.0;
+    for (int h = 0; h < NH; ++h) {
+      const int i = q * kPanel + r, c = lane + 64 * h;
+      w[r][h] = (i < l && c < l && i <= c) ? G[i + (int64_t)c * ldg] : 0.0;
     }
-  if (tid < l) sorig[tid] = orig ? orig[tid * ostride] : G[tid + (int64_t)tid * ldg];
-  __syncthreads();
-  // publish row j (held by the threads with r0 == j % TR, a == j / TR)
-  auto publish = [&](int j) {
-    if (j >= l || r0 != (j % TR)) return;
-    const int a = j / TR;
-    double* rb = rowbuf[j & 1];
+  // drop threshold of this wave's row 8q + (lane & 7)
+  const int tr = q * kPanel + (lane & (kPanel - 1));
+  const double thr =
+      tr < l ? tau * (orig ? orig[tr * ostride] : G[tr + (int64_t)tr * ldg]) : 0.0;
+  // the wave that factors the next panel is on the critical path: it runs at
+  // raised issue priority from its last update until it has published
+  if (q == 0) __builtin_amdgcn_s_setprio(3);
+  for (int p = 0; p < np; ++p) {
+    const int buf = p & 1, p0 = p * kPanel;
+    if (q == p) {
+      double inv[kPanel], pk[kPanel];
 #pragma unroll
-    for (int aa = 0; aa < NA; ++aa) {
-      if (aa != a) continue;
+      for (int r = 0; r < kPanel; ++r) {
+        const int j = p0 + r;
+        inv[r] = 0.0;
+        pk[r] = 0.0;
+        if (j >= l) continue;
+        const double pv = readlane_f64((NH > 1 && j >= 64) ? w[r][NH - 1] : w[r][0], j & 63);
+        const bool keep = pv > readlane_f64(thr, r) && pv > 1e-300;
+        inv[r] = keep ? 1.0 / pv : 0.0;
+        pk[r] = keep ? pv : 0.0;
+        if (!keep && lane == 0) or_status(status, RMM_STATUS_QR_FALLBACK);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int c = c0 + TC * b;
-        rb[c] = w[aa][b];
-        if (c == j) {
-          const double p = w[aa][b];
-          const bool keep = p > tau * sorig[j] && p > 1e-300;
-          invbuf[j & 1] = keep ? 1.0 / p : 0.0;
-          piv[j] = keep ? p : 0.0;
-          if (!keep) or_status(status, RMM_STATUS_QR_FALLBACK);
+        for (int r2 = r + 1; r2 < kPanel; ++r2) {
+          const int i = p0 + r2;  // rows past l hold zeros and stay zero
+          const double fi =
+              inv[r] * readlane_f64((NH > 1 && i >= 64) ? w[r][NH - 1] : w[r][0], i & 63);
+#pragma unroll
+          for (int h = 0; h < NH; ++h) {
+            const int c = lane + 64 * h;
+            const double rj = (c == j) ? 1.0 : w[r][h];
+            const double upd = fma(-fi, rj, w[r2][h]);
+            w[r2][h] = (c >= i || c <= j) ? upd : w[r2][h];
+          }
+        }
+      }
+      // publish the panel (rows past l are never read: a partial panel is
+      // the last one)
+#pragma unroll
+      for (int r = 0; r < kPanel; ++r)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const int c = lane + 64 * h;
+          prow[buf][r][c] = (c == p0 + r) ? 1.0 : w[r][h];
+          pmul[buf][c][r] = w[r][h] * inv[r];
+        }
+      if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < kPanel; ++r)
+          if (p0 + r < l) piv[p0 + r] = pk[r];
+      }
+      __builtin_amdgcn_s_setprio(0);
+    }
+    lds_barrier();
+    // later waves (always whole panels: a partial panel is the last one)
+    if (q > p) {
+      if (q == p + 1) __builtin_amdgcn_s_setprio(3);
+      const int q0 = q * kPanel;
+      double rl[kPanel][NH];
+#pragma unroll
+      for (int jj = 0; jj < kPanel; ++jj)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          // r_c of pivot j for this lane's column; columns between the panel
+          // and this wave's rows are untouched, those inside the wave's own
+          // block are masked per row below
+          const int c = lane + 64 * h;
+          const bool on = c < p0 || (c < p0 + kPanel && c <= p0 + jj) || c >= q0;
+          rl[jj][h] = on ? prow[buf][jj][c] : 0.0;
+        }
+#pragma unroll
+      for (int r = 0; r < kPanel; ++r) {
+        const int i = q0 + r;
+        double f[kPanel];
+#pragma unroll
+        for (int jj = 0; jj < kPanel; ++jj) f[jj] = pmul[buf][i][jj];
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const int c = lane + 64 * h;
+          double t = 0.0;
+#pragma unroll
+          for (int jj = 0; jj < kPanel; ++jj) t = fma(f[jj], rl[jj][h], t);
+          w[r][h] = (c >= i || c < q0) ? w[r][h] - t : w[r][h];
         }
       }
     }
-  };
-  publish(0);
-  for (int j = 0; j < l; ++j) {
-    __syncthreads();
-    const double inv = invbuf[j & 1];
-    const double* rb = rowbuf[j & 1];
-    double rc[NB], fr[NA];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) rc[b] = rb[c0 + TC * b];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) fr[a] = rb[r0 + TR * a];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      if (c0 + TC * b == j) rc[b] = 1.0;
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      const int i = r0 + TR * a;
-      if (i <= j) continue;  // uniform over runs of TC lanes
-      const double f = fr[a] * inv;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int c = c0 + TC * b;
-        const double d = (c >= i || c <= j) ? f * rc[b] : 0.0;
-        w[a][b] -= d;
-      }
-    }
-    publish(j + 1);
   }
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < NA; ++a)
+  for (int r = 0; r < kPanel; ++r)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int j = r0 + TR * a, c = c0 + TC * b;  // W[j][c]
+    for (int h = 0; h < NH; ++h) {
+      const int j = q * kPanel + r, c = lane + 64 * h;  // W[j][c]
       if (j >= l || c >= l) continue;
       const double pj = piv[j];
       double v = 0.0;
-      if (pj > 0.0 && c <= j) v = ((c == j) ? 1.0 : w[a][b]) / sqrt(pj);
+      if (pj > 0.0 && c <= j) v = ((c == j) ? 1.0 : w[r][h]) / sqrt(pj);
       Rinv[c + (int64_t)j * ldr] = v;
     }
-  if (tid < l) diag[tid] = sqrt(piv[tid]);
+  if ((int)threadIdx.x < l) diag[threadIdx.x] = sqrt(piv[threadIdx.x]);
 }
 
 __global__ void fill_block_kernel(int rows, double* __restrict__ X, int64_t ldx) {
@@ -161,12 +212,13 @@ static int cholinv_rec(rmm_ctx* h, int l, const double* G, int64_t ldg, double t
                        const double* orig, int64_t ostride, double* Rinv, int64_t ldr, double* diag,
                        int32_t* status, Carver& ws) {
   if (l <= kLdsMaxL) {
-    if (l <= 32)
-      hipLaunchKernelGGL((cholinv_reg_kernel<8, 32, 4, 1>), dim3(1), dim3(256), 0, h->stream, l, G,
-                         ldg, tau, orig, ostride, Rinv, ldr, diag, status);
+    const dim3 block(64 * ((l + kPanel - 1) / kPanel));
+    if (l <= 64)
+      hipLaunchKernelGGL((cholinv_panel_kernel<1>), dim3(1), block, 0, h->stream, l, G, ldg, tau,
+                         orig, ostride, Rinv, ldr, diag, status);
     else
-      hipLaunchKernelGGL((cholinv_reg_kernel<32, 32, 4, 4>), dim3(1), dim3(1024), 0, h->stream, l,
-                         G, ldg, tau, orig, ostride, Rinv, ldr, diag, status);
+      hipLaunchKernelGGL((cholinv_panel_kernel<2>), dim3(1), block, 0, h->stream, l, G, ldg, tau,
+                         orig, ostride, Rinv, ldr, diag, status);
     return launch_status();
   }
   const int l1 = (l + 1) / 2, l2 = l - l1;
@@ -890,18 +942,39 @@ int zero_status(const rmm_ctx* h, int32_t* status) {
   return launch_status();
 }
 
-__global__ void trmv_upper_kernel(int d, const double* __restrict__ R, const double* __restrict__ y,
-                                  double* __restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d) return;
+// x = R y for upper triangular R (d x d, ld d).  A workgroup owns 64 rows
+// (one per lane); its 16 waves take every 16th column from the first owned
+// row on, so a wave's loads of R are 512-byte column segments, and the 16
+// partial sums of a row are added in wave order through LDS.
+constexpr int kTrmvWaves = 16;
+
+__global__ __launch_bounds__(64 * kTrmvWaves) void trmv_upper_kernel(
+    int d, const double* __restrict__ R, const double* __restrict__ y, double* __restrict__ x) {
+  __shared__ double part[kTrmvWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 64;
+  const int i = i0 + lane;
+  const int ir = i < d ? i : d - 1;  // rows past d read a valid row and are not stored
   double acc = 0.0;
-  for (int c = i; c < d; ++c) acc += R[i + (int64_t)c * d] * y[c];
-  x[i] = acc;
+#pragma unroll 4
+  for (int c = i0 + w; c < d; c += kTrmvWaves) {
+    const double r = R[ir + (int64_t)c * d];
+    acc = fma(c >= i ? r : 0.0, y[c], acc);
+  }
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && i < d) {
+    double s = 0.0;
+#pragma unroll
+    for (int v = 0; v < kTrmvWaves; ++v) s += part[v][lane];
+    x[i] = s;
+  }
 }
 
 int trmv_upper(const rmm_ctx* h, int d, const double* Rinv, const double* y, double* x) {
   if (d == 0) return RMM_OK;
-  hipLaunchKernelGGL(trmv_upper_kernel, dim3((d + 255) / 256), dim3(256), 0, h->stream, d, Rinv, y, x);
+  hipLaunchKernelGGL(trmv_upper_kernel, dim3((d + 63) / 64), dim3(64 * kTrmvWaves), 0, h->stream, d,
+                     Rinv, y, x);
   return launch_status();
 }
 
