@@ -30,14 +30,22 @@ __device__ __forceinline__ void or_status(int32_t* status, int32_t flag) {
 // together once those pivot rows are final.
 //
 // Blocked by panels of 8 rows: wave q holds rows 8q .. 8q+7 in registers,
-// lane t columns t and t + 64.  Panel p is eliminated within wave p (pivots
-// and multipliers broadcast with readlane, no barrier); the wave then
-// publishes the 8 pivot rows and the rows scaled by 1/p_j (the multipliers
-// of every later row, stored column-major so a row's 8 multipliers are
-// contiguous) to LDS, and after one barrier every later wave subtracts the
-// 8 rank-one terms from its rows.  Wave p + 1 does that before factoring its
-// own panel, while the waves behind it are still updating; the LDS panel
-// buffers alternate, so one barrier per panel suffices.
+// lane t columns t and t + 64.  Panel p is eliminated within wave p; the
+// wave then publishes the 8 pivot rows and the rows scaled by 1/p_j (the
+// multipliers of every later row) to LDS, and after one barrier every later
+// wave subtracts the 8 rank-one terms from its rows.  Wave p + 1 does that
+// before factoring its own panel, while the waves behind it are still
+// updating; the LDS panel buffers alternate, so one barrier per panel
+// suffices.
+//
+// The elimination is a chain of dependent FP64 operations, so both phases
+// are arranged for instruction-level parallelism: the update of a later
+// wave accumulates its 16 entries side by side, pivot by pivot, and inside a
+// panel the diagonal entries of the panel rows are tracked as wave-uniform
+// values with the same operations the lanes apply to them, so a pivot
+// depends on the previous one through one FMA and a reciprocal while the
+// row updates run beside that chain.  The reciprocal is the hardware
+// estimate refined by two Newton steps.
 // The drop test of pivot j compares against orig[j * ostride] (the diagonal
 // of the matrix the caller considers original), or G_jj when orig is null;
 // a dropped pivot eliminates nothing and gives a zero column of R^{-1}.
@@ -50,30 +58,84 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+__device__ __forceinline__ double recip_f64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(fma(-x, y, 1.0), y, y);
+  return fma(fma(-x, y, 1.0), y, y);
+}
+
+// Phase A of one panel (rows p0 .. p0+7, all held by this wave); HP is the
+// column half that holds the panel's own columns.  Outside them every entry
+// of a later row is updated (c < p0 is inverse part with c < j, c >= p0 + 8
+// Schur part with c > i); inside, an entry with j < c < i is left alone and
+// r_j = 1.  Rows past l have zero pivots and thresholds, so their steps
+// change nothing; `live` has bit r set for rows below l.
+template <int NH, int HP>
+__device__ __forceinline__ void panel_factor(double (&w)[kPanel][NH], int lane, int p0, unsigned live,
+                                             double thr, double (*prow)[kLdsMaxL],
+                                             double (*pmul)[kLdsMaxL], double* piv,
+                                             int32_t* status) {
+  // W[i][i] of the panel rows, uniform
+  double dg[kPanel];
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r) dg[r] = readlane_f64(w[r][HP], (p0 + r) & 63);
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r) {
+    const int j = p0 + r;
+    const double pv = dg[r];
+    const bool keep = pv > readlane_f64(thr, r) && pv > 1e-300;
+    const double inv = keep ? recip_f64(pv) : 0.0;
+    if (lane == 0) {
+      piv[j] = keep ? pv : 0.0;
+      if (!keep && ((live >> r) & 1u)) or_status(status, RMM_STATUS_QR_FALLBACK);
+    }
+    const int c = lane + 64 * HP;
+    const double rlo = c < j ? w[r][HP] : (c == j ? 1.0 : 0.0);  // r_c where c <= j
+#pragma unroll
+    for (int r2 = r + 1; r2 < kPanel; ++r2) {
+      const int i = p0 + r2;
+      const double b = readlane_f64(w[r][HP], i & 63);
+      const double fi = inv * b;
+      dg[r2] = fma(-fi, b, dg[r2]);  // what lane i does to W[i][i] below
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        const double rj = (h != HP || c >= i) ? w[r][h] : rlo;
+        w[r2][h] = fma(-fi, rj, w[r2][h]);
+      }
+    }
+    // row j is final: publish it and its multipliers
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int ch = lane + 64 * h;
+      prow[r][ch] = (ch == j) ? 1.0 : w[r][h];
+      pmul[r][ch] = w[r][h] * inv;
+    }
+  }
+}
+
 template <int NH>
 __global__ __launch_bounds__(1024) void cholinv_panel_kernel(
     int l, const double* __restrict__ G, int64_t ldg, double tau, const double* orig,
     int64_t ostride, double* __restrict__ Rinv, int64_t ldr, double* __restrict__ diag,
     int32_t* status) {
-  // pivot rows (r_j = 1) and multipliers [i][jj] = W[j][i] / p_j; a
-  // multiplier row is padded to 9 doubles so the column-wise stores of a
-  // panel do not collide in the LDS banks
-  __shared__ double prow[2][kPanel][kLdsMaxL];
-  __shared__ double pmul[2][kLdsMaxL][kPanel + 1];
+  // pivot rows (r_j = 1) and multipliers [jj][i] = W[j][i] / p_j
+  __shared__ __align__(16) double prow[2][kPanel][kLdsMaxL];
+  __shared__ __align__(16) double pmul[2][kPanel][kLdsMaxL];
   __shared__ double piv[kLdsMaxL];
   const int lane = threadIdx.x & 63;
   const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int q0 = q * kPanel;
   const int np = (l + kPanel - 1) / kPanel;  // one wave per panel
   double w[kPanel][NH];
 #pragma unroll
   for (int r = 0; r < kPanel; ++r)
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
-      const int i = q * kPanel + r, c = lane + 64 * h;
+      const int i = q0 + r, c = lane + 64 * h;
       w[r][h] = (i < l && c < l && i <= c) ? G[i + (int64_t)c * ldg] : 0.0;
     }
   // drop threshold of this wave's row 8q + (lane & 7)
-  const int tr = q * kPanel + (lane & (kPanel - 1));
+  const int tr = q0 + (lane & (kPanel - 1));
   const double thr =
       tr < l ? tau * (orig ? orig[tr * ostride] : G[tr + (int64_t)tr * ldg]) : 0.0;
   // the wave that factors the next panel is on the critical path: it runs at
@@ -82,94 +144,93 @@ __global__ __launch_bounds__(1024) void cholinv_panel_kernel(
   for (int p = 0; p < np; ++p) {
     const int buf = p & 1, p0 = p * kPanel;
     if (q == p) {
-      double inv[kPanel], pk[kPanel];
-#pragma unroll
-      for (int r = 0; r < kPanel; ++r) {
-        const int j = p0 + r;
-        inv[r] = 0.0;
-        pk[r] = 0.0;
-        if (j >= l) continue;
-        const double pv = readlane_f64((NH > 1 && j >= 64) ? w[r][NH - 1] : w[r][0], j & 63);
-        const bool keep = pv > readlane_f64(thr, r) && pv > 1e-300;
-        inv[r] = keep ? 1.0 / pv : 0.0;
-        pk[r] = keep ? pv : 0.0;
-        if (!keep && lane == 0) or_status(status, RMM_STATUS_QR_FALLBACK);
-#pragma unroll
-        for (int r2 = r + 1; r2 < kPanel; ++r2) {
-          const int i = p0 + r2;  // rows past l hold zeros and stay zero
-          const double fi =
-              inv[r] * readlane_f64((NH > 1 && i >= 64) ? w[r][NH - 1] : w[r][0], i & 63);
-#pragma unroll
-          for (int h = 0; h < NH; ++h) {
-            const int c = lane + 64 * h;
-            const double rj = (c == j) ? 1.0 : w[r][h];
-            const double upd = fma(-fi, rj, w[r2][h]);
-            w[r2][h] = (c >= i || c <= j) ? upd : w[r2][h];
-          }
-        }
-      }
-      // publish the panel (rows past l are never read: a partial panel is
-      // the last one)
-#pragma unroll
-      for (int r = 0; r < kPanel; ++r)
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          const int c = lane + 64 * h;
-          prow[buf][r][c] = (c == p0 + r) ? 1.0 : w[r][h];
-          pmul[buf][c][r] = w[r][h] * inv[r];
-        }
-      if (lane == 0) {
-#pragma unroll
-        for (int r = 0; r < kPanel; ++r)
-          if (p0 + r < l) piv[p0 + r] = pk[r];
-      }
+      const int nl = l - p0;
+      const unsigned live = nl >= kPanel ? 0xFFu : ((1u << nl) - 1u);
+      if (NH > 1 && p0 >= 64)
+        panel_factor<NH, NH - 1>(w, lane, p0, live, thr, prow[buf], pmul[buf], piv, status);
+      else
+        panel_factor<NH, 0>(w, lane, p0, live, thr, prow[buf], pmul[buf], piv, status);
       __builtin_amdgcn_s_setprio(0);
     }
     lds_barrier();
     // later waves (always whole panels: a partial panel is the last one)
     if (q > p) {
       if (q == p + 1) __builtin_amdgcn_s_setprio(3);
-      const int q0 = q * kPanel;
-      double rl[kPanel][NH];
+      // r_c of pivot p0 + jj for this lane's columns: always for c < p0 and
+      // c >= q0, for the panel's own columns when c <= p0 + jj, never for the
+      // columns between the panel and this wave's rows; those inside the
+      // wave's own block are masked per row below
+      bool always[NH];
+      unsigned pc[NH];
 #pragma unroll
-      for (int jj = 0; jj < kPanel; ++jj)
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          // r_c of pivot j for this lane's column; columns between the panel
-          // and this wave's rows are untouched, those inside the wave's own
-          // block are masked per row below
-          const int c = lane + 64 * h;
-          const bool on = c < p0 || (c < p0 + kPanel && c <= p0 + jj) || c >= q0;
-          rl[jj][h] = on ? prow[buf][jj][c] : 0.0;
-        }
-#pragma unroll
-      for (int r = 0; r < kPanel; ++r) {
-        const int i = q0 + r;
-        double f[kPanel];
-#pragma unroll
-        for (int jj = 0; jj < kPanel; ++jj) f[jj] = pmul[buf][i][jj];
-#pragma unroll
-        for (int h = 0; h < NH; ++h) {
-          const int c = lane + 64 * h;
-          double t = 0.0;
-#pragma unroll
-          for (int jj = 0; jj < kPanel; ++jj) t = fma(f[jj], rl[jj][h], t);
-          w[r][h] = (c >= i || c < q0) ? w[r][h] - t : w[r][h];
-        }
+      for (int h = 0; h < NH; ++h) {
+        const int c = lane + 64 * h;
+        always[h] = c < p0 || c >= q0;
+        pc[h] = (unsigned)(c - p0);
       }
+      double t[kPanel][NH];
+#pragma unroll
+      for (int r = 0; r < kPanel; ++r)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) t[r][h] = 0.0;
+      // pivot jj + 1's operands are read while pivot jj's are multiplied
+      double f[kPanel], rv[NH];
+#pragma unroll
+      for (int r = 0; r < kPanel; ++r) f[r] = pmul[buf][0][q0 + r];
+#pragma unroll
+      for (int h = 0; h < NH; ++h) rv[h] = prow[buf][0][lane + 64 * h];
+#pragma unroll
+      for (int jj = 0; jj < kPanel; ++jj) {
+        double fn[kPanel], rn[NH];
+        if (jj + 1 < kPanel) {
+#pragma unroll
+          for (int r = 0; r < kPanel; ++r) fn[r] = pmul[buf][jj + 1][q0 + r];
+#pragma unroll
+          for (int h = 0; h < NH; ++h) rn[h] = prow[buf][jj + 1][lane + 64 * h];
+        }
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const double rl = (always[h] || pc[h] <= (unsigned)jj) ? rv[h] : 0.0;
+#pragma unroll
+          for (int r = 0; r < kPanel; ++r) t[r][h] = fma(f[r], rl, t[r][h]);
+        }
+        if (jj + 1 < kPanel) {
+#pragma unroll
+          for (int r = 0; r < kPanel; ++r) f[r] = fn[r];
+#pragma unroll
+          for (int h = 0; h < NH; ++h) rv[h] = rn[h];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int r = 0; r < kPanel; ++r)
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          const int c = lane + 64 * h, i = q0 + r;
+          w[r][h] = (c >= i || c < q0) ? w[r][h] - t[r][h] : w[r][h];
+        }
     }
   }
   __syncthreads();
+  // R^{-1}[c][j] = (c == j ? 1 : W[j][c]) / sqrt(p_j) for c <= j; every value
+  // is formed before the first store
+#pragma unroll
+  for (int r = 0; r < kPanel; ++r) {
+    const int j = q0 + r;
+    const double pj = j < l ? piv[j] : 0.0;
+    const double rs = pj > 0.0 ? 1.0 / sqrt(pj) : 0.0;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      const int c = lane + 64 * h;
+      w[r][h] = c <= j ? ((c == j) ? 1.0 : w[r][h]) * rs : 0.0;
+    }
+  }
 #pragma unroll
   for (int r = 0; r < kPanel; ++r)
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
-      const int j = q * kPanel + r, c = lane + 64 * h;  // W[j][c]
-      if (j >= l || c >= l) continue;
-      const double pj = piv[j];
-      double v = 0.0;
-      if (pj > 0.0 && c <= j) v = ((c == j) ? 1.0 : w[r][h]) / sqrt(pj);
-      Rinv[c + (int64_t)j * ldr] = v;
+      const int j = q0 + r, c = lane + 64 * h;
+      if (j < l && c < l) Rinv[c + (int64_t)j * ldr] = w[r][h];
     }
   if ((int)threadIdx.x < l) diag[threadIdx.x] = sqrt(piv[threadIdx.x]);
 }
