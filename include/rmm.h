@@ -97,6 +97,18 @@ int rmm_set_autotune(rmm_handle h, int on);
 int rmm_autotune_count(rmm_handle h, int64_t* count);
 int rmm_autotune_save(rmm_handle h, const char* path);
 int rmm_autotune_load(rmm_handle h, const char* path);
+/* Kernel timing: with it on, the handle records a HIP event on its stream
+ * right before and right after the main kernel of each sketch (the
+ * CountSketch scatter-add, the SRHT transform and sample, the Gaussian
+ * product; not the index, schedule or reduction kernels around them),
+ * whether it runs for rmm_sketch or inside a driver; the grouped CountSketch
+ * launch of rmm_sketch_batch is not timed.  rmm_kernel_time waits for the later event and
+ * returns the milliseconds between the two of the last such kernel; it
+ * returns RMM_ERR_INVALID_ARG when timing is off or no kernel has been
+ * timed since it was turned on.  Off by default (the events serialize
+ * nothing, but are not meant for graph capture). */
+int rmm_set_kernel_timing(rmm_handle h, int on);
+int rmm_kernel_time(rmm_handle h, float* ms);
 
 /* Sets the hipStream_t (passed as void*) on which later calls enqueue work. */
 int rmm_set_stream(rmm_handle h, void* hip_stream);

@@ -60,6 +60,8 @@ def lib():
             "rmm_set_workspace": [_vp, _vp, ctypes.c_size_t],
             "rmm_device_cus": [_vp, ctypes.POINTER(_i32)],
             "rmm_set_autotune": [_vp, _i32],
+            "rmm_set_kernel_timing": [_vp, _i32],
+            "rmm_kernel_time": [_vp, ctypes.POINTER(ctypes.c_float)],
             "rmm_autotune_count": [_vp, ctypes.POINTER(_i64)],
             "rmm_autotune_save": [_vp, ctypes.c_char_p],
             "rmm_autotune_load": [_vp, ctypes.c_char_p],
@@ -309,6 +311,16 @@ class Handle:
 
     def autotune_load(self, path: str):
         _check(lib().rmm_autotune_load(self._h, path.encode()), "rmm_autotune_load")
+
+    # ---- timing of the sketches' main kernels (rmm_set_kernel_timing) ------------
+    def set_kernel_timing(self, on: bool = True):
+        _check(lib().rmm_set_kernel_timing(self._h, 1 if on else 0), "rmm_set_kernel_timing")
+
+    def kernel_time(self) -> float:
+        """Milliseconds of the last timed sketch kernel (waits for it)."""
+        ms = ctypes.c_float()
+        _check(lib().rmm_kernel_time(self._h, ctypes.byref(ms)), "rmm_kernel_time")
+        return float(ms.value)
 
     # ---- least squares -------------------------------------------------------
     def sketched_lsr(self, A: torch.Tensor, b: torch.Tensor, s: int, kind, seed: int,

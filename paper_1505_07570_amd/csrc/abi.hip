@@ -119,6 +119,24 @@ int rmm_set_autotune(rmm_handle h, int on) {
   return RMM_OK;
 }
 
+int rmm_set_kernel_timing(rmm_handle h, int on) {
+  if (!h) return RMM_ERR_INVALID_ARG;
+  if (on) {
+    for (hipEvent_t& e : h->kev)
+      if (!e) RMM_HIP(hipEventCreate(&e));
+  }
+  h->ktime = on != 0;
+  h->kmarked = false;
+  return RMM_OK;
+}
+
+int rmm_kernel_time(rmm_handle h, float* ms) {
+  if (!h || !ms || !h->ktime || !h->kmarked) return RMM_ERR_INVALID_ARG;
+  RMM_HIP(hipEventSynchronize(h->kev[1]));
+  RMM_HIP(hipEventElapsedTime(ms, h->kev[0], h->kev[1]));
+  return RMM_OK;
+}
+
 int rmm_autotune_count(rmm_handle h, int64_t* count) {
   if (!h || !count) return RMM_ERR_INVALID_ARG;
   *count = (int64_t)h->plans.size();

@@ -21,11 +21,27 @@ struct rmm_ctx {
   std::vector<unsigned char> table_host;  // staging of the last batch descriptor table
   bool autotune = false;                  // time the candidate plans of new shapes
   std::map<std::string, int> plans;       // tuned plan per kernel shape key
+  // rmm_set_kernel_timing: events around the main kernel of each sketch
+  bool ktime = false;
+  mutable bool kmarked = false;  // both events recorded since timing was enabled
+  hipEvent_t kev[2] = {nullptr, nullptr};
+  ~rmm_ctx() {
+    for (hipEvent_t e : kev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace rmm {
 
 constexpr size_t kAlign = 256;
+
+// Event k (0 before, 1 after) around a sketch's main kernel when kernel
+// timing is on; recorded on the handle's stream.
+inline void ktime_mark(const rmm_ctx* h, int k) {
+  if (!h->ktime) return;
+  (void)hipEventRecord(h->kev[k], h->stream);
+  if (k == 1) h->kmarked = true;
+}
 
 // Bump allocator over the caller's workspace.  The size queries run the
 // same carving sequence with a null base, so a query and the call that

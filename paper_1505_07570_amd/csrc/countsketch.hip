@@ -548,8 +548,10 @@ int launch_cs(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
   auto kern = countsketch_kernel<T, WAVES, UNROLL, VEC>;
   RMM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
+  ktime_mark(h, 0);
   hipLaunchKernelGGL(kern, dim3(plan.G), dim3(WAVES * 64), lds, h->stream, A, lda, b, n, plan,
                      seed, partials);
+  ktime_mark(h, 1);
   return launch_status();
 }
 
@@ -578,8 +580,10 @@ int launch_cs_sched(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n
     auto kern = countsketch_sched_kernel<T, VEC, W>;                                        \
     RMM_HIP(hipFuncSetAttribute((const void*)kern,                                          \
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));     \
+    ktime_mark(h, 0);                                                                       \
     hipLaunchKernelGGL(kern, dim3(plan.G), dim3(64 * W), lds, h->stream, A, lda, b, n, plan, \
                        table, partials);                                                    \
+    ktime_mark(h, 1);                                                                       \
     return launch_status();                                                                 \
   }
   switch (plan.width) {

@@ -354,6 +354,7 @@ int launch_gauss(const rmm_ctx* h, const GaussShape& g, const T* A, int64_t lda,
 #define RMM_GS_LAUNCH(V, M)                                                                    \
   hipLaunchKernelGGL((gauss_sketch_kernel<T, NT, V, M, XC>), grid, dim3(256), 0, h->stream, A, lda, b, \
                      n, ncols, m, s, g.kchunk, tag, seed, Qm, ldq, partials)
+  ktime_mark(h, 0);
   if (Qm) {
     if (vec) RMM_GS_LAUNCH(true, true);
     else RMM_GS_LAUNCH(false, true);
@@ -361,6 +362,7 @@ int launch_gauss(const rmm_ctx* h, const GaussShape& g, const T* A, int64_t lda,
     if (vec) RMM_GS_LAUNCH(true, false);
     else RMM_GS_LAUNCH(false, false);
   }
+  ktime_mark(h, 1);
 #undef RMM_GS_LAUNCH
   return launch_status();
 }

@@ -259,8 +259,10 @@ int launch_srht(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
   const size_t lds = srht_lds<T>();
   RMM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
+  ktime_mark(h, 0);
   hipLaunchKernelGGL(kern, dim3(plan.G), dim3(256), lds, h->stream, A, lda, b, n, plan, idx, seed,
                      partials);
+  ktime_mark(h, 1);
   return launch_status();
 }
 

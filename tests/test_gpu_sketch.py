@@ -153,6 +153,31 @@ def test_sketch_deterministic(h, name, kind):
     assert torch.equal(C1, C2)
 
 
+@pytest.mark.parametrize("name,kind", KINDS)
+def test_kernel_timing_brackets_the_sketch_kernel(name, kind):
+    hk = rmm.handle()  # own handle: timing state is per handle
+    r = np.random.default_rng(5)
+    A = dev(r.standard_normal((300000, 9)).astype(np.float32))
+    with pytest.raises(rmm.RmmError):
+        hk.kernel_time()                  # timing off
+    C0 = hk.sketch(A, 256, name, 3).clone()
+    hk.set_kernel_timing(True)
+    with pytest.raises(rmm.RmmError):
+        hk.kernel_time()                  # nothing timed yet
+    a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    C1 = hk.sketch(A, 256, name, 3).clone()
+    z.record()
+    ms = hk.kernel_time()
+    z.synchronize()
+    call_ms = a.elapsed_time(z)
+    assert 0.0 < ms <= call_ms * 1.05 + 0.01
+    assert torch.equal(C0, C1)            # the marks change nothing
+    hk.set_kernel_timing(False)
+    with pytest.raises(rmm.RmmError):
+        hk.kernel_time()
+
+
 def test_srht_full_sample_is_orthogonal_transform(h):
     # m = N = s: S = D H / sqrt(N) * sqrt(N/s) ... with s = N, S^T S = I * N / s = I
     m = 1024
