@@ -134,3 +134,26 @@ def sketch(A, s: int, kind: int, seed: int, fp64: bool = True, rows=None):
         A = A[:, None]
     S = sketch_matrix(kind, A.shape[0], s, seed, fp64, cols=rows)
     return S.T @ A
+
+
+# --------------------------------------------------------------------------
+# Composite sketch (Sec. 3.2.4)
+# --------------------------------------------------------------------------
+
+def composite_matrix(m: int, s1: int, s: int, kind2: int, seed: int, fp64: bool = True):
+    """S = S_cs S_2 (m x s) of Sec. 3.2.4: an m x s1 count sketch followed by
+    an s1 x s Gaussian projection (the section's case) or SRHT (the
+    alternative the paper names in its remarks on the faster k-SVD of
+    Sec. 5.3).  Both factors come from ``seed``; their random streams are
+    told apart by tag, so S_2 is the sketch matrix of an s1-row input."""
+    if kind2 not in (GAUSSIAN, SRHT):
+        raise ValueError("the second factor is a Gaussian projection or an SRHT")
+    return countsketch_matrix(m, s1, seed) @ sketch_matrix(kind2, s1, s, seed, fp64)
+
+
+def composite_sketch(A, s1: int, s: int, kind2: int, seed: int, fp64: bool = True):
+    """C = S^T A = S_2^T (S_cs^T A) (s x n)."""
+    A = np.asarray(A, dtype=np.float64)
+    if A.ndim == 1:
+        A = A[:, None]
+    return composite_matrix(A.shape[0], s1, s, kind2, seed, fp64).T @ A

@@ -176,3 +176,55 @@ def test_subspace_embedding_distortion_shrinks(kind):
         gam.append(worst)
     assert gam[0] > gam[1] > gam[2]
     assert gam[2] < 1.6
+
+
+# ---- composite sketch (Sec. 3.2.4) -------------------------------------------------
+
+@pytest.mark.parametrize("kind2", [sk.GAUSSIAN, sk.SRHT])
+def test_composite_expected_SSt_is_identity(kind2):
+    """E[S_cs S_2 S_2^T S_cs^T] = I: S_2 is isotropic and S_cs has unit rows."""
+    m, s1, s, T = 6, 8, 4, 3000
+    acc = np.zeros((m, m))
+    acc2 = np.zeros((m, m))
+    for t in range(T):
+        S = sk.composite_matrix(m, s1, s, kind2, 900 + t)
+        P = S @ S.T
+        acc += P
+        acc2 += P * P
+    mean = acc / T
+    se = np.sqrt(np.maximum(acc2 / T - mean ** 2, 1e-30) / T)
+    assert np.all(np.abs(mean - np.eye(m)) < 5 * se + 1e-12)
+
+
+@pytest.mark.parametrize("kind2", [sk.GAUSSIAN, sk.SRHT])
+def test_composite_subspace_embedding_distortion_shrinks(kind2):
+    """The composite keeps the subspace embedding of its factors: the worst
+    distortion of span(U) falls as the final size s grows (s1 fixed, large)."""
+    r = np.random.default_rng(8)
+    m, d, s1 = 2048, 4, 1024
+    U, _ = np.linalg.qr(r.standard_normal((m, d)))
+    gam = []
+    for s in (16, 64, 512):
+        worst = 0.0
+        for t in range(8):
+            sv = np.linalg.svd(sk.composite_sketch(U, s1, s, kind2, 60 + t), compute_uv=False)
+            worst = max(worst, sv[0] ** 2, 1 / sv[-1] ** 2)
+        gam.append(worst)
+    assert gam[0] > gam[1] > gam[2]
+    assert gam[2] < 1.8
+
+
+def test_composite_rows_are_signed_rows_of_the_second_factor():
+    """Row i of S_cs S_2 is +-(a row of S_2), since S_cs has a single +-1 per
+    row; a transposed or reordered product fails this."""
+    m, s1, s, seed = 300, 20, 7, 5
+    S = sk.composite_matrix(m, s1, s, sk.GAUSSIAN, seed)
+    S2 = sk.gaussian_matrix(s1, s, seed, True)
+    for i in range(m):
+        gap = np.minimum(np.abs(S[i] - S2).max(axis=1), np.abs(S[i] + S2).max(axis=1))
+        assert gap.min() == 0.0
+
+
+def test_composite_rejects_countsketch_second_factor():
+    with pytest.raises(ValueError):
+        sk.composite_matrix(10, 4, 2, sk.COUNTSKETCH, 1)
