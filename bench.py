@@ -483,6 +483,22 @@ def main():
         out["plain_lsr"] = {"p50_ms": percentile(ts, 50), "p99_ms": percentile(ts, 99),
                             "method": "fp64 normal equations on the GPU"}
         out["objective_ratio"] = {k: (float(res[k].item()) / float(rp.item())) ** 2 for k in kinds}
+        # composite sketch (Sec. 3.2.4): CountSketch to s1 = 4 s rows, then a
+        # Gaussian projection or SRHT to s; the same sketch-and-solve after it
+        comp = {}
+        s1 = 4 * s
+        Cc = torch.empty(d + 1, s, dtype=torch.float32, device="cuda").t()
+        for k2 in ("gaussian", "srht"):
+            fn = lambda: h.sketch_composite(Ad, s1, s, k2, seed, b=bd, out=Cc)
+            fn()
+            ts = lat(fn, R)
+            xc, _ = h.lsr_solve(Cc, d)
+            rc = h.residual(Ad, bd, xc)
+            p50 = percentile(ts, 50)
+            comp["countsketch+" + k2] = {"s1": s1, "p50_ms": p50, "p99_ms": percentile(ts, 99),
+                                         "gbs_of_A": ab_bytes / (p50 * 1e-3) / 1e9,
+                                         "objective_ratio": (float(rc.item()) / float(rp.item())) ** 2}
+        out["composite_sketch"] = comp
         # machine-precision LSR (Alg. 4.1): sketch-and-solve start, 20 CG steps
         # (one fused FP64 pass over A each); objective ratio against the
         # normal-equation solve, and per-step time from the 0- and 20-step runs

@@ -136,6 +136,23 @@ int rmm_sketch(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m,
                int64_t n, const void* A, int64_t lda, const void* b, int64_t s,
                uint64_t seed, void* C, int64_t ldc);
 
+/* Composite sketch (Sec. 3.2.4): C = S^T [A | b] with S = S_cs S_2, an
+ * m x s1 COUNTSKETCH followed by an s1 x s sketch of kind `kind2` (GAUSSIAN,
+ * the section's GaussianProjection+CountSketch, or SRHT, the combination
+ * the paper suggests with the faster k-SVD of Sec. 5.3).  Both factors are
+ * the rmm_sketch operators above, drawn from the same seed (their streams
+ * differ by tag): the call equals rmm_sketch(COUNTSKETCH, s1) into an
+ * s1 x n' buffer followed by rmm_sketch(kind2, s) of that buffer.  The
+ * intermediate lives in the workspace.  C is s x n', ldc >= s.  Requires
+ * s1 >= 1, s >= 1 and, for SRHT, s <= N = 2^ceil(log2 s1); kind2 =
+ * COUNTSKETCH is RMM_ERR_UNSUPPORTED. */
+int rmm_sketch_composite_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2,
+                                   int64_t m, int64_t n_total, int64_t s1, int64_t s,
+                                   size_t* bytes);
+int rmm_sketch_composite(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m,
+                         int64_t n, const void* A, int64_t lda, const void* b, int64_t s1,
+                         int64_t s, uint64_t seed, void* C, int64_t ldc);
+
 /* ---- batches of sketches (grouped execution) ----------------------------------
  * One call sketches `count` independent problems of different shapes, each
  * as in rmm_sketch (C_i = S_i^T [A_i | b_i] with its own s_i and seed_i; A_i

@@ -67,6 +67,10 @@ def lib():
             "rmm_autotune_load": [_vp, ctypes.c_char_p],
             "rmm_sketch_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_sketch": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _i64],
+            "rmm_sketch_composite_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, _i64,
+                                               ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_sketch_composite": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _u64,
+                                     _vp, _i64],
             "rmm_rsvd_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_rsvd": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _i64, _i64, _i64, _u64,
                          _vp, _i64, _vp, _vp, _i64, _vp],
@@ -259,6 +263,28 @@ class Handle:
         self._prepare(nbytes)
 
     # ---- sketching -------------------------------------------------------
+    def sketch_composite_workspace(self, dtype, kind2, m, ncols, s1, s) -> int:
+        out = ctypes.c_size_t()
+        dt = F32 if dtype == torch.float32 else F64
+        _check(lib().rmm_sketch_composite_workspace(self._h, dt, _kind(kind2), m, ncols, s1, s,
+                                                    ctypes.byref(out)), "rmm_sketch_composite_workspace")
+        return out.value
+
+    def sketch_composite(self, A: torch.Tensor, s1: int, s: int, kind2, seed: int,
+                         b: torch.Tensor = None, out: torch.Tensor = None) -> torch.Tensor:
+        """C = (S_cs S_2)^T [A | b] (s x n'): CountSketch to s1 rows, then kind2 to s."""
+        A = colmajor(A)
+        m, n = A.shape
+        ncols = n + (1 if b is not None else 0)
+        if out is None:
+            out = torch.empty(ncols, s, dtype=A.dtype, device=A.device).t()
+        ws = self.sketch_composite_workspace(A.dtype, kind2, m, ncols, s1, s)
+        self._prepare(ws)
+        _check(lib().rmm_sketch_composite(self._h, _dt(A), _kind(kind2), m, n, _ptr(A), _ld(A),
+                                          _bptr(b, out), s1, s, seed, _ptr(out), _ld(out)),
+               "rmm_sketch_composite")
+        return out
+
     def sketch_workspace(self, dtype, kind, m, ncols, s) -> int:
         out = ctypes.c_size_t()
         dt = F32 if dtype == torch.float32 else F64

@@ -91,6 +91,44 @@ int batch_run(rmm_ctx* h, rmm_sketch_kind kind, int count, const rmm_sketch_desc
 
 }  // namespace
 
+namespace {
+
+template <typename T>
+size_t composite_ws(const rmm_ctx* h, rmm_sketch_kind kind2, int64_t m, int ncols, int64_t s1,
+                    int64_t s) {
+  Carver c(nullptr, 0);
+  c.take<T>((size_t)s1 * (ncols > 0 ? ncols : 1));
+  const size_t w1 = countsketch_workspace<T>(h, m, ncols, s1);
+  const size_t w2 = sketch_ws<T>(h, kind2, s1, ncols, s);
+  return c.off + (w1 > w2 ? w1 : w2) + 2 * kAlign;
+}
+
+// Sec. 3.2.4: Y = S_cs^T [A | b] (s1 x n') in the workspace, then C = S_2^T Y
+template <typename T>
+int composite_run(rmm_ctx* h, rmm_sketch_kind kind2, int64_t m, int n, const T* A, int64_t lda,
+                  const T* b, int64_t s1, int64_t s, uint64_t seed, T* C, int64_t ldc) {
+  const int ncols = n + (b ? 1 : 0);
+  Carver ws(h->ws, h->ws_bytes);
+  if (ws.cap < composite_ws<T>(h, kind2, m, ncols, s1, s)) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  T* Y = ws.take<T>((size_t)s1 * (ncols > 0 ? ncols : 1));
+  const size_t mark = ws.off;
+  RMM_TRY(countsketch_run<T>(h, m, n, A, lda, b, s1, seed, Y, s1, ws));
+  ws.off = mark;
+  return sketch_dispatch<T>(h, kind2, s1, ncols, Y, s1, nullptr, s, seed, C, ldc, ws);
+}
+
+int composite_args(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m, int64_t n_total,
+                   int64_t s1, int64_t s) {
+  if (!h || !dt_ok(dt) || !kind_ok(kind2) || !sketch_dims_ok(m, n_total, s1) ||
+      !sketch_dims_ok(s1, n_total, s))
+    return RMM_ERR_INVALID_ARG;
+  if (kind2 == RMM_COUNTSKETCH) return RMM_ERR_UNSUPPORTED;
+  if (kind2 == RMM_SRHT && s > (1ll << ceil_log2((uint64_t)s1))) return RMM_ERR_INVALID_ARG;
+  return RMM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int rmm_create(rmm_handle* h, int device) {
@@ -226,6 +264,27 @@ int rmm_sketch(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m, int6
                                   seed, (float*)C, ldc, ws);
   return sketch_dispatch<double>(h, kind, m, (int)n, (const double*)A, lda, (const double*)b, s,
                                  seed, (double*)C, ldc, ws);
+}
+
+int rmm_sketch_composite_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m,
+                                   int64_t n_total, int64_t s1, int64_t s, size_t* bytes) {
+  RMM_TRY(composite_args(h, dt, kind2, m, n_total, s1, s));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  *bytes = dt == RMM_F32 ? composite_ws<float>(h, kind2, m, (int)n_total, s1, s)
+                         : composite_ws<double>(h, kind2, m, (int)n_total, s1, s);
+  return RMM_OK;
+}
+
+int rmm_sketch_composite(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m, int64_t n,
+                         const void* A, int64_t lda, const void* b, int64_t s1, int64_t s,
+                         uint64_t seed, void* C, int64_t ldc) {
+  RMM_TRY(composite_args(h, dt, kind2, m, n + 1, s1, s));
+  if ((n > 0 && m > 0 && !A) || !C || bad_ld(lda, m) || bad_ld(ldc, s)) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return composite_run<float>(h, kind2, m, (int)n, (const float*)A, lda, (const float*)b, s1, s,
+                                seed, (float*)C, ldc);
+  return composite_run<double>(h, kind2, m, (int)n, (const double*)A, lda, (const double*)b, s1,
+                               s, seed, (double*)C, ldc);
 }
 
 int rmm_sketch_batch_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t count,

@@ -153,6 +153,50 @@ def test_sketch_deterministic(h, name, kind):
     assert torch.equal(C1, C2)
 
 
+# ---- composite sketch (Sec. 3.2.4) ---------------------------------------------------
+
+COMPOSITE = [("gaussian", osk.GAUSSIAN), ("srht", osk.SRHT)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("name,kind2", COMPOSITE)
+@pytest.mark.parametrize("m,n,s1,s", [(1, 1, 1, 1), (1000, 5, 64, 16), (4099, 3, 257, 100),
+                                      (70001, 9, 2048, 300), (5000, 2, 300, 512)])
+def test_composite_parity(h, dtype, name, kind2, m, n, s1, s):
+    if kind2 == osk.SRHT and s > osk.srht_pad(s1):
+        pytest.skip("SRHT needs s <= N(s1)")
+    r = np.random.default_rng(m + 7 * n)
+    A = r.standard_normal((m, n)).astype(np.float32 if dtype == torch.float32 else np.float64)
+    seed = 4321 + s1
+    C = h.sketch_composite(dev(A, dtype), s1, s, name, seed)
+    ref = osk.composite_sketch(A.astype(np.float64), s1, s, kind2, seed,
+                               fp64=(dtype == torch.float64))
+    assert C.shape == (s, n)
+    assert rel(host(C), ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("name,kind2", COMPOSITE)
+def test_composite_is_the_two_sketches_in_turn(h, name, kind2):
+    r = np.random.default_rng(9)
+    A = dev(r.standard_normal((20000, 4)).astype(np.float32))
+    b = dev(r.standard_normal(20000).astype(np.float32))
+    C = h.sketch_composite(A, 512, 128, name, 11, b=b)
+    Y = h.sketch(A, 512, "countsketch", 11, b=b)
+    assert torch.equal(C, h.sketch(Y, 128, name, 11))
+
+
+def test_composite_edge_cases(h):
+    A = torch.zeros(0, 3, dtype=torch.float64, device="cuda")
+    assert torch.count_nonzero(h.sketch_composite(A, 16, 4, "gaussian", 1)).item() == 0
+    A = torch.ones(64, 2, dtype=torch.float32, device="cuda")
+    with pytest.raises(rmm.RmmError):
+        h.sketch_composite(A, 16, 4, "countsketch", 1)   # second factor must densify
+    with pytest.raises(rmm.RmmError):
+        h.sketch_composite(A, 16, 17, "srht", 1)         # s > N(s1)
+    with pytest.raises(rmm.RmmError):
+        h.sketch_composite(A, 0, 4, "gaussian", 1)       # s1 < 1
+
+
 @pytest.mark.parametrize("name,kind", KINDS)
 def test_kernel_timing_brackets_the_sketch_kernel(name, kind):
     hk = rmm.handle()  # own handle: timing state is per handle
