@@ -77,3 +77,44 @@ def rsvd(A, k: int, p: int, q: int, seed: int, fp64: bool = True, Omega=None):
     V = Vt[:k, :].T
     U, V = fix_signs(U, V)
     return U, sig[:k].copy(), V, Q
+
+
+# --------------------------------------------------------------------------
+# Faster randomized k-SVD (Sec. 5.3, Alg. 5.3)
+# --------------------------------------------------------------------------
+
+def ksvd_faster(A, k: int, s: int, p_cs: int, p: int, seed: int, kind2: int = 1,
+                fp64: bool = True):
+    """Alg. 5.3 in its steps, with the readings stated here.
+
+    1. C = A S (m x s), S an n x s count sketch of the columns of A; its
+       buckets and signs come from seed + 1, so that S and the row factor
+       P_cs (seed) are independent although both use the count-sketch tag.
+    2. P = P_cs P_2 (m x p), the composite sketch of Sec. 3.2.4 from seed,
+       P_2 an SRHT (kind2 = 1, the algorithm's statement) or a Gaussian
+       projection (kind2 = 0, the listing's choice);
+       D = P^T C (p x s), L = P^T A (p x n).
+    3. Q_D R_D = D (thin QR).
+    4. Ubar Sigmabar Vbar^T = the rank-k truncated SVD of Q_D^T L (s x n).
+    5. Utilde Sigmatilde Vhat^T = svd(C R_D^+ Ubar Sigmabar) (m x k).
+    6. Vtilde = Vbar Vhat.
+    Returns (Utilde (m x k), sigma (k,), Vtilde (n x k)) with the signs of
+    fix_signs.  kind2 and fp64 follow the composite sketch of oracle.sketch.
+    """
+    from . import sketch as sk
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if not (1 <= k <= s <= p and p <= p_cs):
+        raise ValueError("need 1 <= k <= s <= p <= p_cs")
+    C = A @ sk.countsketch_matrix(n, s, seed + 1)
+    P = sk.composite_matrix(m, p_cs, p, kind2, seed, fp64)
+    D = P.T @ C
+    L = P.T @ A
+    QD, RD = np.linalg.qr(D)
+    Ub, sb, Vbt = np.linalg.svd(QD.T @ L, full_matrices=False)
+    Ub, sb, Vb = Ub[:, :k], sb[:k], Vbt[:k, :].T
+    M = C @ (np.linalg.pinv(RD) @ (Ub * sb))
+    Ut, st, Vht = np.linalg.svd(M, full_matrices=False)
+    Vt = Vb @ Vht.T
+    Ut, Vt = fix_signs(Ut, Vt)
+    return Ut, st, Vt

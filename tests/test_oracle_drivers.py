@@ -235,3 +235,44 @@ def test_precise_lsr_zero_iterations_is_sketch_and_solve():
     x0, _, _ = lsr.precise_lsr(A, b, 40, sk.COUNTSKETCH, 9, iters=0)
     xs, _, _, _ = lsr.sketched_lsr(A, b, 40, sk.COUNTSKETCH, 9)
     assert np.allclose(x0, xs, rtol=1e-12, atol=1e-13)
+
+
+# ---- faster randomized k-SVD (Alg. 5.3) -------------------------------------------
+
+@pytest.mark.parametrize("kind2", [sk.SRHT, sk.GAUSSIAN])
+def test_ksvd_faster_exact_recovery_of_rank_k(kind2):
+    """rank(A) = k <= s: C = A S spans range(A) and the sketched regression of
+    eq. 5.4 is consistent, so A is recovered exactly (up to rounding)."""
+    r = np.random.default_rng(21)
+    m, n, k = 400, 300, 6
+    A = r.standard_normal((m, k)) @ r.standard_normal((k, n))
+    U, sig, V = rsvd.ksvd_faster(A, k, 12, 160, 48, 5, kind2)
+    np.testing.assert_allclose((U * sig) @ V.T, A, atol=1e-9 * np.abs(A).max())
+    np.testing.assert_allclose(sig, np.linalg.svd(A, compute_uv=False)[:k], rtol=1e-9)
+
+
+def test_ksvd_faster_orthonormal_factors_and_signs():
+    r = np.random.default_rng(22)
+    A = r.standard_normal((500, 200))
+    U, sig, V = rsvd.ksvd_faster(A, 5, 20, 300, 80, 7)
+    np.testing.assert_allclose(U.T @ U, np.eye(5), atol=1e-12)
+    np.testing.assert_allclose(V.T @ V, np.eye(5), atol=1e-12)
+    assert np.all(np.diff(sig) <= 0) and sig[-1] > 0
+    for i in range(5):
+        assert U[np.argmax(np.abs(U[:, i])), i] > 0
+
+
+def test_ksvd_faster_error_near_truncation_floor():
+    """Decaying spectrum: ||A - U S V^T||_F within a modest factor of the
+    optimal rank-k error (the (1 + eps)^3 bound of Sec. 5.3.1)."""
+    r = np.random.default_rng(23)
+    m, n, k = 1000, 400, 8
+    Uq, _ = np.linalg.qr(r.standard_normal((m, n)))
+    Vq, _ = np.linalg.qr(r.standard_normal((n, n)))
+    sv = 0.8 ** np.arange(n)
+    A = (Uq * sv) @ Vq.T
+    U, sig, V = rsvd.ksvd_faster(A, k, 40, 600, 200, 9)
+    err = np.linalg.norm(A - (U * sig) @ V.T)
+    opt = np.sqrt(np.sum(sv[k:] ** 2))
+    assert err < 1.2 * opt
+    np.testing.assert_allclose(sig, sv[:k], rtol=0.05)
