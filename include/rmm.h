@@ -211,6 +211,26 @@ int rmm_rsvd(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m,
              int64_t q, uint64_t seed, void* U, int64_t ldu, void* sigma,
              void* V, int64_t ldv, int32_t* status);
 
+/* Faster randomized k-SVD (Sec. 5.3, Alg. 5.3): two passes over A.
+ *   C = A S            S an n x s count sketch of the columns (stream seed + 1)
+ *   L = P^T A, D = P^T C   P = P_cs P_2 (rmm_sketch_composite with p_cs and p,
+ *                      stream seed; kind2 = SRHT as in the algorithm, or
+ *                      GAUSSIAN as in its listing)
+ *   Q_D R_D = D        CholeskyQR2 in FP64
+ *   Ubar Sigmabar Vbar^T = rank-k SVD of Q_D^T L (s x n), FP64
+ *   U Sigma Vhat^T = SVD of C R_D^{-1} Ubar Sigmabar (m x k), FP64;  V = Vbar Vhat
+ * A is m x n (lda >= m); U m x k (ldu >= m), sigma k (descending), V n x k
+ * (ldv >= n), in the input type, signs as rmm_rsvd.  Requires 1 <= k <= s <=
+ * p <= p_cs, s <= 1024, p <= N = 2^ceil(log2 p_cs) for SRHT.  status as
+ * rmm_rsvd (RANK_DEFICIENT when D is numerically rank deficient). */
+int rmm_rsvd_faster_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m,
+                              int64_t n, int64_t k, int64_t s, int64_t p_cs, int64_t p,
+                              size_t* bytes);
+int rmm_rsvd_faster(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m, int64_t n,
+                    const void* A, int64_t lda, int64_t k, int64_t s, int64_t p_cs, int64_t p,
+                    uint64_t seed, void* U, int64_t ldu, void* sigma, void* V, int64_t ldv,
+                    int32_t* status);
+
 /* ---- least squares (Ch. 4) --------------------------------------------------
  * Sketch-and-solve (eq. 4.2): x~ = argmin ||S^T (A x - b)||_2 with one S of
  * the given kind applied to [A | b] (A m x d, lda >= m; b length m; d <= s).

@@ -72,6 +72,10 @@ def lib():
             "rmm_sketch_composite": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _u64,
                                      _vp, _i64],
             "rmm_rsvd_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_rsvd_faster_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, _i64, _i64, _i64,
+                                          ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_rsvd_faster": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _i64, _i64, _i64, _i64, _u64,
+                                _vp, _i64, _vp, _vp, _i64, _vp],
             "rmm_rsvd": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _i64, _i64, _i64, _u64,
                          _vp, _i64, _vp, _vp, _i64, _vp],
             "rmm_lsr_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -321,6 +325,25 @@ class Handle:
         self._prepare(ws.value)
         _check(lib().rmm_rsvd(self._h, dt, prec, m, n, _ptr(A), _ld(A), k, p, q, seed, _ptr(U),
                               _ld(U), _ptr(sig), _ptr(V), _ld(V), _ptr(status)), "rmm_rsvd")
+        return U, sig, V, status
+
+    def rsvd_faster(self, A: torch.Tensor, k: int, s: int, p_cs: int, p: int, seed: int,
+                    kind2="srht"):
+        """Alg. 5.3: (U, sigma, V, status); see rmm_rsvd_faster."""
+        A = colmajor(A)
+        m, n = A.shape
+        dt = _dt(A)
+        U = torch.empty(k, m, dtype=A.dtype, device=A.device).t()
+        V = torch.empty(k, n, dtype=A.dtype, device=A.device).t()
+        sig = torch.empty(k, dtype=A.dtype, device=A.device)
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_rsvd_faster_workspace(self._h, dt, _kind(kind2), m, n, k, s, p_cs, p,
+                                               ctypes.byref(ws)), "rmm_rsvd_faster_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_rsvd_faster(self._h, dt, _kind(kind2), m, n, _ptr(A), _ld(A), k, s, p_cs, p,
+                                     seed, _ptr(U), _ld(U), _ptr(sig), _ptr(V), _ld(V), _ptr(status)),
+               "rmm_rsvd_faster")
         return U, sig, V, status
 
     # ---- autotuning of the dense products (rmm_set_autotune) -------------------

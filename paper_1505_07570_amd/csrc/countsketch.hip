@@ -799,6 +799,132 @@ int countsketch_batch_run(rmm_ctx* h, int count, const rmm_sketch_desc* d, Carve
   return launch_status();
 }
 
+// ---- column count sketch C = A S (the first step of the faster k-SVD) --------------
+//
+// S is an n x s count sketch of the columns of A: column j of A goes, with
+// sign g_j, into column h_j of C (the words of the count-sketch stream for
+// index j).  A gather instead of a scatter: workgroup (row chunk, bucket c)
+// lists the columns of bucket c in increasing j, 2048 at a time (wave
+// ballots, one barrier per round), then sums them for its 4096 rows, 16 per
+// thread in registers, with 16-byte loads when the columns allow them.  Every
+// entry of C is a fixed-order sum, and A is read once.
+constexpr int kColRows = 16;               // rows per thread
+constexpr int kColChunk = 256 * kColRows;  // rows per workgroup
+constexpr int kColSeg = 8;                 // columns scanned per thread per segment
+
+__global__ void colcs_hash_kernel(int64_t n, uint32_t s, uint64_t seed, uint32_t* __restrict__ hs) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const uint32_t w = cs_word((uint64_t)j, seed);
+  hs[j] = cs_bucket(w, s) | ((w & 1u) << 31);
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void colcs_kernel(int64_t m, int64_t n, const T* __restrict__ A,
+                                                    int64_t lda, const uint32_t* __restrict__ hs,
+                                                    T* __restrict__ C, int64_t ldc) {
+  __shared__ int32_t list[256 * kColSeg];
+  __shared__ int32_t wcount[4];
+  __shared__ int32_t total;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const uint32_t c = blockIdx.y;
+  const int64_t r0 = (int64_t)blockIdx.x * kColChunk;
+  T acc[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[q][e] = T(0);
+  for (int64_t seg = 0; seg < n; seg += 256 * kColSeg) {
+    if (tid == 0) total = 0;
+    __syncthreads();
+#pragma unroll 1
+    for (int i = 0; i < kColSeg; ++i) {
+      const int64_t j = seg + (int64_t)i * 256 + tid;
+      const uint32_t w = j < n ? hs[j] : 0xFFFFFFFFu;
+      const bool hit = j < n && (w & 0x7FFFFFFFu) == c;
+      const uint64_t bal = __ballot(hit);
+      if (lane == 0) wcount[wave] = __popcll(bal);
+      __syncthreads();
+      int off = total;
+      for (int v = 0; v < wave; ++v) off += wcount[v];
+      if (hit) {
+        const int pos = off + __popcll(bal & ((1ull << lane) - 1ull));
+        list[pos] = (int32_t)((j - seg) | ((w >> 31) << 30));
+      }
+      __syncthreads();
+      if (tid == 0) total += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+      __syncthreads();
+    }
+    const int cnt = total;
+    for (int t = 0; t < cnt; ++t) {
+      const int32_t ent = list[t];
+      const int64_t j = seg + (ent & 0x3FFFFFFF);
+      const T sg = (ent >> 30) & 1 ? T(-1) : T(1);
+      const T* col = A + j * lda;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = r0 + q * 1024 + 4 * tid;
+        if (VEC) {
+          if (r < m) {
+            if constexpr (sizeof(T) == 4) {
+              const float4 x = *reinterpret_cast<const float4*>(col + r);
+              acc[q][0] += sg * x.x; acc[q][1] += sg * x.y; acc[q][2] += sg * x.z; acc[q][3] += sg * x.w;
+            } else {
+              const double2 x = *reinterpret_cast<const double2*>(col + r);
+              const double2 y = *reinterpret_cast<const double2*>(col + r + 2);
+              acc[q][0] += sg * x.x; acc[q][1] += sg * x.y; acc[q][2] += sg * y.x; acc[q][3] += sg * y.y;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (r + e < m) acc[q][e] += sg * col[r + e];
+        }
+      }
+    }
+    __syncthreads();  // the list is rewritten by the next segment
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t r = r0 + q * 1024 + 4 * tid + e;
+      if (r < m) C[r + (int64_t)c * ldc] = acc[q][e];
+    }
+}
+
+size_t countsketch_cols_workspace(int64_t n) {
+  Carver c(nullptr, 0);
+  c.take<uint32_t>((size_t)(n > 0 ? n : 1));
+  return c.off + kAlign;
+}
+
+template <typename T>
+int countsketch_cols_run(rmm_ctx* h, int64_t m, int64_t n, const T* A, int64_t lda, int64_t s,
+                         uint64_t seed, T* C, int64_t ldc, Carver& ws) {
+  if (m == 0 || s == 0) return RMM_OK;
+  if (n == 0) return launch_fill_zero<T>(C, m, s, ldc, h->stream);
+  const size_t mark = ws.off;
+  uint32_t* hs = ws.take<uint32_t>((size_t)n);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  hipLaunchKernelGGL(colcs_hash_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, h->stream, n,
+                     (uint32_t)s, seed, hs);
+  RMM_TRY(launch_status());
+  const bool vec = (uintptr_t)A % 16 == 0 && lda % 4 == 0 && m % 4 == 0;
+  dim3 grid((unsigned)((m + kColChunk - 1) / kColChunk), (unsigned)s);
+  if (vec)
+    hipLaunchKernelGGL((colcs_kernel<T, true>), grid, dim3(256), 0, h->stream, m, n, A, lda, hs, C, ldc);
+  else
+    hipLaunchKernelGGL((colcs_kernel<T, false>), grid, dim3(256), 0, h->stream, m, n, A, lda, hs, C, ldc);
+  ws.off = mark;
+  return launch_status();
+}
+
+template int countsketch_cols_run<float>(rmm_ctx*, int64_t, int64_t, const float*, int64_t, int64_t,
+                                         uint64_t, float*, int64_t, Carver&);
+template int countsketch_cols_run<double>(rmm_ctx*, int64_t, int64_t, const double*, int64_t,
+                                          int64_t, uint64_t, double*, int64_t, Carver&);
+
 template bool countsketch_batch_grouped<float>(int, const rmm_sketch_desc*);
 template bool countsketch_batch_grouped<double>(int, const rmm_sketch_desc*);
 template size_t countsketch_batch_workspace<float>(const rmm_ctx*, int, const rmm_sketch_desc*);

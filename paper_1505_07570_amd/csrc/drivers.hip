@@ -240,6 +240,21 @@ LsBufs take_ls(Carver& ws, int64_t s, int d) {
   return b;
 }
 
+// CholeskyQR2 of the s x d FP64 matrix Cs (ld s): b.Q = Cs R1 R2 with the
+// two inverse factors kept in b.R1, b.R2 (their diagonals in b.d1, b.d2)
+int cholqr2(rmm_ctx* h, int64_t s, int d, const double* Cs, const LsBufs& b, Carver& ws) {
+  const double tau = 64.0 * kEps * (double)s;
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, d, d, s, Cs, s, Cs, s, 1.0, b.G, d, ws)));
+  RMM_TRY(cholinv(h, d, b.G, d, tau, b.R1, b.d1, nullptr, ws));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, (int)s, d, d, Cs, s, b.R1, d, 1.0,
+                                                b.Q1, s, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, d, d, s, b.Q1, s, b.Q1, s, 1.0, b.G,
+                                                d, ws)));
+  RMM_TRY(cholinv(h, d, b.G, d, tau, b.R2, b.d2, nullptr, ws));
+  return gemm<double, double, double, double>(h, false, false, (int)s, d, d, b.Q1, s, b.R2, d, 1.0,
+                                              b.Q, s, ws);
+}
+
 int ls_solve(rmm_ctx* h, int64_t s, int d, const double* Cs, const LsBufs& b, double* x,
              int32_t* status, Carver& ws) {
   const double tau = 64.0 * kEps * (double)s;
@@ -375,6 +390,123 @@ bool ld_bad(int64_t ld, int64_t rows) { return ld < (rows > 1 ? rows : 1); }
 
 bool kind_ok(rmm_sketch_kind k) { return k == RMM_GAUSSIAN || k == RMM_SRHT || k == RMM_COUNTSKETCH; }
 
+// ---- faster randomized k-SVD (Sec. 5.3, Alg. 5.3) ----------------------------
+
+__global__ void scale_cols_kernel(int rows, int k, const double* __restrict__ X, int64_t ldx,
+                                  const double* __restrict__ sc, double* __restrict__ Y) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * k) return;
+  const int a = e % rows, c = e / rows;
+  Y[a + (int64_t)c * rows] = X[a + (int64_t)c * ldx] * sc[c];
+}
+
+// Steps of Alg. 5.3: C = A S (column count sketch, stream seed + 1);
+// L = P^T A, D = P^T C with P = P_cs P_2 (composite, stream seed); Q_D R_D =
+// D by CholeskyQR2 (R_D^{-1} = R1 R2); Ubar Sigmabar Vbar^T = rank-k SVD of
+// Z = Q_D^T L through Z Z^T; M = C R_D^{-1} Ubar Sigmabar; U Sigma Vhat^T =
+// SVD of M through M^T M; V = Vbar Vhat.  C, L, D in the input type, the
+// small algebra in FP64.
+template <typename T>
+int rsvd_faster_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind2, int64_t m, int64_t n, const T* A,
+                     int64_t lda, int k, int s, int64_t pcs, int p, uint64_t seed, T* U, int64_t ldu,
+                     T* sigma, T* V, int64_t ldv, int32_t* status, size_t* bytes) {
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  const int64_t wide = n > s ? n : s;
+  T* C = ws.take<T>((size_t)m * s);
+  T* Y = ws.take<T>((size_t)pcs * wide);
+  T* L = ws.take<T>((size_t)p * n);
+  T* D = ws.take<T>((size_t)p * s);
+  double* Dd = ws.take<double>((size_t)p * s);
+  LsBufs lb = take_ls(ws, p, s);
+  double* Ri = ws.take<double>((size_t)s * s);
+  double* Z = ws.take<double>((size_t)s * n);
+  double* evals = ws.take<double>((size_t)s);
+  double* Vr = ws.take<double>((size_t)s * s);
+  double* W = ws.take<double>((size_t)s * k);
+  double* sb = ws.take<double>((size_t)k);
+  double* T1 = ws.take<double>((size_t)s * k);
+  double* T2 = ws.take<double>((size_t)s * k);
+  double* Vb = ws.take<double>((size_t)n * k);
+  double* M = ws.take<double>((size_t)m * k);
+  double* G3 = ws.take<double>((size_t)k * k);
+  double* ev3 = ws.take<double>((size_t)k);
+  double* V3 = ws.take<double>((size_t)k * k);
+  double* W3 = ws.take<double>((size_t)k * k);
+  size_t scratch = countsketch_cols_workspace(n);
+  scratch = smax(scratch, countsketch_workspace<T>(h, m, (int)n, pcs));
+  scratch = smax(scratch, countsketch_workspace<T>(h, m, s, pcs));
+  scratch = smax(scratch, sketch_scratch<T>(h, kind2, pcs, (int)n, p));
+  scratch = smax(scratch, sketch_scratch<T>(h, kind2, pcs, s, p));
+  scratch = smax(scratch, ls_scratch(h, p, s));
+  scratch = smax(scratch, gemm_workspace<double>(h, s, (int)n, p));
+  scratch = smax(scratch, gemm_workspace<double>(h, s, s, n));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, s));
+  scratch = smax(scratch, gemm_workspace<double>(h, s, k, s));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, s));
+  scratch = smax(scratch, gemm_workspace<double>(h, k, k, m));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, k));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, k));
+  scratch = smax(scratch, jacobi_workspace(s));
+  scratch = smax(scratch, jacobi_workspace(k));
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  RMM_TRY(zero_status(h, status));
+  const size_t mark = ws.off;
+  // step 1 and the two composite sketches of step 2
+  RMM_TRY(countsketch_cols_run<T>(h, m, n, A, lda, s, seed + 1, C, m, ws));
+  ws.off = mark;
+  RMM_TRY(countsketch_run<T>(h, m, (int)n, A, lda, nullptr, pcs, seed, Y, pcs, ws));
+  ws.off = mark;
+  RMM_TRY(run_sketch<T>(h, kind2, pcs, (int)n, Y, pcs, nullptr, p, seed, L, p, ws));
+  ws.off = mark;
+  RMM_TRY(countsketch_run<T>(h, m, s, C, m, nullptr, pcs, seed, Y, pcs, ws));
+  ws.off = mark;
+  RMM_TRY(run_sketch<T>(h, kind2, pcs, s, Y, pcs, nullptr, p, seed, D, p, ws));
+  ws.off = mark;
+  // step 3: CholeskyQR2 of D, R_D^{-1} = R1 R2
+  RMM_TRY((copy_cast<T, double>(h, p, s, D, p, Dd, p)));
+  RMM_TRY(cholqr2(h, p, s, Dd, lb, ws));
+  RMM_TRY(rank_check(h, s, lb.d1, lb.d2, 10.0 * (double)p * kEps, status));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, s, s, s, lb.R1, s, lb.R2, s, 1.0, Ri,
+                                                s, ws)));
+  // step 4: rank-k SVD of Z = Q_D^T L through Z Z^T
+  RMM_TRY((gemm<double, T, double, double>(h, true, false, s, (int)n, p, lb.Q, p, L, p, 1.0, Z, s, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, false, true, s, s, (int)n, Z, s, Z, s, 1.0, lb.G, s,
+                                                ws)));
+  RMM_TRY(jacobi_eig(h, s, lb.G, s, evals, Vr, status, ws));
+  RMM_TRY(svd_from_eig<double>(h, s, k, evals, Vr, W, sb));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, (int)n, k, s, Z, s, W, s, 1.0, Vb, n,
+                                                ws)));
+  // step 5: M = C R_D^{-1} Ubar Sigmabar and its SVD through M^T M
+  hipLaunchKernelGGL(scale_cols_kernel, dim3((s * k + 255) / 256), dim3(256), 0, h->stream, s, k, Vr,
+                     (int64_t)s, sb, T1);
+  RMM_TRY(launch_status());
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, s, k, s, Ri, s, T1, s, 1.0, T2, s, ws)));
+  RMM_TRY((gemm<T, double, double, double>(h, false, false, (int)m, k, s, C, m, T2, s, 1.0, M, m, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, k, k, m, M, m, M, m, 1.0, G3, k, ws)));
+  RMM_TRY(jacobi_eig(h, k, G3, k, ev3, V3, status, ws));
+  RMM_TRY(svd_from_eig<T>(h, k, k, ev3, V3, W3, sigma));
+  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)m, k, k, M, m, W3, k, 1.0, U, ldu, ws)));
+  // step 6: V = Vbar Vhat
+  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)n, k, k, Vb, n, V3, k, 1.0, V, ldv,
+                                           ws)));
+  return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
+}
+
+int rsvd_faster_args(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m, int64_t n,
+                     int64_t k, int64_t s, int64_t pcs, int64_t p) {
+  if (!h || !dt_ok(dt) || m < 1 || n < 1 || k < 1 || s < k || p < s || pcs < p)
+    return RMM_ERR_INVALID_ARG;
+  if (kind2 != RMM_GAUSSIAN && kind2 != RMM_SRHT) return RMM_ERR_UNSUPPORTED;
+  if (kind2 == RMM_SRHT && p > (1ll << ceil_log2((uint64_t)pcs))) return RMM_ERR_INVALID_ARG;
+  if (s > 1024 || p > (1 << 20) || pcs >= (1ll << 30) || m >= (1ll << 31) || n >= (1ll << 30))
+    return RMM_ERR_UNSUPPORTED;
+  return RMM_OK;
+}
+
 int rsvd_args(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t n, int64_t k,
               int64_t p) {
   if (!h || !dt_ok(dt) || m < 1 || n < 1 || k < 1 || p < 0) return RMM_ERR_INVALID_ARG;
@@ -429,6 +561,34 @@ int rmm_rsvd(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t 
                             (float*)U, ldu, (float*)sigma, (float*)V, ldv, status, nullptr);
   return rsvd_impl<double>(h, true, m, n, (const double*)A, lda, (int)k, (int)p, (int)q, seed,
                            (double*)U, ldu, (double*)sigma, (double*)V, ldv, status, nullptr);
+}
+
+int rmm_rsvd_faster_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m,
+                              int64_t n, int64_t k, int64_t s, int64_t pcs, int64_t p,
+                              size_t* bytes) {
+  RMM_TRY(rsvd_faster_args(h, dt, kind2, m, n, k, s, pcs, p));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return rsvd_faster_impl<float>(h, false, kind2, m, n, nullptr, m, (int)k, (int)s, pcs, (int)p, 0,
+                                   nullptr, m, nullptr, nullptr, n, nullptr, bytes);
+  return rsvd_faster_impl<double>(h, false, kind2, m, n, nullptr, m, (int)k, (int)s, pcs, (int)p, 0,
+                                  nullptr, m, nullptr, nullptr, n, nullptr, bytes);
+}
+
+int rmm_rsvd_faster(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m, int64_t n,
+                    const void* A, int64_t lda, int64_t k, int64_t s, int64_t pcs, int64_t p,
+                    uint64_t seed, void* U, int64_t ldu, void* sigma, void* V, int64_t ldv,
+                    int32_t* status) {
+  RMM_TRY(rsvd_faster_args(h, dt, kind2, m, n, k, s, pcs, p));
+  if (!A || !U || !sigma || !V || ld_bad(lda, m) || ld_bad(ldu, m) || ld_bad(ldv, n))
+    return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return rsvd_faster_impl<float>(h, true, kind2, m, n, (const float*)A, lda, (int)k, (int)s, pcs,
+                                   (int)p, seed, (float*)U, ldu, (float*)sigma, (float*)V, ldv, status,
+                                   nullptr);
+  return rsvd_faster_impl<double>(h, true, kind2, m, n, (const double*)A, lda, (int)k, (int)s, pcs,
+                                  (int)p, seed, (double*)U, ldu, (double*)sigma, (double*)V, ldv,
+                                  status, nullptr);
 }
 
 int rmm_lsr_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m, int64_t d,

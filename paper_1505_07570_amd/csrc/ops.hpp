@@ -5,6 +5,12 @@
 
 namespace rmm {
 
+// C (m x s) = A S for an n x s count sketch S of the columns of A (stream of seed)
+size_t countsketch_cols_workspace(int64_t n);
+template <typename T>
+int countsketch_cols_run(rmm_ctx* h, int64_t m, int64_t n, const T* A, int64_t lda, int64_t s,
+                         uint64_t seed, T* C, int64_t ldc, Carver& ws);
+
 template <typename T>
 size_t countsketch_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s);
 template <typename T>

@@ -284,3 +284,55 @@ def test_autotune_plans_kept_saved_and_loaded(h, tmp_path):
     assert u.autotune_count() == t.autotune_count()
     U3, s3, V3, _ = u.rsvd(Ad, 10, 6, 1, 3)
     assert torch.equal(s3, s2) and torch.equal(U3, U2) and torch.equal(V3, V2)
+
+
+# ---- faster randomized k-SVD (Alg. 5.3) -------------------------------------------
+
+def _decaying(m, n, seed, rate=0.8):
+    r = np.random.default_rng(seed)
+    Uq, _ = np.linalg.qr(r.standard_normal((m, min(m, n))))
+    Vq, _ = np.linalg.qr(r.standard_normal((n, min(m, n))))
+    sv = rate ** np.arange(min(m, n))
+    return (Uq * sv) @ Vq.T
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("kind2,ok2", [("srht", osk.SRHT), ("gaussian", osk.GAUSSIAN)])
+@pytest.mark.parametrize("m,n,k,s,pcs,p", [(1000, 400, 8, 40, 600, 200), (1001, 333, 5, 21, 257, 60),
+                                           (4096, 512, 20, 64, 2048, 256)])
+def test_rsvd_faster_parity(h, dtype, kind2, ok2, m, n, k, s, pcs, p):
+    A = _decaying(m, n, m + n)
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    A = A.astype(npdt)
+    seed = 31 + k
+    U, sig, V, st = h.rsvd_faster(dev(A, dtype), k, s, pcs, p, seed, kind2)
+    Ur, sr, Vr = orsvd.ksvd_faster(A.astype(np.float64), k, s, pcs, p, seed, ok2,
+                                   fp64=(dtype == torch.float64))
+    tol = 1e-10 if dtype == torch.float64 else 2e-4
+    assert int(st.item()) == 0
+    U, sig, V = host(U), host(sig), host(V)
+    assert np.abs(sig - sr).max() <= tol * sr[0]
+    assert rel((U * sig) @ V.T, (Ur * sr) @ Vr.T) < tol
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=10 * tol)
+
+
+def test_rsvd_faster_exact_recovery_of_rank_k(h):
+    r = np.random.default_rng(5)
+    m, n, k = 2000, 300, 6
+    A = r.standard_normal((m, k)) @ r.standard_normal((k, n))
+    U, sig, V, st = h.rsvd_faster(dev(A), k, 12, 400, 48, 3)
+    U, sig, V = host(U), host(sig), host(V)
+    assert rel((U * sig) @ V.T, A) < 1e-10
+    np.testing.assert_allclose(sig, np.linalg.svd(A, compute_uv=False)[:k], rtol=1e-10)
+
+
+def test_rsvd_faster_invalid(h):
+    A = torch.zeros(100, 50, dtype=torch.float64, device="cuda")
+    with pytest.raises(rmm.RmmError):
+        h.rsvd_faster(A, 8, 4, 64, 16, 1)              # s < k
+    with pytest.raises(rmm.RmmError):
+        h.rsvd_faster(A, 4, 8, 16, 32, 1)              # p > p_cs
+    with pytest.raises(rmm.RmmError):
+        h.rsvd_faster(A, 4, 8, 64, 16, 1, "countsketch")
+    with pytest.raises(rmm.RmmError):
+        h.rsvd_faster(A, 4, 1025, 2048, 1025, 1)      # s above the small-solve limit
