@@ -70,6 +70,14 @@ __device__ __forceinline__ double recip_f64(double x) {
 // Schur part with c > i); inside, an entry with j < c < i is left alone and
 // r_j = 1.  Rows past l have zero pivots and thresholds, so their steps
 // change nothing; `live` has bit r set for rows below l.
+// 1/sqrt(x), x > 0 finite: the hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  return y * fma(-hx * y, y, 1.5);
+}
+
 template <int NH, int HP>
 __device__ __forceinline__ void panel_factor(double (&w)[kPanel][NH], int lane, int p0, unsigned live,
                                              double thr, double (*prow)[kLdsMaxL],
@@ -391,8 +399,10 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
     for (int e = tid; e < l * l; e += blockDim.x) {
       const int a = e % l, b = e / l;
       if (a < b) {
+        // exactly the rotation test below
         const double gpq = S[a + b * lds];
-        if (fabs(gpq) > abs_tol && fabs(gpq) > 0x1p-52 * sqrt(fabs(S[a + a * lds] * S[b + b * lds])))
+        if (fabs(gpq) > abs_tol && fabs(gpq) > 1e-300 &&
+            gpq * gpq > 0x1p-104 * fabs(S[a + a * lds] * S[b + b * lds]))
           done = 0;
       }
     }
@@ -407,10 +417,17 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
         if (q < l) {
           const double gpq = S[p + q * lds];
           const double gpp = S[p + p * lds], gqq = S[q + q * lds];
-          if (fabs(gpq) > abs_tol && fabs(gpq) > 0x1p-52 * sqrt(fabs(gpp * gqq))) {
-            const double theta = (gqq - gpp) / (2.0 * gpq);
-            tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(tt * tt + 1.0);
+          // same test as |g_pq| > 2^-52 sqrt(|g_pp g_qq|), squared; the
+          // rotation is built from refined hardware estimates (a short
+          // dependent chain at the head of every round)
+          if (fabs(gpq) > abs_tol && fabs(gpq) > 1e-300 &&
+              gpq * gpq > 0x1p-104 * fabs(gpp * gqq)) {
+            const double theta = (gqq - gpp) * recip_f64(2.0 * gpq);
+            const double at = fabs(theta);
+            const double w = at * at + 1.0;
+            const double den = at > 0x1p26 ? 2.0 * at : at + w * rsqrt_f64(w);
+            tt = (theta >= 0 ? 1.0 : -1.0) * recip_f64(den);
+            c = rsqrt_f64(tt * tt + 1.0);
             s = tt * c;
           }
         }
