@@ -186,7 +186,9 @@ def rsvd_spectrum(h, reps, lat):
     seed = synth.sketch_seed(3)
     out = {"m": m, "n": n, "k": k, "p": p, "q": q, "sigma": "1/i", "opt_resid_fro": opt}
     for name, prec in (("fp32", rmm.PREC_NATIVE), ("bf16", rmm.PREC_BF16), ("fp8", rmm.PREC_FP8)):
+        h.set_autotune(True)  # the dense products get their tuned launch plans
         U, s, V, st = h.rsvd(A, k, p, q, seed, prec=prec)
+        h.set_autotune(False)
         ts = lat(lambda: h.rsvd(A, k, p, q, seed, prec=prec), reps)
         s64 = s.double().cpu().numpy()
         # ||A - U diag(s) V^T||_F in row blocks
@@ -209,7 +211,9 @@ def rsvd_spectrum(h, reps, lat):
     # the faster randomized k-SVD of Alg. 5.3 on the same A (two passes):
     # s = 128 (> k), composite row sketch to p_cs = 4096 then SRHT to p = 1024
     fs, fpcs, fp = 128, 4096, 1024
+    h.set_autotune(True)
     U, s, V, st = h.rsvd_faster(A, k, fs, fpcs, fp, seed, "srht")
+    h.set_autotune(False)
     ts = lat(lambda: h.rsvd_faster(A, k, fs, fpcs, fp, seed, "srht"), reps)
     s64 = s.double().cpu().numpy()
     acc = 0.0

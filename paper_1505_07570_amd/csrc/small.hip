@@ -921,22 +921,31 @@ int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* ev
 // ---- sign convention, small glue -------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(256) void sign_fix_kernel(int64_t m, int64_t n, T* __restrict__ U,
-                                                       int64_t ldu, T* __restrict__ V, int64_t ldv) {
-  __shared__ double bv[256];
-  __shared__ int64_t bi[256];
+__global__ __launch_bounds__(1024) void sign_fix_kernel(int64_t m, int64_t n, T* __restrict__ U,
+                                                        int64_t ldu, T* __restrict__ V, int64_t ldv) {
+  // argmax |u_i| with the lowest index on ties: each thread scans its rows in
+  // increasing order, four independent loads per step, then a tree reduction
+  __shared__ double bv[1024];
+  __shared__ int64_t bi[1024];
   const int64_t c = blockIdx.x;
   T* u = U + c * ldu;
   double best = -1.0;
   int64_t besti = 0;
-  for (int64_t i = threadIdx.x; i < m; i += 256) {
-    const double a = fabs((double)u[i]);
-    if (a > best) { best = a; besti = i; }
+  for (int64_t i0 = threadIdx.x; i0 < m; i0 += 4096) {
+    double a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t i = i0 + 1024 * e;
+      a[e] = i < m ? fabs((double)u[i]) : -1.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (a[e] > best) { best = a[e]; besti = i0 + 1024 * e; }
   }
   bv[threadIdx.x] = best;
   bi[threadIdx.x] = besti;
   __syncthreads();
-  for (int st = 128; st > 0; st >>= 1) {
+  for (int st = 512; st > 0; st >>= 1) {
     if (threadIdx.x < st) {
       const double o = bv[threadIdx.x + st];
       const int64_t oi = bi[threadIdx.x + st];
@@ -950,15 +959,15 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(int64_t m, int64_t n, T* 
   const bool flip = (double)u[bi[0]] < 0.0;
   __syncthreads();
   if (!flip) return;
-  for (int64_t i = threadIdx.x; i < m; i += 256) u[i] = -u[i];
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) u[i] = -u[i];
   T* v = V + c * ldv;
-  for (int64_t i = threadIdx.x; i < n; i += 256) v[i] = -v[i];
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v[i] = -v[i];
 }
 
 template <typename T>
 int sign_fix(const rmm_ctx* h, int64_t m, int64_t n, int k, T* U, int64_t ldu, T* V, int64_t ldv) {
   if (k == 0) return RMM_OK;
-  hipLaunchKernelGGL((sign_fix_kernel<T>), dim3(k), dim3(256), 0, h->stream, m, n, U, ldu, V, ldv);
+  hipLaunchKernelGGL((sign_fix_kernel<T>), dim3(k), dim3(1024), 0, h->stream, m, n, U, ldu, V, ldv);
   return launch_status();
 }
 
