@@ -118,3 +118,37 @@ def ksvd_faster(A, k: int, s: int, p_cs: int, p: int, seed: int, kind2: int = 1,
     Vt = Vb @ Vht.T
     Ut, Vt = fix_signs(Ut, Vt)
     return Ut, st, Vt
+
+
+# --------------------------------------------------------------------------
+# k-SVD by the block Lanczos method (Sec. 5.1, Alg. 5.1)
+# --------------------------------------------------------------------------
+
+def block_lanczos(A, k: int, s: int, q: int, seed: int, fp64: bool = True, Omega=None):
+    """Alg. 5.1 with q Krylov blocks K = [C, (A A^T) C, ..., (A A^T)^{q-1} C],
+    C = A Omega (Omega as in rsvd: n x s, unscaled, stream of the rsvd).
+
+    Reading of the stability remark of Sec. 5.1: block i + 1 is (A A^T)
+    applied to the orthonormal block i, orthogonalized against every
+    earlier block (two passes of block Gram-Schmidt) and then QR'd; the
+    blocks together span range(K), so Q_C is an orthonormal basis of it.
+    Then B = Q_C^T A (sq x n), B = Ubar S V^T truncated to k, U = Q_C Ubar.
+    Returns (U (m x k), sigma (k,), V (n x k), Q_C (m x sq))."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    if not (1 <= k <= s * q and s * q <= min(m, n) and q >= 1):
+        raise ValueError("need 1 <= k <= s q <= min(m, n), q >= 1")
+    Om = omega(n, s, seed, fp64) if Omega is None else np.asarray(Omega, dtype=np.float64)
+    blocks = [qr_pos(A @ Om)[0]]
+    for _ in range(1, q):
+        Y = A @ (A.T @ blocks[-1])
+        for _pass in range(2):
+            for Qb in blocks:
+                Y = Y - Qb @ (Qb.T @ Y)
+        blocks.append(qr_pos(Y)[0])
+    Q = np.hstack(blocks)
+    Ub, sig, Vt = np.linalg.svd(Q.T @ A, full_matrices=False)
+    U = Q @ Ub[:, :k]
+    V = Vt[:k, :].T
+    U, V = fix_signs(U, V)
+    return U, sig[:k].copy(), V, Q

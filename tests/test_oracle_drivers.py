@@ -276,3 +276,43 @@ def test_ksvd_faster_error_near_truncation_floor():
     opt = np.sqrt(np.sum(sv[k:] ** 2))
     assert err < 1.2 * opt
     np.testing.assert_allclose(sig, sv[:k], rtol=0.05)
+
+
+# ---- block Lanczos k-SVD (Alg. 5.1) --------------------------------------------------
+
+def test_block_lanczos_one_block_is_the_prototype():
+    """q = 1 block is Alg. 5.2 with no power step on the same Omega."""
+    r = np.random.default_rng(31)
+    A = r.standard_normal((300, 120))
+    U, s, V, Q = rsvd.block_lanczos(A, 5, 12, 1, 4)
+    Ur, sr, Vr, Qr = rsvd.rsvd(A, 5, 7, 0, 4)
+    np.testing.assert_allclose(s, sr, rtol=1e-12)
+    np.testing.assert_allclose((U * s) @ V.T, (Ur * sr) @ Vr.T, atol=1e-10)
+
+
+def test_block_lanczos_exact_recovery_and_orthonormal_basis():
+    """rank(A) = s q: the two Krylov blocks span range(A) exactly (a rank
+    below s q makes K rank deficient, the instability the paper warns of)."""
+    r = np.random.default_rng(32)
+    m, n, rk = 400, 200, 10
+    A = r.standard_normal((m, rk)) @ r.standard_normal((rk, n))
+    U, s, V, Q = rsvd.block_lanczos(A, rk, 5, 2, 6)
+    np.testing.assert_allclose(Q.T @ Q, np.eye(10), atol=1e-12)
+    np.testing.assert_allclose((U * s) @ V.T, A, atol=1e-9 * np.abs(A).max())
+
+
+def test_block_lanczos_beats_power_iteration_with_the_same_products():
+    """The q-block Krylov space contains the block power iterate (A A^T)^{q-1} C,
+    so its projection error is no larger than the prototype's with q - 1
+    power steps on the same Omega."""
+    r = np.random.default_rng(33)
+    m, n = 600, 300
+    Uq, _ = np.linalg.qr(r.standard_normal((m, n)))
+    Vq, _ = np.linalg.qr(r.standard_normal((n, n)))
+    A = (Uq * (1.0 / np.arange(1, n + 1))) @ Vq.T
+    for q in (2, 3):
+        _, _, _, Q = rsvd.block_lanczos(A, 10, 15, q, 8)
+        _, _, _, Qp = rsvd.rsvd(A, 10, 5, q - 1, 8)
+        e_l = np.linalg.norm(A - Q @ (Q.T @ A))
+        e_p = np.linalg.norm(A - Qp @ (Qp.T @ A))
+        assert e_l <= e_p * (1 + 1e-9)
