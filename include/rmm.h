@@ -223,6 +223,19 @@ int rmm_rsvd(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m,
  * (ldv >= n), in the input type, signs as rmm_rsvd.  Requires 1 <= k <= s <=
  * p <= p_cs, s <= 1024, p <= N = 2^ceil(log2 p_cs) for SRHT.  status as
  * rmm_rsvd (RANK_DEFICIENT when D is numerically rank deficient). */
+/* k-SVD by the block Lanczos method (Sec. 5.1, Alg. 5.1): q Krylov blocks
+ * K = [C, (A A^T) C, ..., (A A^T)^{q-1} C], C = A Omega (Omega n x s, the
+ * stream of rmm_rsvd); each block after the first is (A A^T) of the previous
+ * orthonormal block, orthogonalized against all earlier ones (two passes of
+ * block Gram-Schmidt) and CholeskyQR2'd, so Q_C (m x sq) spans range(K).
+ * Then B = Q_C^T A, its top-k SVD, U = Q_C Ubar; outputs, signs and status
+ * as rmm_rsvd.  Requires 1 <= k <= s q <= min(m, n), s q <= 1024. */
+int rmm_rsvd_lanczos_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, int64_t k,
+                               int64_t s, int64_t q, size_t* bytes);
+int rmm_rsvd_lanczos(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, const void* A,
+                     int64_t lda, int64_t k, int64_t s, int64_t q, uint64_t seed, void* U,
+                     int64_t ldu, void* sigma, void* V, int64_t ldv, int32_t* status);
+
 int rmm_rsvd_faster_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m,
                               int64_t n, int64_t k, int64_t s, int64_t p_cs, int64_t p,
                               size_t* bytes);

@@ -72,6 +72,10 @@ def lib():
             "rmm_sketch_composite": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _i64, _u64,
                                      _vp, _i64],
             "rmm_rsvd_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_rsvd_lanczos_workspace": [_vp, _i32, _i64, _i64, _i64, _i64, _i64,
+                                           ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_rsvd_lanczos": [_vp, _i32, _i64, _i64, _vp, _i64, _i64, _i64, _i64, _u64, _vp, _i64,
+                                 _vp, _vp, _i64, _vp],
             "rmm_rsvd_faster_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, _i64, _i64, _i64,
                                           ctypes.POINTER(ctypes.c_size_t)],
             "rmm_rsvd_faster": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _i64, _i64, _i64, _i64, _u64,
@@ -325,6 +329,24 @@ class Handle:
         self._prepare(ws.value)
         _check(lib().rmm_rsvd(self._h, dt, prec, m, n, _ptr(A), _ld(A), k, p, q, seed, _ptr(U),
                               _ld(U), _ptr(sig), _ptr(V), _ld(V), _ptr(status)), "rmm_rsvd")
+        return U, sig, V, status
+
+    def rsvd_lanczos(self, A: torch.Tensor, k: int, s: int, q: int, seed: int):
+        """Alg. 5.1 with q Krylov blocks of width s: (U, sigma, V, status)."""
+        A = colmajor(A)
+        m, n = A.shape
+        dt = _dt(A)
+        U = torch.empty(k, m, dtype=A.dtype, device=A.device).t()
+        V = torch.empty(k, n, dtype=A.dtype, device=A.device).t()
+        sig = torch.empty(k, dtype=A.dtype, device=A.device)
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_rsvd_lanczos_workspace(self._h, dt, m, n, k, s, q, ctypes.byref(ws)),
+               "rmm_rsvd_lanczos_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_rsvd_lanczos(self._h, dt, m, n, _ptr(A), _ld(A), k, s, q, seed, _ptr(U),
+                                      _ld(U), _ptr(sig), _ptr(V), _ld(V), _ptr(status)),
+               "rmm_rsvd_lanczos")
         return U, sig, V, status
 
     def rsvd_faster(self, A: torch.Tensor, k: int, s: int, p_cs: int, p: int, seed: int,

@@ -119,6 +119,75 @@ int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t ld
   return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
 }
 
+// ---- k-SVD by block Lanczos (Sec. 5.1, Alg. 5.1) ----------------------------------
+//
+// q Krylov blocks of width s: Q_0 = qr(A Omega); block i + 1 = A (A^T Q_i),
+// orthogonalized against every earlier block by two passes of block
+// Gram-Schmidt, then CholeskyQR2 (the blocks span range(K) of Alg. 5.1).  Then
+// Z = A^T Q_C (n x sq), the small SVD of B = Z^T through Z^T Z, U = Q_C Ubar,
+// V = Z W, as in the prototype.
+template <typename T>
+int lanczos_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t lda, int k, int s,
+                 int q, uint64_t seed, T* U, int64_t ldu, T* sigma, T* V, int64_t ldv,
+                 int32_t* status, size_t* bytes) {
+  const int L = s * q;
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  T* Om = ws.take<T>((size_t)n * s);
+  T* Qc = ws.take<T>((size_t)m * L);
+  T* Y = ws.take<T>((size_t)m * s);
+  T* Z = ws.take<T>((size_t)n * L);
+  OrthBufs ob;
+  ob.G = ws.take<double>((size_t)L * L);
+  ob.Rinv = ws.take<double>((size_t)s * s);
+  ob.diag = ws.take<double>((size_t)s);
+  ob.Xd = ws.take<double>((size_t)m * s);
+  double* Wb = ws.take<double>((size_t)s * s);
+  double* evals = ws.take<double>((size_t)L);
+  double* Vr = ws.take<double>((size_t)L * L);
+  double* W = ws.take<double>((size_t)L * k);
+  size_t scratch = orth_scratch<T>(h, m, s);
+  scratch = smax(scratch, gemm_workspace<T>(h, (int)m, s, n));
+  scratch = smax(scratch, gauss_sketch_workspace<T>(h, m, (int)n, s));
+  scratch = smax(scratch, gauss_sketch_workspace<T>(h, m, (int)n, L));
+  scratch = smax(scratch, gemm_workspace<double>(h, s, s, m));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)m, s, s));
+  scratch = smax(scratch, gemm_workspace<double>(h, L, L, n));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, L));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, L));
+  scratch = smax(scratch, jacobi_workspace(L));
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const double tau_m = 64.0 * kEps * (double)(m > s ? m : s);
+  RMM_TRY(zero_status(h, status));
+  RMM_TRY(launch_gaussian<T>(h, TAG_GAUSS_RSVD, n, s, seed, Om, n));
+  RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, s, n, A, lda, Om, n, 1.0, Y, m, ws)));
+  RMM_TRY(orth<T>(h, m, s, Y, m, Qc, m, ob, tau_m, status, ws));
+  for (int i = 1; i < q; ++i) {
+    const T* Qp = Qc + (int64_t)(i - 1) * s * m;
+    RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Qp, m, s, Z, n, ws));  // Z = A^T Q_{i-1}
+    RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, s, n, A, lda, Z, n, 1.0, Y, m, ws)));
+    for (int pass = 0; pass < 2; ++pass)
+      for (int b = 0; b < i; ++b) {
+        const T* Qb = Qc + (int64_t)b * s * m;
+        RMM_TRY((gemm<T, T, double, double>(h, true, false, s, s, m, Qb, m, Y, m, 1.0, Wb, s, ws)));
+        RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, s, s, Qb, m, Wb, s, -1.0, Y, m,
+                                            ws, 1.0)));
+      }
+    RMM_TRY(orth<T>(h, m, s, Y, m, Qc + (int64_t)i * s * m, m, ob, tau_m, status, ws));
+  }
+  // Z = A^T Q_C = B^T and the small SVD of B through B B^T = Z^T Z
+  RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Qc, m, L, Z, n, ws));
+  RMM_TRY((gemm<T, T, double, double>(h, true, false, L, L, n, Z, n, Z, n, 1.0, ob.G, L, ws)));
+  RMM_TRY(jacobi_eig(h, L, ob.G, L, evals, Vr, status, ws));
+  RMM_TRY(svd_from_eig<T>(h, L, k, evals, Vr, W, sigma));
+  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, k, L, Qc, m, Vr, L, 1.0, U, ldu, ws)));
+  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)n, k, L, Z, n, W, L, 1.0, V, ldv, ws)));
+  return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
+}
+
 // ---- randomized SVD with BF16 / FP8 passes over A ----------------------------------------
 //
 // Same steps as rsvd_impl; every product with A runs on a one-time quantized
@@ -589,6 +658,33 @@ int rmm_rsvd_faster(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind2, int64_t m
   return rsvd_faster_impl<double>(h, true, kind2, m, n, (const double*)A, lda, (int)k, (int)s, pcs,
                                   (int)p, seed, (double*)U, ldu, (double*)sigma, (double*)V, ldv,
                                   status, nullptr);
+}
+
+int rmm_rsvd_lanczos_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, int64_t k,
+                               int64_t s, int64_t q, size_t* bytes) {
+  if (!h || !dt_ok(dt) || k < 1 || s < 1 || q < 1 || k > s * q || s * q > m || s * q > n || !bytes)
+    return RMM_ERR_INVALID_ARG;
+  if (s * q > 1024 || m >= (1ll << 31) || n >= (1ll << 30)) return RMM_ERR_UNSUPPORTED;
+  if (dt == RMM_F32)
+    return lanczos_impl<float>(h, false, m, n, nullptr, m, (int)k, (int)s, (int)q, 0, nullptr, m,
+                               nullptr, nullptr, n, nullptr, bytes);
+  return lanczos_impl<double>(h, false, m, n, nullptr, m, (int)k, (int)s, (int)q, 0, nullptr, m,
+                              nullptr, nullptr, n, nullptr, bytes);
+}
+
+int rmm_rsvd_lanczos(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, const void* A, int64_t lda,
+                     int64_t k, int64_t s, int64_t q, uint64_t seed, void* U, int64_t ldu,
+                     void* sigma, void* V, int64_t ldv, int32_t* status) {
+  if (!h || !dt_ok(dt) || k < 1 || s < 1 || q < 1 || k > s * q || s * q > m || s * q > n)
+    return RMM_ERR_INVALID_ARG;
+  if (s * q > 1024 || m >= (1ll << 31) || n >= (1ll << 30)) return RMM_ERR_UNSUPPORTED;
+  if (!A || !U || !sigma || !V || ld_bad(lda, m) || ld_bad(ldu, m) || ld_bad(ldv, n))
+    return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return lanczos_impl<float>(h, true, m, n, (const float*)A, lda, (int)k, (int)s, (int)q, seed,
+                               (float*)U, ldu, (float*)sigma, (float*)V, ldv, status, nullptr);
+  return lanczos_impl<double>(h, true, m, n, (const double*)A, lda, (int)k, (int)s, (int)q, seed,
+                              (double*)U, ldu, (double*)sigma, (double*)V, ldv, status, nullptr);
 }
 
 int rmm_lsr_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m, int64_t d,

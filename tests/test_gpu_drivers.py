@@ -336,3 +336,41 @@ def test_rsvd_faster_invalid(h):
         h.rsvd_faster(A, 4, 8, 64, 16, 1, "countsketch")
     with pytest.raises(rmm.RmmError):
         h.rsvd_faster(A, 4, 1025, 2048, 1025, 1)      # s above the small-solve limit
+
+
+# ---- block Lanczos k-SVD (Alg. 5.1) -------------------------------------------------
+
+@pytest.mark.parametrize("dtype,m,n,k,s,q", [(torch.float64, 2048, 512, 20, 30, 3),
+                                             (torch.float32, 4001, 600, 10, 16, 3),
+                                             (torch.float64, 1000, 300, 8, 12, 2)])
+def test_rsvd_lanczos_parity(h, dtype, m, n, k, s, q):
+    A = _decaying(m, n, 7 * m + n, rate=0.9)
+    npdt = np.float32 if dtype == torch.float32 else np.float64
+    A = A.astype(npdt)
+    seed = 101 + q
+    U, sig, V, st = h.rsvd_lanczos(dev(A, dtype), k, s, q, seed)
+    Ur, sr, Vr, _ = orsvd.block_lanczos(A.astype(np.float64), k, s, q, seed,
+                                        fp64=(dtype == torch.float64))
+    tol = 1e-10 if dtype == torch.float64 else 2e-4
+    assert int(st.item()) == 0
+    U, sig, V = host(U), host(sig), host(V)
+    assert np.abs(sig - sr).max() <= tol * sr[0]
+    assert rel((U * sig) @ V.T, (Ur * sr) @ Vr.T) < tol
+
+
+def test_rsvd_lanczos_one_block_is_the_prototype(h):
+    A = dev(_decaying(800, 300, 44))
+    U, sig, V, _ = h.rsvd_lanczos(A, 6, 14, 1, 9)
+    Ur, sr, Vr, _ = h.rsvd(A, 6, 8, 0, 9)
+    assert rel(host(sig), host(sr)) < 1e-12
+    assert rel(host(U * sig) @ host(V).T, host(Ur * sr) @ host(Vr).T) < 1e-11
+
+
+def test_rsvd_lanczos_invalid(h):
+    A = torch.zeros(100, 50, dtype=torch.float64, device="cuda")
+    with pytest.raises(rmm.RmmError):
+        h.rsvd_lanczos(A, 10, 4, 2, 1)      # k > s q
+    with pytest.raises(rmm.RmmError):
+        h.rsvd_lanczos(A, 4, 20, 3, 1)      # s q > n
+    with pytest.raises(rmm.RmmError):
+        h.rsvd_lanczos(A, 4, 8, 0, 1)       # q < 1
