@@ -71,8 +71,8 @@ typedef enum {
 
 /* device-side status flags */
 #define RMM_STATUS_RANK_DEFICIENT 1  /* sketched LSR: min|R_jj| <= 10 s eps max|R_jj| */
-#define RMM_STATUS_QR_FALLBACK 2     /* Gram matrix numerically singular: eigen-based
-                                        orthonormalization dropped directions */
+#define RMM_STATUS_QR_FALLBACK 2     /* a CholeskyQR pass met a numerically singular
+                                        Gram matrix and dropped directions */
 #define RMM_STATUS_NOT_CONVERGED 4   /* Jacobi sweep limit reached */
 
 /* ---- handle ------------------------------------------------------------ */
@@ -203,6 +203,12 @@ int rmm_sched_stats(rmm_sched_t s, size_t* in_use, int64_t* queued, int64_t* run
  * largest-magnitude entry positive.  prec selects the operand precision of
  * the passes over A (RMM_PREC_NATIVE: dt itself; BF16/FP8 need dt = RMM_F32
  * and accumulate in FP32); orthonormalization and the small SVD are FP64.
+ * Orthonormalization is shifted CholeskyQR (a shifted first pass, then one
+ * more pass inside the subspace iteration and two for the final basis); the
+ * small SVD of B = Q^T A is taken from Z = A^T Q = B^T: Z = Q_z M_z (shifted
+ * CholeskyQR, M_z = Q_z^T Z), then one-sided Jacobi on the l x l M_z, so
+ * sigma carries an absolute error of order eps * sigma_1 (the condition
+ * number is not squared).  l <= 1024.
  * status: device int32, see RMM_STATUS_*. */
 int rmm_rsvd_workspace(rmm_handle h, rmm_dtype dt, rmm_precision prec,
                        int64_t m, int64_t n, int64_t k, int64_t p, size_t* bytes);
@@ -219,6 +225,8 @@ int rmm_rsvd(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m,
  *   Q_D R_D = D        CholeskyQR2 in FP64
  *   Ubar Sigmabar Vbar^T = rank-k SVD of Q_D^T L (s x n), FP64
  *   U Sigma Vhat^T = SVD of C R_D^{-1} Ubar Sigmabar (m x k), FP64;  V = Vbar Vhat
+ * (both SVDs as the small SVD of rmm_rsvd: shifted CholeskyQR of the tall
+ * factor, then one-sided Jacobi)
  * A is m x n (lda >= m); U m x k (ldu >= m), sigma k (descending), V n x k
  * (ldv >= n), in the input type, signs as rmm_rsvd.  Requires 1 <= k <= s <=
  * p <= p_cs, s <= 1024, p <= N = 2^ceil(log2 p_cs) for SRHT.  status as
@@ -227,7 +235,8 @@ int rmm_rsvd(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m,
  * K = [C, (A A^T) C, ..., (A A^T)^{q-1} C], C = A Omega (Omega n x s, the
  * stream of rmm_rsvd); each block after the first is (A A^T) of the previous
  * orthonormal block, orthogonalized against all earlier ones (two passes of
- * block Gram-Schmidt) and CholeskyQR2'd, so Q_C (m x sq) spans range(K).
+ * block Gram-Schmidt) and orthonormalized (shifted CholeskyQR, three
+ * passes), so Q_C (m x sq) spans range(K).
  * Then B = Q_C^T A, its top-k SVD, U = Q_C Ubar; outputs, signs and status
  * as rmm_rsvd.  Requires 1 <= k <= s q <= min(m, n), s q <= 1024. */
 int rmm_rsvd_lanczos_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, int64_t k,

@@ -36,20 +36,26 @@ int cholinv(rmm_ctx* h, int l, const double* G, int64_t ldg, double tau, double*
 size_t cholinv_workspace(const rmm_ctx* h, int l);
 
 // Symmetric eigendecomposition by cyclic Jacobi: evals descending, V (l x l,
-// ld l) orthonormal eigenvectors.  l <= 128.
+// ld l) orthonormal eigenvectors.  l <= 1024.
 int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals, double* V,
                int32_t* status, Carver& ws);
 size_t jacobi_workspace(int l);
 
+// SVD of an l x l FP64 matrix by one-sided Jacobi: M J = Ubar diag(sigma)
+// with sigma (l, descending, ties by index) the column norms of M J, Ubar
+// (l x l, ld l) their normalized columns (zero for sigma = 0) and J (l x l,
+// ld l) the accumulated rotations.  l <= 1024.  RMM_STATUS_NOT_CONVERGED is
+// raised when the sweep limit is reached.
+int jacobi_svd(const rmm_ctx* h, int l, const double* M, int64_t ldm, double* sigma, double* Ubar,
+               double* J, int32_t* status, Carver& ws);
+size_t jacobi_svd_workspace(int l);
+
+// G_jj += c * trace(G) (l x l, fp64): the shift of shifted CholeskyQR.
+int shift_diag(const rmm_ctx* h, int l, double* G, int64_t ldg, double c);
+
 // Flip (u_i, v_i) so that the largest-magnitude entry of u_i is positive.
 template <typename T>
 int sign_fix(const rmm_ctx* h, int64_t m, int64_t n, int k, T* U, int64_t ldu, T* V, int64_t ldv);
-
-// W (l x k) = Vr[:, :k] * diag(1 / sigma), sigma = sqrt(max(evals, 0)) (desc);
-// also writes sigma (k) in type T.
-template <typename T>
-int svd_from_eig(const rmm_ctx* h, int l, int k, const double* evals, const double* Vr,
-                 double* W, T* sigma);
 
 // status |= RANK_DEFICIENT if min|d1 d2| <= tol * max|d1 d2|
 int rank_check(const rmm_ctx* h, int d, const double* d1, const double* d2, double tol,

@@ -3,11 +3,14 @@
 // least-squares comparator (Sec. 4.1).
 //
 // Everything is enqueued on the handle's stream; no host synchronization.
-// Orthonormalization is CholeskyQR2 in fp64 (Gram matrix, Cholesky with
-// dropping of numerically dependent directions, triangular inverse, twice).
-// The small SVD of B = Q^T A is taken from the Jacobi eigendecomposition of
-// B B^T = Z^T Z with Z = A^T Q, so that B never has to be formed: sigma =
-// sqrt(lambda), Ubar = eigenvectors, V = Z Ubar diag(1/sigma).
+// Orthonormalization is shifted CholeskyQR in fp64: one pass on the Gram
+// matrix shifted by c tr(G) I, which cannot break down for any numerically
+// full-rank input, then plain CholeskyQR passes (two of them where the basis
+// is an output, one inside the subspace iteration where only its span is
+// used).  The small SVD of B = Q^T A is taken from Z = A^T Q = B^T without
+// squaring its condition: Z = Q_z M_z with Q_z from shifted CholeskyQR and
+// M_z = Q_z^T Z (l x l), then one-sided Jacobi on M_z, M_z J = Ubar Sigma, so
+// that B = J Sigma (Q_z Ubar)^T: U = Q J, V = Q_z Ubar.
 #include <math.h>
 
 #include "common.hpp"
@@ -28,14 +31,37 @@ constexpr double kEps = 2.220446049250313e-16;
 
 size_t smax(size_t a, size_t b) { return a > b ? a : b; }
 
-// ---- CholeskyQR2 ---------------------------------------------------------------
+// ---- shifted CholeskyQR ---------------------------------------------------------
+//
+// Shift of the first pass: c tr(G) with c = 11 (rows l + l (l + 1)) u,
+// u = 2^-53 (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa, "Shifted
+// Cholesky QR for computing the QR factorization of ill-conditioned
+// matrices", SIAM J. Sci. Comput. 2020, with ||X||_F^2 for ||X||_2^2).
+// Its Cholesky factor R1 exists whenever the condition number of X is below
+// about u^-1, and X R1^{-1} has a condition number of order u^{-1/2}, which
+// plain CholeskyQR then orthonormalizes.
 
 struct OrthBufs {
   double* G;
   double* Rinv;
   double* diag;
-  double* Xd;  // rows x l fp64
+  double* Xd;   // rows x l fp64
+  double* Xd2;  // rows x l fp64 (second intermediate of three passes)
 };
+
+OrthBufs take_orth(Carver& ws, int64_t rows, int l) {
+  OrthBufs b;
+  b.G = ws.take<double>((size_t)l * l);
+  b.Rinv = ws.take<double>((size_t)l * l);
+  b.diag = ws.take<double>((size_t)l);
+  b.Xd = ws.take<double>((size_t)rows * l);
+  b.Xd2 = ws.take<double>((size_t)rows * l);
+  return b;
+}
+
+double chol_shift(int64_t rows, int l) {
+  return 11.0 * ((double)rows * l + (double)l * (l + 1)) * 0x1p-53;
+}
 
 template <typename T>
 size_t orth_scratch(const rmm_ctx* h, int64_t rows, int l) {
@@ -45,23 +71,92 @@ size_t orth_scratch(const rmm_ctx* h, int64_t rows, int l) {
   return w;
 }
 
-// Q (rows x l, type T) = orthonormal basis of range(X) by CholeskyQR2.
-template <typename T>
-int orth(rmm_ctx* h, int64_t rows, int l, const T* X, int64_t ldx, T* Q, int64_t ldq,
-         const OrthBufs& b, double tau, int32_t* status, Carver& ws) {
+// Q (rows x l, type TQ) = orthonormal basis of range(X): the shifted pass,
+// then passes - 1 (>= 1) CholeskyQR passes.  Directions whose pivot falls
+// below tau G_jj in a pass are dropped (zero columns of Q) and
+// RMM_STATUS_QR_FALLBACK is raised.
+template <typename T, typename TQ>
+int orth(rmm_ctx* h, int64_t rows, int l, const T* X, int64_t ldx, TQ* Q, int64_t ldq,
+         const OrthBufs& b, double tau, int32_t* status, Carver& ws, int passes) {
   const int r = (int)rows;
   RMM_TRY((gemm<T, T, double, double>(h, true, false, l, l, rows, X, ldx, X, ldx, 1.0, b.G, l, ws)));
+  RMM_TRY(shift_diag(h, l, b.G, l, chol_shift(rows, l)));
   RMM_TRY(cholinv(h, l, b.G, l, tau, b.Rinv, b.diag, status, ws));
   RMM_TRY((gemm<T, double, double, double>(h, false, false, r, l, l, X, ldx, b.Rinv, l, 1.0, b.Xd,
                                            rows, ws)));
-  RMM_TRY((gemm<double, double, double, double>(h, true, false, l, l, rows, b.Xd, rows, b.Xd, rows,
-                                                1.0, b.G, l, ws)));
-  RMM_TRY(cholinv(h, l, b.G, l, tau, b.Rinv, b.diag, status, ws));
-  return gemm<double, double, double, T>(h, false, false, r, l, l, b.Xd, rows, b.Rinv, l, 1.0, Q,
-                                         ldq, ws);
+  double* cur = b.Xd;
+  double* nxt = b.Xd2;
+  for (int pass = 1;; ++pass) {
+    RMM_TRY((gemm<double, double, double, double>(h, true, false, l, l, rows, cur, rows, cur, rows,
+                                                  1.0, b.G, l, ws)));
+    RMM_TRY(cholinv(h, l, b.G, l, tau, b.Rinv, b.diag, status, ws));
+    if (pass + 1 >= passes)
+      return gemm<double, double, double, TQ>(h, false, false, r, l, l, cur, rows, b.Rinv, l, 1.0, Q,
+                                              ldq, ws);
+    RMM_TRY((gemm<double, double, double, double>(h, false, false, r, l, l, cur, rows, b.Rinv, l, 1.0,
+                                                  nxt, rows, ws)));
+    double* t = cur;
+    cur = nxt;
+    nxt = t;
+  }
+}
+
+// ---- small SVD of a tall matrix ----------------------------------------------------
+//
+// X (rows x l) = Qx Mx with Qx (rows x l, fp64) from shifted CholeskyQR with
+// three passes and Mx = Qx^T X (l x l); then one-sided Jacobi on Mx:
+// Mx J = Ubar diag(sigma), so X = (Qx Ubar) diag(sigma) J^T.
+struct SvdBufs {
+  OrthBufs ob;
+  double* Qx;     // rows x l
+  double* Mx;     // l x l
+  double* sigma;  // l
+  double* Ubar;   // l x l
+  double* J;      // l x l
+};
+
+SvdBufs take_svd(Carver& ws, int64_t rows, int l) {
+  SvdBufs b;
+  b.ob = take_orth(ws, rows, l);
+  b.Qx = ws.take<double>((size_t)rows * l);
+  b.Mx = ws.take<double>((size_t)l * l);
+  b.sigma = ws.take<double>((size_t)l);
+  b.Ubar = ws.take<double>((size_t)l * l);
+  b.J = ws.take<double>((size_t)l * l);
+  return b;
+}
+
+template <typename T>
+size_t svd_scratch(const rmm_ctx* h, int64_t rows, int l) {
+  size_t w = orth_scratch<T>(h, rows, l);
+  w = smax(w, gemm_workspace<double>(h, l, l, rows));
+  w = smax(w, jacobi_svd_workspace(l));
+  return w;
+}
+
+template <typename T>
+int tall_svd(rmm_ctx* h, int64_t rows, int l, const T* X, int64_t ldx, const SvdBufs& b,
+             int32_t* status, Carver& ws) {
+  const double tau = 64.0 * kEps * (double)(rows > l ? rows : l);
+  RMM_TRY((orth<T, double>(h, rows, l, X, ldx, b.Qx, rows, b.ob, tau, status, ws, 3)));
+  RMM_TRY((gemm<double, T, double, double>(h, true, false, l, l, rows, b.Qx, rows, X, ldx, 1.0, b.Mx,
+                                           l, ws)));
+  return jacobi_svd(h, l, b.Mx, l, b.sigma, b.Ubar, b.J, status, ws);
 }
 
 // ---- randomized SVD --------------------------------------------------------------
+
+// U = Q J[:, :k], V = Qz Ubar[:, :k], sigma = sigma_B[:k] from the small SVD
+// of Z = A^T Q (see the header comment); then the sign convention.
+template <typename T>
+int finish_rsvd(rmm_ctx* h, int64_t m, int64_t n, int l, int k, const T* Q, const SvdBufs& sb,
+                T* U, int64_t ldu, T* sigma, T* V, int64_t ldv, Carver& ws) {
+  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, k, l, Q, m, sb.J, l, 1.0, U, ldu, ws)));
+  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)n, k, l, sb.Qx, n, sb.Ubar, l, 1.0, V,
+                                           ldv, ws)));
+  RMM_TRY((copy_cast<double, T>(h, k, 1, sb.sigma, k, sigma, k)));
+  return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
+}
 
 template <typename T>
 int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t lda, int k, int p,
@@ -74,23 +169,16 @@ int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t ld
   T* Q = ws.take<T>((size_t)m * l);
   T* Z = ws.take<T>((size_t)n * l);
   T* Qz = ws.take<T>((size_t)n * l);
-  OrthBufs ob;
-  ob.G = ws.take<double>((size_t)l * l);
-  ob.Rinv = ws.take<double>((size_t)l * l);
-  ob.diag = ws.take<double>((size_t)l);
-  ob.Xd = ws.take<double>((size_t)(m > n ? m : n) * l);
-  double* evals = ws.take<double>((size_t)l);
-  double* Vr = ws.take<double>((size_t)l * l);
-  double* W = ws.take<double>((size_t)l * k);
+  OrthBufs ob = take_orth(ws, m > n ? m : n, l);
+  SvdBufs sb = take_svd(ws, n, l);
   // scratch shared by the steps below (released after each)
   size_t scratch = orth_scratch<T>(h, m, l);
   scratch = smax(scratch, orth_scratch<T>(h, n, l));
   scratch = smax(scratch, gemm_workspace<T>(h, (int)m, l, n));
   scratch = smax(scratch, gauss_sketch_workspace<T>(h, m, (int)n, l));
-  scratch = smax(scratch, gemm_workspace<double>(h, l, l, n));
+  scratch = smax(scratch, svd_scratch<T>(h, n, l));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, l));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, l));
-  scratch = smax(scratch, jacobi_workspace(l));
   if (!run) {
     *bytes = ws.off + scratch + 8 * kAlign;
     return RMM_OK;
@@ -100,32 +188,28 @@ int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t ld
   const double tau_n = 64.0 * kEps * (double)(n > l ? n : l);
   RMM_TRY(zero_status(h, status));
   RMM_TRY(launch_gaussian<T>(h, TAG_GAUSS_RSVD, n, l, seed, Om, n));
-  // range finder: Y = A Omega, Q = qr(Y); q times Z = A^T Q, Qz = qr(Z), Y = A Qz, Q = qr(Y)
+  // range finder: Y = A Omega; q times (Q = qr(Y), Z = A^T Q, Qz = qr(Z),
+  // Y = A Qz); Q = qr(Y)
   RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, l, n, A, lda, Om, n, 1.0, Y, m, ws)));
-  RMM_TRY(orth<T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
   for (int t = 0; t < q; ++t) {
+    RMM_TRY((orth<T, T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws, 2)));
     RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Q, m, l, Z, n, ws));
-    RMM_TRY(orth<T>(h, n, l, Z, n, Qz, n, ob, tau_n, status, ws));
+    RMM_TRY((orth<T, T>(h, n, l, Z, n, Qz, n, ob, tau_n, status, ws, 2)));
     RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, l, n, A, lda, Qz, n, 1.0, Y, m, ws)));
-    RMM_TRY(orth<T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
   }
-  // projection: Z = A^T Q = B^T, and the small SVD of B through B B^T = Z^T Z
+  RMM_TRY((orth<T, T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws, 3)));
+  // projection: Z = A^T Q = B^T, and the small SVD of B from that of Z
   RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Q, m, l, Z, n, ws));
-  RMM_TRY((gemm<T, T, double, double>(h, true, false, l, l, n, Z, n, Z, n, 1.0, ob.G, l, ws)));
-  RMM_TRY(jacobi_eig(h, l, ob.G, l, evals, Vr, status, ws));
-  RMM_TRY(svd_from_eig<T>(h, l, k, evals, Vr, W, sigma));
-  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, k, l, Q, m, Vr, l, 1.0, U, ldu, ws)));
-  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)n, k, l, Z, n, W, l, 1.0, V, ldv, ws)));
-  return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
+  RMM_TRY(tall_svd<T>(h, n, l, Z, n, sb, status, ws));
+  return finish_rsvd<T>(h, m, n, l, k, Q, sb, U, ldu, sigma, V, ldv, ws);
 }
 
 // ---- k-SVD by block Lanczos (Sec. 5.1, Alg. 5.1) ----------------------------------
 //
 // q Krylov blocks of width s: Q_0 = qr(A Omega); block i + 1 = A (A^T Q_i),
 // orthogonalized against every earlier block by two passes of block
-// Gram-Schmidt, then CholeskyQR2 (the blocks span range(K) of Alg. 5.1).  Then
-// Z = A^T Q_C (n x sq), the small SVD of B = Z^T through Z^T Z, U = Q_C Ubar,
-// V = Z W, as in the prototype.
+// Gram-Schmidt, then orthonormalized (the blocks span range(K) of Alg. 5.1).
+// Then Z = A^T Q_C (n x sq) and the small SVD of B = Z^T, as in the prototype.
 template <typename T>
 int lanczos_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t lda, int k, int s,
                  int q, uint64_t seed, T* U, int64_t ldu, T* sigma, T* V, int64_t ldv,
@@ -136,25 +220,18 @@ int lanczos_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t
   T* Qc = ws.take<T>((size_t)m * L);
   T* Y = ws.take<T>((size_t)m * s);
   T* Z = ws.take<T>((size_t)n * L);
-  OrthBufs ob;
-  ob.G = ws.take<double>((size_t)L * L);
-  ob.Rinv = ws.take<double>((size_t)s * s);
-  ob.diag = ws.take<double>((size_t)s);
-  ob.Xd = ws.take<double>((size_t)m * s);
+  OrthBufs ob = take_orth(ws, m, s);
   double* Wb = ws.take<double>((size_t)s * s);
-  double* evals = ws.take<double>((size_t)L);
-  double* Vr = ws.take<double>((size_t)L * L);
-  double* W = ws.take<double>((size_t)L * k);
+  SvdBufs sb = take_svd(ws, n, L);
   size_t scratch = orth_scratch<T>(h, m, s);
   scratch = smax(scratch, gemm_workspace<T>(h, (int)m, s, n));
   scratch = smax(scratch, gauss_sketch_workspace<T>(h, m, (int)n, s));
   scratch = smax(scratch, gauss_sketch_workspace<T>(h, m, (int)n, L));
   scratch = smax(scratch, gemm_workspace<double>(h, s, s, m));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)m, s, s));
-  scratch = smax(scratch, gemm_workspace<double>(h, L, L, n));
+  scratch = smax(scratch, svd_scratch<T>(h, n, L));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, L));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, L));
-  scratch = smax(scratch, jacobi_workspace(L));
   if (!run) {
     *bytes = ws.off + scratch + 8 * kAlign;
     return RMM_OK;
@@ -164,7 +241,7 @@ int lanczos_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t
   RMM_TRY(zero_status(h, status));
   RMM_TRY(launch_gaussian<T>(h, TAG_GAUSS_RSVD, n, s, seed, Om, n));
   RMM_TRY((gemm<T, T, T, T>(h, false, false, (int)m, s, n, A, lda, Om, n, 1.0, Y, m, ws)));
-  RMM_TRY(orth<T>(h, m, s, Y, m, Qc, m, ob, tau_m, status, ws));
+  RMM_TRY((orth<T, T>(h, m, s, Y, m, Qc, m, ob, tau_m, status, ws, 3)));
   for (int i = 1; i < q; ++i) {
     const T* Qp = Qc + (int64_t)(i - 1) * s * m;
     RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Qp, m, s, Z, n, ws));  // Z = A^T Q_{i-1}
@@ -176,23 +253,20 @@ int lanczos_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t
         RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, s, s, Qb, m, Wb, s, -1.0, Y, m,
                                             ws, 1.0)));
       }
-    RMM_TRY(orth<T>(h, m, s, Y, m, Qc + (int64_t)i * s * m, m, ob, tau_m, status, ws));
+    RMM_TRY((orth<T, T>(h, m, s, Y, m, Qc + (int64_t)i * s * m, m, ob, tau_m, status, ws, 3)));
   }
-  // Z = A^T Q_C = B^T and the small SVD of B through B B^T = Z^T Z
+  // Z = A^T Q_C = B^T and the small SVD of B from that of Z
   RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Qc, m, L, Z, n, ws));
-  RMM_TRY((gemm<T, T, double, double>(h, true, false, L, L, n, Z, n, Z, n, 1.0, ob.G, L, ws)));
-  RMM_TRY(jacobi_eig(h, L, ob.G, L, evals, Vr, status, ws));
-  RMM_TRY(svd_from_eig<T>(h, L, k, evals, Vr, W, sigma));
-  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, k, L, Qc, m, Vr, L, 1.0, U, ldu, ws)));
-  RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)n, k, L, Z, n, W, L, 1.0, V, ldv, ws)));
-  return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
+  RMM_TRY(tall_svd<T>(h, n, L, Z, n, sb, status, ws));
+  return finish_rsvd<T>(h, m, n, L, k, Qc, sb, U, ldu, sigma, V, ldv, ws);
 }
 
 // ---- randomized SVD with BF16 / FP8 passes over A ----------------------------------------
 //
 // Same steps as rsvd_impl; every product with A runs on a one-time quantized
 // copy of A (mixed.hip), the small operands are quantized per column before
-// each pass, and the results come back in fp32 for the fp64 CholeskyQR2.
+// each pass, and the results come back in fp32 for the fp64 orthonormalization
+// and small SVD.
 int rsvd_mixed(rmm_ctx* h, bool run, rmm_precision prec, int64_t m, int64_t n, const float* A,
                int64_t lda, int k, int p, int q, uint64_t seed, float* U, int64_t ldu, float* sigma,
                float* V, int64_t ldv, int32_t* status, size_t* bytes) {
@@ -212,22 +286,15 @@ int rsvd_mixed(rmm_ctx* h, bool run, rmm_precision prec, int64_t m, int64_t n, c
   float* Q = ws.take<float>((size_t)m * l);
   float* Z = ws.take<float>((size_t)n * l);
   float* Qz = ws.take<float>((size_t)n * l);
-  OrthBufs ob;
-  ob.G = ws.take<double>((size_t)l * l);
-  ob.Rinv = ws.take<double>((size_t)l * l);
-  ob.diag = ws.take<double>((size_t)l);
-  ob.Xd = ws.take<double>((size_t)(m > n ? m : n) * l);
-  double* evals = ws.take<double>((size_t)l);
-  double* Vr = ws.take<double>((size_t)l * l);
-  double* W = ws.take<double>((size_t)l * k);
+  OrthBufs ob = take_orth(ws, m > n ? m : n, l);
+  SvdBufs sb = take_svd(ws, n, l);
   size_t scratch = orth_scratch<float>(h, m, l);
   scratch = smax(scratch, orth_scratch<float>(h, n, l));
   scratch = smax(scratch, qgemm_workspace(h, (int)m, l, pn));
   scratch = smax(scratch, qgemm_workspace(h, (int)n, l, pm));
-  scratch = smax(scratch, gemm_workspace<double>(h, l, l, n));
+  scratch = smax(scratch, svd_scratch<float>(h, n, l));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, l));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, l));
-  scratch = smax(scratch, jacobi_workspace(l));
   if (!run) {
     *bytes = ws.off + scratch + 8 * kAlign;
     return RMM_OK;
@@ -241,23 +308,19 @@ int rsvd_mixed(rmm_ctx* h, bool run, rmm_precision prec, int64_t m, int64_t n, c
   // Y = A Omega = Aq_t^T q(diag(sc) Omega)
   RMM_TRY(mp_quantize_cols(h, prec, n, l, Om, n, sc, Xq, ux));
   RMM_TRY(mp_gemm_tn(h, prec, (int)m, l, pn, Aqt, Xq, nullptr, ux, Y, m, ws));
-  RMM_TRY(orth<float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
   for (int t = 0; t < q; ++t) {
+    RMM_TRY((orth<float, float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws, 2)));
     RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq));
     RMM_TRY(mp_gemm_tn(h, prec, (int)n, l, pm, Aq, Qq, sc, uq, Z, n, ws));
-    RMM_TRY(orth<float>(h, n, l, Z, n, Qz, n, ob, tau_n, status, ws));
+    RMM_TRY((orth<float, float>(h, n, l, Z, n, Qz, n, ob, tau_n, status, ws, 2)));
     RMM_TRY(mp_quantize_cols(h, prec, n, l, Qz, n, sc, Xq, ux));
     RMM_TRY(mp_gemm_tn(h, prec, (int)m, l, pn, Aqt, Xq, nullptr, ux, Y, m, ws));
-    RMM_TRY(orth<float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws));
   }
+  RMM_TRY((orth<float, float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws, 3)));
   RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq));
   RMM_TRY(mp_gemm_tn(h, prec, (int)n, l, pm, Aq, Qq, sc, uq, Z, n, ws));
-  RMM_TRY((gemm<float, float, double, double>(h, true, false, l, l, n, Z, n, Z, n, 1.0, ob.G, l, ws)));
-  RMM_TRY(jacobi_eig(h, l, ob.G, l, evals, Vr, status, ws));
-  RMM_TRY(svd_from_eig<float>(h, l, k, evals, Vr, W, sigma));
-  RMM_TRY((gemm<float, double, double, float>(h, false, false, (int)m, k, l, Q, m, Vr, l, 1.0, U, ldu, ws)));
-  RMM_TRY((gemm<float, double, double, float>(h, false, false, (int)n, k, l, Z, n, W, l, 1.0, V, ldv, ws)));
-  return sign_fix<float>(h, m, n, k, U, ldu, V, ldv);
+  RMM_TRY(tall_svd<float>(h, n, l, Z, n, sb, status, ws));
+  return finish_rsvd<float>(h, m, n, l, k, Q, sb, U, ldu, sigma, V, ldv, ws);
 }
 
 // ---- sketch-and-solve least squares ---------------------------------------------------
@@ -472,9 +535,9 @@ __global__ void scale_cols_kernel(int rows, int k, const double* __restrict__ X,
 // Steps of Alg. 5.3: C = A S (column count sketch, stream seed + 1);
 // L = P^T A, D = P^T C with P = P_cs P_2 (composite, stream seed); Q_D R_D =
 // D by CholeskyQR2 (R_D^{-1} = R1 R2); Ubar Sigmabar Vbar^T = rank-k SVD of
-// Z = Q_D^T L through Z Z^T; M = C R_D^{-1} Ubar Sigmabar; U Sigma Vhat^T =
-// SVD of M through M^T M; V = Vbar Vhat.  C, L, D in the input type, the
-// small algebra in FP64.
+// Z = Q_D^T L, taken from the small SVD of the tall Z^T = L^T Q_D; M = C
+// R_D^{-1} Ubar Sigmabar and its SVD U Sigma Vhat^T by the same route; V =
+// Vbar Vhat.  C, L, D in the input type, the small algebra in FP64.
 template <typename T>
 int rsvd_faster_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind2, int64_t m, int64_t n, const T* A,
                      int64_t lda, int k, int s, int64_t pcs, int p, uint64_t seed, T* U, int64_t ldu,
@@ -488,35 +551,27 @@ int rsvd_faster_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind2, int64_t m, int
   double* Dd = ws.take<double>((size_t)p * s);
   LsBufs lb = take_ls(ws, p, s);
   double* Ri = ws.take<double>((size_t)s * s);
-  double* Z = ws.take<double>((size_t)s * n);
-  double* evals = ws.take<double>((size_t)s);
-  double* Vr = ws.take<double>((size_t)s * s);
-  double* W = ws.take<double>((size_t)s * k);
-  double* sb = ws.take<double>((size_t)k);
+  double* Zt = ws.take<double>((size_t)n * s);
+  SvdBufs sz = take_svd(ws, n, s);
   double* T1 = ws.take<double>((size_t)s * k);
   double* T2 = ws.take<double>((size_t)s * k);
   double* Vb = ws.take<double>((size_t)n * k);
   double* M = ws.take<double>((size_t)m * k);
-  double* G3 = ws.take<double>((size_t)k * k);
-  double* ev3 = ws.take<double>((size_t)k);
-  double* V3 = ws.take<double>((size_t)k * k);
-  double* W3 = ws.take<double>((size_t)k * k);
+  SvdBufs sm = take_svd(ws, m, k);
   size_t scratch = countsketch_cols_workspace(n);
   scratch = smax(scratch, countsketch_workspace<T>(h, m, (int)n, pcs));
   scratch = smax(scratch, countsketch_workspace<T>(h, m, s, pcs));
   scratch = smax(scratch, sketch_scratch<T>(h, kind2, pcs, (int)n, p));
   scratch = smax(scratch, sketch_scratch<T>(h, kind2, pcs, s, p));
   scratch = smax(scratch, ls_scratch(h, p, s));
-  scratch = smax(scratch, gemm_workspace<double>(h, s, (int)n, p));
-  scratch = smax(scratch, gemm_workspace<double>(h, s, s, n));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)n, s, p));
+  scratch = smax(scratch, svd_scratch<double>(h, n, s));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, s));
   scratch = smax(scratch, gemm_workspace<double>(h, s, k, s));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, s));
-  scratch = smax(scratch, gemm_workspace<double>(h, k, k, m));
+  scratch = smax(scratch, svd_scratch<double>(h, m, k));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)m, k, k));
   scratch = smax(scratch, gemm_workspace<double>(h, (int)n, k, k));
-  scratch = smax(scratch, jacobi_workspace(s));
-  scratch = smax(scratch, jacobi_workspace(k));
   if (!run) {
     *bytes = ws.off + scratch + 8 * kAlign;
     return RMM_OK;
@@ -541,26 +596,25 @@ int rsvd_faster_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind2, int64_t m, int
   RMM_TRY(rank_check(h, s, lb.d1, lb.d2, 10.0 * (double)p * kEps, status));
   RMM_TRY((gemm<double, double, double, double>(h, false, false, s, s, s, lb.R1, s, lb.R2, s, 1.0, Ri,
                                                 s, ws)));
-  // step 4: rank-k SVD of Z = Q_D^T L through Z Z^T
-  RMM_TRY((gemm<double, T, double, double>(h, true, false, s, (int)n, p, lb.Q, p, L, p, 1.0, Z, s, ws)));
-  RMM_TRY((gemm<double, double, double, double>(h, false, true, s, s, (int)n, Z, s, Z, s, 1.0, lb.G, s,
-                                                ws)));
-  RMM_TRY(jacobi_eig(h, s, lb.G, s, evals, Vr, status, ws));
-  RMM_TRY(svd_from_eig<double>(h, s, k, evals, Vr, W, sb));
-  RMM_TRY((gemm<double, double, double, double>(h, true, false, (int)n, k, s, Z, s, W, s, 1.0, Vb, n,
-                                                ws)));
-  // step 5: M = C R_D^{-1} Ubar Sigmabar and its SVD through M^T M
-  hipLaunchKernelGGL(scale_cols_kernel, dim3((s * k + 255) / 256), dim3(256), 0, h->stream, s, k, Vr,
-                     (int64_t)s, sb, T1);
+  // step 4: Z^T = L^T Q_D = (Qx Ubar_z) Sigma_z J_z^T, so that Z = J_z Sigma_z
+  // (Qx Ubar_z)^T: Ubar = J_z[:, :k], Sigmabar = Sigma_z[:k], Vbar = Qx Ubar_z[:, :k]
+  RMM_TRY((gemm<T, double, double, double>(h, true, false, (int)n, s, p, L, p, lb.Q, p, 1.0, Zt, n,
+                                           ws)));
+  RMM_TRY(tall_svd<double>(h, n, s, Zt, n, sz, status, ws));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, (int)n, k, s, sz.Qx, n, sz.Ubar, s,
+                                                1.0, Vb, n, ws)));
+  // step 5: M = C R_D^{-1} Ubar Sigmabar = (Qm Ubar_m) Sigma J_m^T
+  hipLaunchKernelGGL(scale_cols_kernel, dim3((s * k + 255) / 256), dim3(256), 0, h->stream, s, k, sz.J,
+                     (int64_t)s, sz.sigma, T1);
   RMM_TRY(launch_status());
   RMM_TRY((gemm<double, double, double, double>(h, false, false, s, k, s, Ri, s, T1, s, 1.0, T2, s, ws)));
   RMM_TRY((gemm<T, double, double, double>(h, false, false, (int)m, k, s, C, m, T2, s, 1.0, M, m, ws)));
-  RMM_TRY((gemm<double, double, double, double>(h, true, false, k, k, m, M, m, M, m, 1.0, G3, k, ws)));
-  RMM_TRY(jacobi_eig(h, k, G3, k, ev3, V3, status, ws));
-  RMM_TRY(svd_from_eig<T>(h, k, k, ev3, V3, W3, sigma));
-  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)m, k, k, M, m, W3, k, 1.0, U, ldu, ws)));
-  // step 6: V = Vbar Vhat
-  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)n, k, k, Vb, n, V3, k, 1.0, V, ldv,
+  RMM_TRY(tall_svd<double>(h, m, k, M, m, sm, status, ws));
+  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)m, k, k, sm.Qx, m, sm.Ubar, k, 1.0, U,
+                                           ldu, ws)));
+  RMM_TRY((copy_cast<double, T>(h, k, 1, sm.sigma, k, sigma, k)));
+  // step 6: V = Vbar Vhat, Vhat = J_m
+  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)n, k, k, Vb, n, sm.J, k, 1.0, V, ldv,
                                            ws)));
   return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
 }

@@ -1,6 +1,7 @@
 // Small FP64 factorizations that run in a single workgroup: the Cholesky
-// step of CholeskyQR2 with the triangular inverse, and the cyclic Jacobi
-// eigensolver used for the small SVD of the projected matrix.  These sit on
+// step of CholeskyQR with the triangular inverse, the cyclic Jacobi
+// eigensolver (Nystrom's W) and the one-sided Jacobi SVD used for the small
+// SVD of the projected matrix.  These sit on
 // the latency path of every driver call; a Cholesky leaf is at most
 // 128 x 128 and lives in registers (larger factors are split recursively).
 #include "common.hpp"
@@ -918,6 +919,427 @@ int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* ev
   return launch_status();
 }
 
+// ---- one-sided (Hestenes) Jacobi SVD ------------------------------------------------------
+//
+// The small SVD of the drivers: for an l x l FP64 matrix M, plane rotations
+// J_1 J_2 ... applied to pairs of columns make the columns of M J mutually
+// orthogonal; then M J = Ubar diag(sigma) with sigma_j the column norms.
+// Every rotation is computed from the current columns themselves (their
+// squared norms a, b and inner product c), so the singular values come out
+// with an absolute error of order eps * ||M||, not eps * ||M||^2 / sigma as
+// from an eigendecomposition of M^T M.  A pair is rotated when
+//   c^2 > l * eps^2 * a * b,
+// with the angle that makes the pair orthogonal,
+//   zeta = (b - a) / (2 c),  t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+//   cs = 1 / sqrt(1 + t^2),  sn = t cs,
+//   col_p <- cs col_p - sn col_q,  col_q <- sn col_p + cs col_q.
+// The pairs of a round follow the same circle method as the eigensolver, and
+// the (cs, sn) of every pair of every round go to the same log, so J is
+// accumulated by jacobi_vectors_kernel.  A sweep without a rotation ends the
+// iteration (the columns are orthogonal to the test's precision).
+//
+// osj_kernel (l <= 128, one workgroup): M sits in LDS column-major; a group
+// of g lanes (a power of two, 16 at l = 128) owns one pair per round, holds
+// R <= 8 rows of each of its two columns in registers and forms a, b, c with
+// a butterfly reduction over the group.  Each butterfly step adds two lanes'
+// values in both lanes, so every lane of a group ends with bitwise the same
+// sums and takes the same decision.  One barrier per round: within a round
+// the pairs are disjoint.
+constexpr int kOsjMaxRows = 8;
+
+// DPP lane permutations inside a row of 16 lanes
+constexpr int kDppQuad1032 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuad2301 = 0x4E;  // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over aligned groups of 2^gl2 lanes; the partner of every step is an
+// involution, so both lanes of a step add the same two values.
+__device__ __forceinline__ double group_sum(double v, int gl2) {
+  v += dpp_f64<kDppQuad1032>(v);
+  v += dpp_f64<kDppQuad2301>(v);
+  if (gl2 >= 3) v += dpp_f64<kDppRowHalfMirror>(v);
+  if (gl2 >= 4) v += dpp_f64<kDppRowMirror>(v);
+  if (gl2 >= 5) v += __shfl_xor(v, 16);
+  if (gl2 >= 6) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// rotation of the pair with squared norms a, b and inner product c; false
+// when the pair already passes the orthogonality test
+__device__ __forceinline__ bool osj_rotation(double a, double b, double c, double tol2, double& cs,
+                                             double& sn) {
+  cs = 1.0;
+  sn = 0.0;
+  if (!(fabs(c) > 1e-300) || !(c * c > tol2 * a * b)) return false;
+  const double zeta = (b - a) * recip_f64(2.0 * c);
+  const double az = fabs(zeta);
+  const double w = az * az + 1.0;
+  const double den = az > 0x1p26 ? 2.0 * az : az + w * rsqrt_f64(w);
+  const double t = (zeta >= 0 ? 1.0 : -1.0) * recip_f64(den);
+  cs = rsqrt_f64(t * t + 1.0);
+  sn = t * cs;
+  return true;
+}
+
+__global__ __launch_bounds__(kSmallThreads) void osj_kernel(int l, const double* __restrict__ M,
+                                                            int64_t ldm, int gl2,
+                                                            double* __restrict__ sigma,
+                                                            int* __restrict__ perm,
+                                                            double* __restrict__ Ubar,
+                                                            double2* __restrict__ rlog,
+                                                            int* __restrict__ nrounds,
+                                                            int32_t* status, int max_sweeps) {
+  extern __shared__ double S[];  // L columns of L rows
+  __shared__ double nrm[kLdsMaxL];
+  __shared__ int sperm[kLdsMaxL];
+  __shared__ int rotated[2];
+  const int L = (l + 1) & ~1;
+  const int npairs = L / 2;
+  const int g = 1 << gl2;
+  const int tid = threadIdx.x, pair = tid >> gl2, t = tid & (g - 1);
+  for (int e = tid; e < L * L; e += blockDim.x) {
+    const int a = e % L, b = e / L;
+    S[e] = (a < l && b < l) ? M[a + (int64_t)b * ldm] : 0.0;
+  }
+  if (tid < 2) rotated[tid] = 0;
+  __syncthreads();
+  const double tol2 = (double)l * 0x1p-104;
+  int rounds = 0, sweep = 0;
+  bool conv = false;
+  for (; sweep < max_sweeps; ++sweep) {
+    const int fl = sweep & 1;
+    for (int r = 0; r < L - 1; ++r, ++rounds) {
+      int p, q;
+      rr_pair(pair, r, L, p, q);
+      double x[kOsjMaxRows], y[kOsjMaxRows];
+      double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+      for (int k = 0; k < kOsjMaxRows; ++k) {
+        const int i = t + (k << gl2);
+        const bool in = i < L;
+        x[k] = in ? S[i + p * L] : 0.0;
+        y[k] = in ? S[i + q * L] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kOsjMaxRows; ++k) {
+        a = fma(x[k], x[k], a);
+        b = fma(y[k], y[k], b);
+        c = fma(x[k], y[k], c);
+      }
+      a = group_sum(a, gl2);
+      b = group_sum(b, gl2);
+      c = group_sum(c, gl2);
+      double cs, sn;
+      const bool rot = osj_rotation(a, b, c, tol2, cs, sn);
+      if (rot) {
+#pragma unroll
+        for (int k = 0; k < kOsjMaxRows; ++k) {
+          const int i = t + (k << gl2);
+          if (i < L) {
+            S[i + p * L] = cs * x[k] - sn * y[k];
+            S[i + q * L] = sn * x[k] + cs * y[k];
+          }
+        }
+        if (t == 0) rotated[fl] = 1;
+      }
+      if (t == 0) rlog[(size_t)rounds * npairs + pair] = make_double2(cs, sn);
+      lds_barrier();
+    }
+    conv = rotated[fl] == 0;
+    lds_barrier();
+    if (tid == 0) rotated[fl] = 0;  // next read in sweep + 2, after more barriers
+    if (conv) break;
+  }
+  if (tid == 0) {
+    // the sweep that found no rotation logged identities only
+    *nrounds = conv ? rounds - (L - 1) : rounds;
+    if (!conv) or_status(status, RMM_STATUS_NOT_CONVERGED);
+  }
+  {
+    // column norms of the final M J (pairs of round 0 cover every column)
+    int p, q;
+    rr_pair(pair, 0, L, p, q);
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int k = 0; k < kOsjMaxRows; ++k) {
+      const int i = t + (k << gl2);
+      const double xv = i < L ? S[i + p * L] : 0.0;
+      const double yv = i < L ? S[i + q * L] : 0.0;
+      a = fma(xv, xv, a);
+      b = fma(yv, yv, b);
+    }
+    a = group_sum(a, gl2);
+    b = group_sum(b, gl2);
+    if (t == 0) {
+      nrm[p] = sqrt(a);
+      nrm[q] = sqrt(b);
+    }
+  }
+  __syncthreads();
+  // descending, ties by index
+  if (tid < l) {
+    const double v = nrm[tid];
+    int rank = 0;
+    for (int i = 0; i < l; ++i) {
+      const double u = nrm[i];
+      rank += (u > v) || (u == v && i < tid);
+    }
+    sigma[rank] = v;
+    perm[rank] = tid;
+    sperm[rank] = tid;
+  }
+  __syncthreads();
+  for (int e = tid; e < l * l; e += blockDim.x) {
+    const int a = e % l, rank = e / l;
+    const int j = sperm[rank];
+    const double nj = nrm[j];
+    Ubar[a + (int64_t)rank * l] = nj > 0.0 ? S[a + j * L] / nj : 0.0;
+  }
+}
+
+// ---- one-sided Jacobi for 128 < l <= 1024: one launch per round ------------------------
+//
+// Same rotations, test, ordering and stopping rule; M (L x L, column-major)
+// lives in the workspace and is rotated in place (a round's pairs are
+// disjoint).  One wave per pair, lane i holding rows i, i + 64, ...; the
+// sweep's log is applied to the rows of J by big_vectors_kernel.
+constexpr int kOsjBigRows = kBigMaxL / 64;
+
+__global__ void osj_big_init_kernel(int l, int L, const double* __restrict__ M, int64_t ldm,
+                                    double* __restrict__ Mg, double* __restrict__ Vr,
+                                    uint16_t* __restrict__ ptab, uint16_t* __restrict__ qtab,
+                                    BigState* st) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int npairs = L / 2;
+  if (e < (int64_t)L * L) {
+    const int a = (int)(e % L), b = (int)(e / L);
+    Mg[e] = (a < l && b < l) ? M[a + (int64_t)b * ldm] : 0.0;
+    Vr[e] = (a == b) ? 1.0 : 0.0;  // row-major identity
+  }
+  if (e < (int64_t)(L - 1) * npairs) {
+    int p, q;
+    rr_pair((int)(e % npairs), (int)(e / npairs), L, p, q);
+    ptab[e] = (uint16_t)p;
+    qtab[e] = (uint16_t)q;
+  }
+  if (e == 0) *st = BigState{0.0, 0, 0, 0, 0};
+}
+
+__global__ __launch_bounds__(256) void osj_big_round_kernel(int l, int L, int r, double* __restrict__ Mg,
+                                                            const uint16_t* __restrict__ ptab,
+                                                            const uint16_t* __restrict__ qtab,
+                                                            double2* __restrict__ rlog, BigState* st) {
+  if (st->converged) return;
+  const int npairs = L / 2;
+  const int pair = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (pair >= npairs) return;
+  const int p = ptab[(size_t)r * npairs + pair], q = qtab[(size_t)r * npairs + pair];
+  double* cp = Mg + (int64_t)p * L;
+  double* cq = Mg + (int64_t)q * L;
+  double x[kOsjBigRows], y[kOsjBigRows];
+  double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+  for (int k = 0; k < kOsjBigRows; ++k) {
+    const int i = lane + 64 * k;
+    x[k] = i < L ? cp[i] : 0.0;
+    y[k] = i < L ? cq[i] : 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < kOsjBigRows; ++k) {
+    a = fma(x[k], x[k], a);
+    b = fma(y[k], y[k], b);
+    c = fma(x[k], y[k], c);
+  }
+  a = group_sum(a, 6);
+  b = group_sum(b, 6);
+  c = group_sum(c, 6);
+  double cs, sn;
+  if (osj_rotation(a, b, c, (double)l * 0x1p-104, cs, sn)) {
+#pragma unroll
+    for (int k = 0; k < kOsjBigRows; ++k) {
+      const int i = lane + 64 * k;
+      if (i < L) {
+        cp[i] = cs * x[k] - sn * y[k];
+        cq[i] = sn * x[k] + cs * y[k];
+      }
+    }
+    if (lane == 0) atomicOr(&st->pending, 1);
+  }
+  if (lane == 0) rlog[(size_t)r * npairs + pair] = make_double2(cs, sn);
+}
+
+// converged when the sweep just run rotated nothing; the sweep's log (all
+// identities then) is applied only otherwise
+__global__ void osj_big_decide_kernel(BigState* st) {
+  if (st->converged) return;
+  if (st->pending == 0) st->converged = 1;
+  else st->sweeps += 1;
+  st->pending = 0;
+}
+
+// column norms of the rotated M, one wave per column
+__global__ __launch_bounds__(256) void osj_big_norms_kernel(int L, const double* __restrict__ Mg,
+                                                            double* __restrict__ nrm) {
+  const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (j >= L) return;
+  double a = 0.0;
+  for (int i = lane; i < L; i += 64) {
+    const double v = Mg[i + (int64_t)j * L];
+    a = fma(v, v, a);
+  }
+  a = group_sum(a, 6);
+  if (lane == 0) nrm[j] = sqrt(a);
+}
+
+// sigma descending (ties by index), Ubar[:, rank] = M[:, j] / sigma, and
+// Jout[:, rank] = J[:, j] (J row-major: J[k][j] = Vr[k * L + j])
+__global__ void osj_big_finish_kernel(int l, int L, const double* __restrict__ Mg,
+                                      const double* __restrict__ nrm, const double* __restrict__ Vr,
+                                      double* __restrict__ sigma, double* __restrict__ Ubar,
+                                      double* __restrict__ Jout, const BigState* st,
+                                      int32_t* status) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j == 0 && !st->converged) or_status(status, RMM_STATUS_NOT_CONVERGED);
+  if (j >= l) return;
+  const double v = nrm[j];
+  int rank = 0;
+  for (int i = 0; i < l; ++i) {
+    const double u = nrm[i];
+    rank += (u > v) || (u == v && i < j);
+  }
+  sigma[rank] = v;
+  const double inv = v > 0.0 ? 1.0 / v : 0.0;
+  for (int k = 0; k < l; ++k) {
+    Ubar[k + (int64_t)rank * l] = Mg[k + (int64_t)j * L] * inv;
+    Jout[k + (int64_t)rank * l] = Vr[(int64_t)k * L + j];
+  }
+}
+
+size_t jacobi_svd_workspace(int l) {
+  const int L = (l + 1) & ~1;
+  Carver c(nullptr, 0);
+  if (l <= kLdsMaxL) {
+    c.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * (L / 2));
+    c.take<int>((size_t)l);
+    c.take<int>(1);
+    return c.off + 3 * kAlign;
+  }
+  c.take<double>((size_t)L * L);  // M
+  c.take<double>((size_t)L * L);  // J
+  c.take<double>((size_t)L);      // norms
+  c.take<double2>((size_t)(L - 1) * (L / 2));
+  c.take<uint16_t>((size_t)(L - 1) * (L / 2));
+  c.take<uint16_t>((size_t)(L - 1) * (L / 2));
+  c.take<BigState>(1);
+  return c.off + 8 * kAlign;
+}
+
+static int jacobi_svd_big(const rmm_ctx* h, int l, const double* M, int64_t ldm, double* sigma,
+                          double* Ubar, double* J, int32_t* status, Carver& ws) {
+  const int L = (l + 1) & ~1;
+  const int npairs = L / 2;
+  const size_t mark = ws.off;
+  double* Mg = ws.take<double>((size_t)L * L);
+  double* Vr = ws.take<double>((size_t)L * L);
+  double* nrm = ws.take<double>((size_t)L);
+  double2* rlog = ws.take<double2>((size_t)(L - 1) * npairs);
+  uint16_t* ptab = ws.take<uint16_t>((size_t)(L - 1) * npairs);
+  uint16_t* qtab = ws.take<uint16_t>((size_t)(L - 1) * npairs);
+  BigState* st = ws.take<BigState>(1);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const int64_t init_n = (int64_t)L * L;
+  hipLaunchKernelGGL(osj_big_init_kernel, dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0,
+                     h->stream, l, L, M, ldm, Mg, Vr, ptab, qtab, st);
+  RMM_TRY(launch_status());
+  const size_t vlds = (size_t)4 * kBigVecRows * L * sizeof(double);
+  RMM_HIP(hipFuncSetAttribute((const void*)big_vectors_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
+  const unsigned vgroups = (unsigned)((L + 4 * kBigVecRows - 1) / (4 * kBigVecRows));
+  const unsigned rgroups = (unsigned)((npairs + 3) / 4);
+  for (int sweep = 0; sweep < kBigMaxSweeps; ++sweep) {
+    for (int r = 0; r < L - 1; ++r)
+      hipLaunchKernelGGL(osj_big_round_kernel, dim3(rgroups), dim3(256), 0, h->stream, l, L, r, Mg,
+                         ptab, qtab, rlog, st);
+    RMM_TRY(launch_status());
+    hipLaunchKernelGGL(osj_big_decide_kernel, dim3(1), dim3(1), 0, h->stream, st);
+    hipLaunchKernelGGL(big_vectors_kernel, dim3(vgroups), dim3(256), vlds, h->stream, L, rlog, ptab,
+                       qtab, Vr, st);
+    RMM_TRY(launch_status());
+  }
+  hipLaunchKernelGGL(osj_big_norms_kernel, dim3((unsigned)((L + 3) / 4)), dim3(256), 0, h->stream, L,
+                     Mg, nrm);
+  hipLaunchKernelGGL(osj_big_finish_kernel, dim3((unsigned)((l + 255) / 256)), dim3(256), 0,
+                     h->stream, l, L, Mg, nrm, Vr, sigma, Ubar, J, st, status);
+  ws.off = mark;
+  return launch_status();
+}
+
+int jacobi_svd(const rmm_ctx* h, int l, const double* M, int64_t ldm, double* sigma, double* Ubar,
+               double* J, int32_t* status, Carver& ws) {
+  if (l == 0) return RMM_OK;
+  if (l > kBigMaxL) return RMM_ERR_UNSUPPORTED;
+  if (l > kLdsMaxL) return jacobi_svd_big(h, l, M, ldm, sigma, Ubar, J, status, ws);
+  const int L = (l + 1) & ~1;
+  const int npairs = L / 2;
+  const size_t mark = ws.off;
+  double2* rlog = ws.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * npairs);
+  int* perm = ws.take<int>((size_t)l);
+  int* nr = ws.take<int>(1);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const size_t lds = (size_t)L * L * sizeof(double);
+  RMM_HIP(hipFuncSetAttribute((const void*)osj_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds));
+  // lanes per pair: the largest power of two with npairs * g <= 1024, at
+  // most 64 and at least 4 (the quad step of the butterfly)
+  int gl2 = 6;
+  while (gl2 > 2 && (npairs << gl2) > kSmallThreads) --gl2;
+  hipLaunchKernelGGL(osj_kernel, dim3(1), dim3(npairs << gl2), lds, h->stream, l, M, ldm, gl2, sigma,
+                     perm, Ubar, rlog, nr, status, kJacobiMaxSweeps);
+  RMM_TRY(launch_status());
+  const size_t vlds = (size_t)4 * kVecRows * L * sizeof(double) + 2 * (size_t)(L - 1) * npairs;
+  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
+  const int groups = (l + 4 * kVecRows - 1) / (4 * kVecRows);
+  hipLaunchKernelGGL(jacobi_vectors_kernel, dim3(groups), dim3(256), vlds, h->stream, l, rlog, nr,
+                     perm, J);
+  ws.off = mark;
+  return launch_status();
+}
+
+// G_jj += c * trace(G) for the l x l matrix G (one workgroup): the shift of
+// the first pass of shifted CholeskyQR
+__global__ __launch_bounds__(256) void shift_diag_kernel(int l, double* __restrict__ G, int64_t ldg,
+                                                         double c) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < l; j += 256) s += G[j + (int64_t)j * ldg];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double sh = c * red[0];
+  for (int j = threadIdx.x; j < l; j += 256) G[j + (int64_t)j * ldg] += sh;
+}
+
+int shift_diag(const rmm_ctx* h, int l, double* G, int64_t ldg, double c) {
+  if (l == 0) return RMM_OK;
+  hipLaunchKernelGGL(shift_diag_kernel, dim3(1), dim3(256), 0, h->stream, l, G, ldg, c);
+  return launch_status();
+}
+
 // ---- sign convention, small glue -------------------------------------------------------
 
 template <typename T>
@@ -968,28 +1390,6 @@ template <typename T>
 int sign_fix(const rmm_ctx* h, int64_t m, int64_t n, int k, T* U, int64_t ldu, T* V, int64_t ldv) {
   if (k == 0) return RMM_OK;
   hipLaunchKernelGGL((sign_fix_kernel<T>), dim3(k), dim3(1024), 0, h->stream, m, n, U, ldu, V, ldv);
-  return launch_status();
-}
-
-template <typename T>
-__global__ void svd_from_eig_kernel(int l, int k, const double* __restrict__ evals,
-                                    const double* __restrict__ Vr, double* __restrict__ W,
-                                    T* __restrict__ sigma) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= l * k) return;
-  const int a = e % l, c = e / l;
-  const double lam = evals[c] > 0.0 ? evals[c] : 0.0;
-  const double sg = sqrt(lam);
-  W[a + (int64_t)c * l] = sg > 0.0 ? Vr[a + (int64_t)c * l] / sg : 0.0;
-  if (a == 0) sigma[c] = (T)sg;
-}
-
-template <typename T>
-int svd_from_eig(const rmm_ctx* h, int l, int k, const double* evals, const double* Vr, double* W,
-                 T* sigma) {
-  if (l * k == 0) return RMM_OK;
-  hipLaunchKernelGGL((svd_from_eig_kernel<T>), dim3((l * k + 255) / 256), dim3(256), 0, h->stream, l,
-                     k, evals, Vr, W, sigma);
   return launch_status();
 }
 
@@ -1067,7 +1467,5 @@ int trmv_upper(const rmm_ctx* h, int d, const double* Rinv, const double* y, dou
 
 template int sign_fix<float>(const rmm_ctx*, int64_t, int64_t, int, float*, int64_t, float*, int64_t);
 template int sign_fix<double>(const rmm_ctx*, int64_t, int64_t, int, double*, int64_t, double*, int64_t);
-template int svd_from_eig<float>(const rmm_ctx*, int, int, const double*, const double*, double*, float*);
-template int svd_from_eig<double>(const rmm_ctx*, int, int, const double*, const double*, double*, double*);
 
 }  // namespace rmm

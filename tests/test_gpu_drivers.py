@@ -49,6 +49,39 @@ def test_rsvd_config_fp64(h):
     assert np.abs(V.T @ V - np.eye(20)).max() < 1e-13
 
 
+def _wide_spectrum(m, n, seed):
+    """A = U diag(10^(-i/3)) V^T, U, V orthonormal: sigma_20 ~ 2e-7 sigma_1,
+    sigma_30 ~ 1e-10 sigma_1 (no noise)."""
+    r = np.random.default_rng(seed)
+    Uq, _ = np.linalg.qr(r.standard_normal((m, n)))
+    Vq, _ = np.linalg.qr(r.standard_normal((n, n)))
+    sv = 10.0 ** (-np.arange(n) / 3.0)
+    return (Uq * sv) @ Vq.T, sv
+
+
+@pytest.mark.parametrize("q", [0, 2])
+def test_rsvd_wide_spectrum_fp64(h, q):
+    """k = 20, l = 30 on a spectrum spanning 10 decades.  A backward-stable
+    small SVD leaves each sigma_i within O(eps) sigma_1 (relative error
+    O(eps) sigma_1 / sigma_i); the route through eig(Z^T Z) would be off by
+    eps sigma_1^2 / sigma_i ~ 1e-9 sigma_1 at sigma_20 and its V would lose
+    orthogonality at the 1e-3 level.  Every sigma_i is checked against the
+    oracle (and, with q = 2, against the exact spectrum), and U, V for
+    orthonormality."""
+    A, sv = _wide_spectrum(2048, 512, 21)
+    k, p = 20, 10
+    U, s, V, st = h.rsvd(dev(A), k, p, q, 61)
+    Ur, sr, Vr, _ = orsvd.rsvd(A, k, p, q, 61, fp64=True)
+    assert int(st.item()) == 0
+    U, s, V = host(U), host(s), host(V)
+    assert np.abs(s - sr).max() <= 1e-12 * sr[0]
+    if q == 2:  # the randomized error (sigma_31 / sigma_20)^5 is far below 1e-12
+        assert np.abs(s - sv[:k]).max() <= 1e-12 * sv[0]
+    assert np.abs(U.T @ U - np.eye(k)).max() < 1e-12
+    assert np.abs(V.T @ V - np.eye(k)).max() < 1e-12
+    assert rel((U * s) @ V.T, (Ur * sr) @ Vr.T) < 1e-12
+
+
 @pytest.mark.parametrize("m,n,k,p,q", [(1000, 37, 5, 3, 0), (301, 300, 7, 9, 1), (64, 4000, 3, 2, 2),
                                        (5000, 129, 16, 16, 1)])
 def test_rsvd_shapes_fp64(h, m, n, k, p, q):
@@ -111,7 +144,7 @@ def test_rsvd_invalid(h):
         h.rsvd(A, 6, 4, 0, 1)  # k + p > min(m, n)
     B = torch.zeros(2000, 1100, dtype=torch.float64, device="cuda")
     with pytest.raises(rmm.RmmError):
-        h.rsvd(B, 1000, 30, 0, 1)  # k + p > 1024: eigensolver limit
+        h.rsvd(B, 1000, 30, 0, 1)  # k + p > 1024: small-SVD limit
 
 
 # ---- least squares --------------------------------------------------------------------
@@ -308,7 +341,7 @@ def test_rsvd_faster_parity(h, dtype, kind2, ok2, m, n, k, s, pcs, p):
     U, sig, V, st = h.rsvd_faster(dev(A, dtype), k, s, pcs, p, seed, kind2)
     Ur, sr, Vr = orsvd.ksvd_faster(A.astype(np.float64), k, s, pcs, p, seed, ok2,
                                    fp64=(dtype == torch.float64))
-    tol = 1e-10 if dtype == torch.float64 else 2e-4
+    tol = TOL[dtype]
     assert int(st.item()) == 0
     U, sig, V = host(U), host(sig), host(V)
     assert np.abs(sig - sr).max() <= tol * sr[0]
@@ -351,7 +384,7 @@ def test_rsvd_lanczos_parity(h, dtype, m, n, k, s, q):
     U, sig, V, st = h.rsvd_lanczos(dev(A, dtype), k, s, q, seed)
     Ur, sr, Vr, _ = orsvd.block_lanczos(A.astype(np.float64), k, s, q, seed,
                                         fp64=(dtype == torch.float64))
-    tol = 1e-10 if dtype == torch.float64 else 2e-4
+    tol = TOL[dtype]
     assert int(st.item()) == 0
     U, sig, V = host(U), host(sig), host(V)
     assert np.abs(sig - sr).max() <= tol * sr[0]
