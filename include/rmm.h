@@ -66,7 +66,9 @@ typedef enum {
   RMM_ERR_INVALID_ARG = -1,        /* null pointer, bad size or leading dimension */
   RMM_ERR_WORKSPACE_TOO_SMALL = -2,
   RMM_ERR_HIP = -3,                /* a HIP runtime call failed */
-  RMM_ERR_UNSUPPORTED = -4         /* valid but unsupported combination */
+  RMM_ERR_UNSUPPORTED = -4,        /* valid but unsupported combination */
+  RMM_ERR_SCRATCH_LIMIT = -5       /* rmm_sketched_lsr_noalloc: the problem needs more
+                                      than RMM_NOALLOC_SCRATCH_BYTES of scratch */
 } rmm_status;
 
 /* device-side status flags */
@@ -266,6 +268,24 @@ int rmm_sketched_lsr(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,
                      int64_t m, int64_t d, const void* A, int64_t lda,
                      const void* b, int64_t s, uint64_t seed, double* x,
                      double* resid, int32_t* status);
+/* rmm_sketched_lsr without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * rmm_sketched_lsr (bitwise); the scratch comes from a static device array of
+ * RMM_NOALLOC_SCRATCH_BYTES (128 MiB) per device, set up by rmm_create and
+ * held until the process ends.  The handle's registered workspace is neither
+ * used nor changed.  Nothing is allocated: no hipMalloc, hipFree or
+ * allocating library call.  Returns RMM_ERR_SCRATCH_LIMIT when
+ * rmm_lsr_workspace reports more than RMM_NOALLOC_SCRATCH_BYTES (e.g. the
+ * Gaussian sketch of a 2^20 x 257 FP32 [A | b] to s = 4096, whose split-K
+ * partials alone take 270 MB; CountSketch and SRHT of that problem fit) and
+ * RMM_ERR_HIP when the array's address could not be looked up.  Every call
+ * on one device shares that device's array: calls that overlap on one device
+ * (two streams, two host threads) race and give wrong results. */
+#define RMM_NOALLOC_SCRATCH_BYTES (128u << 20)
+int rmm_sketched_lsr_noalloc(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind, int64_t m,
+                             int64_t d, const void* A, int64_t lda, const void* b, int64_t s,
+                             uint64_t seed, double* x, double* resid, int32_t* status);
 /* Machine-precision least squares (Alg. 4.1, Sec. 4.3): the sketch of [A | b]
  * gives the preconditioner T = R^{-1} (R from the FP64 CholeskyQR2 of S^T A)
  * and the start x0 (the sketch-and-solve solution of rmm_sketched_lsr); then

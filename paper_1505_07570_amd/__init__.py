@@ -28,6 +28,8 @@ F32, F64 = 0, 1
 STATUS_RANK_DEFICIENT = 1
 STATUS_QR_FALLBACK = 2
 STATUS_NOT_CONVERGED = 4
+ERR_SCRATCH_LIMIT = -5
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 _i64 = ctypes.c_int64
 _u64 = ctypes.c_uint64
@@ -84,6 +86,8 @@ def lib():
                          _vp, _i64, _vp, _vp, _i64, _vp],
             "rmm_lsr_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_sketched_lsr": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _vp, _vp],
+            "rmm_sketched_lsr_noalloc": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp,
+                                         _vp, _vp],
             "rmm_precise_lsr_workspace": [_vp, _i32, _i32, _i64, _i64, _i64,
                                           ctypes.POINTER(ctypes.c_size_t)],
             "rmm_precise_lsr": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _i64, _vp,
@@ -267,6 +271,11 @@ class Handle:
         _check(lib().rmm_set_workspace(self._h, _ptr(self._ws), self._ws.numel()),
                "rmm_set_workspace")
 
+    def _bind_stream(self):
+        """Bind the current torch stream only (no workspace)."""
+        stream = torch.cuda.current_stream(self.device)
+        _check(lib().rmm_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)), "rmm_set_stream")
+
     def reserve(self, nbytes: int):
         self._prepare(nbytes)
 
@@ -408,6 +417,22 @@ class Handle:
         self._prepare(ws.value)
         _check(lib().rmm_sketched_lsr(self._h, dt, _kind(kind), m, d, _ptr(A), _ld(A), _ptr(b), s,
                                       seed, _ptr(x), _ptr(res), _ptr(status)), "rmm_sketched_lsr")
+        return x, res, status
+
+    def sketched_lsr_noalloc(self, A: torch.Tensor, b: torch.Tensor, s: int, kind, seed: int,
+                             residual: bool = True):
+        """sketched_lsr with the library's static device scratch instead of the
+        handle's workspace (the workspace is neither grown nor used)."""
+        A = colmajor(A)
+        m, d = A.shape
+        dt = _dt(A)
+        x = torch.empty(d, dtype=torch.float64, device=A.device)
+        res = torch.empty(1, dtype=torch.float64, device=A.device) if residual else None
+        status = torch.zeros(1, dtype=torch.int32, device=A.device)
+        self._bind_stream()
+        _check(lib().rmm_sketched_lsr_noalloc(self._h, dt, _kind(kind), m, d, _ptr(A), _ld(A),
+                                              _ptr(b), s, seed, _ptr(x), _ptr(res), _ptr(status)),
+               "rmm_sketched_lsr_noalloc")
         return x, res, status
 
     def precise_lsr(self, A: torch.Tensor, b: torch.Tensor, s: int, kind, seed: int, iters: int,

@@ -147,6 +147,7 @@ int rmm_create(rmm_handle* h, int device) {
       v > 0)
     c->lds_bytes = (size_t)v;
   if (const char* path = getenv("RMM_TUNE_CACHE")) (void)rmm_autotune_load(c, path);
+  (void)noalloc_scratch(device);  // rmm_sketched_lsr_noalloc reports a failed lookup
   *h = c;
   return RMM_OK;
 }
@@ -236,6 +237,7 @@ const char* rmm_strerror(int code) {
     case RMM_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
     case RMM_ERR_HIP: return "HIP runtime error";
     case RMM_ERR_UNSUPPORTED: return "unsupported combination";
+    case RMM_ERR_SCRATCH_LIMIT: return "problem needs more than the static scratch of the no-alloc entry point";
   }
   return "unknown error";
 }

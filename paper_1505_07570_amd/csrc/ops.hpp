@@ -65,6 +65,10 @@ int pcg_step(const rmm_ctx* h, int d, const double* part, const double* M, doubl
              double* y, double* p, double* sc);
 int pass_resid(const rmm_ctx* h, int d, const double* part, double* out);
 
+// Device address of the static scratch array of rmm_sketched_lsr_noalloc on
+// `device` (looked up once per device; null when the lookup failed).
+void* noalloc_scratch(int device);
+
 int launch_sample_indices_u32(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
                               uint32_t tag, uint64_t seed, uint32_t* out);
 int launch_sample_indices_i64(const rmm_ctx* h, uint64_t domain, int k, int64_t s,
