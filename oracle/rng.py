@@ -115,7 +115,12 @@ def countsketch_hash_sign(m: int, s: int, seed: int):
     uniformly from [s] and a sign uniformly from {+1, -1}; here the sketched
     dimension is the row dimension of A (the row form S^T A of eq. 4.2).
     """
-    w = row_words(np.arange(m, dtype=np.uint64), TAG_COUNTSKETCH, seed)
+    return countsketch_hash_sign_rows(np.arange(m, dtype=np.uint64), s, seed)
+
+
+def countsketch_hash_sign_rows(rows, s: int, seed: int):
+    """h_i and g_i of countsketch_hash_sign for the listed row indices."""
+    w = row_words(np.asarray(rows, dtype=np.uint64), TAG_COUNTSKETCH, seed)
     h = ((w * np.uint64(s)) >> _S32).astype(np.int64)
     g = np.where((w & np.uint64(1)) == 0, 1, -1).astype(np.int64)
     return h, g
@@ -128,7 +133,12 @@ def srht_signs(m: int, seed: int):
     (i div 128, TAG_SRHT_SIGN, 0); bit b sits in word b div 32 at position
     b mod 32; a set bit means -1.
     """
-    i = np.arange(m, dtype=np.uint64)
+    return srht_signs_rows(np.arange(m, dtype=np.uint64), seed)
+
+
+def srht_signs_rows(rows, seed: int):
+    """d_i of srht_signs for the listed row indices."""
+    i = np.asarray(rows, dtype=np.uint64)
     lo, hi = _split64(i >> np.uint64(7))
     w = philox4x32_10(lo, hi, TAG_SRHT_SIGN, 0, seed)
     bit = i & np.uint64(127)

@@ -79,7 +79,7 @@ def srht_indices(m: int, s: int, seed: int):
     return rng.sample_indices(N, s, rng.TAG_SRHT_SAMPLE, seed)
 
 
-def srht_matrix(m: int, s: int, seed: int, cols=None):
+def srht_matrix(m: int, s: int, seed: int, cols=None, rows=None):
     """S = s^{-1/2} D H_N[0:m, idx] (m x s), or the listed columns of it.
 
     Sec. 3.2.2: random signs D on the m real rows, zero-padding to N, the
@@ -95,35 +95,40 @@ def srht_matrix(m: int, s: int, seed: int, cols=None):
     idx = srht_indices(m, s, seed)
     if cols is not None:
         idx = idx[np.asarray(cols)]
-    d = rng.srht_signs(m, seed).astype(np.float64)
-    H = hadamard_entries(np.arange(m)[:, None], idx[None, :]).astype(np.float64)
+    r = np.arange(m) if rows is None else np.asarray(rows)
+    d = rng.srht_signs_rows(r, seed).astype(np.float64)
+    H = hadamard_entries(r[:, None], idx[None, :]).astype(np.float64)
     return (d[:, None] * H) / np.sqrt(s)
 
 
-def gaussian_matrix(m: int, s: int, seed: int, fp64: bool, cols=None):
+def gaussian_matrix(m: int, s: int, seed: int, fp64: bool, cols=None, rows=None):
     """S = G / sqrt(s) with G i.i.d. N(0, 1) (Sec. 3.2.1)."""
     c = np.arange(s) if cols is None else np.asarray(cols)
-    G = rng.gaussian(np.arange(m), c, rng.TAG_GAUSS_SKETCH, seed, fp64)
+    r = np.arange(m) if rows is None else np.asarray(rows)
+    G = rng.gaussian(r, c, rng.TAG_GAUSS_SKETCH, seed, fp64)
     return G / np.sqrt(s)
 
 
 def sketch_matrix(kind: int, m: int, s: int, seed: int, fp64: bool = True,
-                  cols=None):
-    """Columns ``cols`` (default: all) of the m x s sketch matrix S.
+                  cols=None, rows=None):
+    """Columns ``cols`` (default: all) and rows ``rows`` (default: all) of
+    the m x s sketch matrix S; row and column indices are global, so a
+    block of rows of S is exactly that block of the full matrix.
 
     ``fp64`` only matters for the Gaussian kind, whose entries are drawn
     from 53-bit (fp64) or 24-bit (fp32) uniforms.
     """
     if kind == GAUSSIAN:
-        return gaussian_matrix(m, s, seed, fp64, cols)
+        return gaussian_matrix(m, s, seed, fp64, cols, rows)
     if kind == SRHT:
-        return srht_matrix(m, s, seed, cols)
+        return srht_matrix(m, s, seed, cols, rows)
     if kind == COUNTSKETCH:
-        if cols is None:
+        if cols is None and rows is None:
             return countsketch_matrix(m, s, seed)
-        h, g = rng.countsketch_hash_sign(m, s, seed)
-        cols = np.asarray(cols)
-        return np.where(h[:, None] == cols[None, :], g[:, None], 0).astype(np.float64)
+        r = np.arange(m) if rows is None else np.asarray(rows)
+        c = np.arange(s) if cols is None else np.asarray(cols)
+        h, g = rng.countsketch_hash_sign_rows(r, s, seed)
+        return np.where(h[:, None] == c[None, :], g[:, None], 0).astype(np.float64)
     raise ValueError("unknown sketch kind")
 
 

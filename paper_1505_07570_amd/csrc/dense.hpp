@@ -49,6 +49,14 @@ size_t jacobi_workspace(int l);
 int jacobi_svd(const rmm_ctx* h, int l, const double* M, int64_t ldm, double* sigma, double* Ubar,
                double* J, int32_t* status, Carver& ws);
 size_t jacobi_svd_workspace(int l);
+// The same one-sided Jacobi applied directly to the columns of a tall X
+// (rows x l, rows >= l, input type TI): X J = Ux diag(sigma) with Ux (rows x
+// l, ld rows) the normalized columns; possible when jacobi_svd_direct_ok
+// (X fits in one workgroup's LDS, l <= 128).  Workspace jacobi_svd_workspace(l).
+bool jacobi_svd_direct_ok(int64_t rows, int l);
+template <typename TI>
+int jacobi_svd_direct(const rmm_ctx* h, int64_t rows, int l, const TI* X, int64_t ldx, double* sigma,
+                      double* Ux, double* J, int32_t* status, Carver& ws);
 
 // G_jj += c * trace(G) (l x l, fp64): the shift of shifted CholeskyQR.
 int shift_diag(const rmm_ctx* h, int l, double* G, int64_t ldg, double c);

@@ -103,9 +103,13 @@ int orth(rmm_ctx* h, int64_t rows, int l, const T* X, int64_t ldx, TQ* Q, int64_
 
 // ---- small SVD of a tall matrix ----------------------------------------------------
 //
-// X (rows x l) = Qx Mx with Qx (rows x l, fp64) from shifted CholeskyQR with
-// three passes and Mx = Qx^T X (l x l); then one-sided Jacobi on Mx:
-// Mx J = Ubar diag(sigma), so X = (Qx Ubar) diag(sigma) J^T.
+// X (rows x l) = Ux diag(sigma) J^T with sigma descending, J (l x l)
+// orthogonal and Ux (rows x kk) the first kk left singular vectors, all fp64:
+// * when X fits in one workgroup's LDS, one-sided Jacobi on X itself
+//   (X J = Ux diag(sigma));
+// * otherwise X = Qx Mx with Qx from shifted CholeskyQR with three passes and
+//   Mx = Qx^T X (l x l), one-sided Jacobi on Mx (Mx J = Ubar diag(sigma)) and
+//   Ux = Qx Ubar[:, :kk].
 struct SvdBufs {
   OrthBufs ob;
   double* Qx;     // rows x l
@@ -113,6 +117,7 @@ struct SvdBufs {
   double* sigma;  // l
   double* Ubar;   // l x l
   double* J;      // l x l
+  double* Ux;     // rows x l
 };
 
 SvdBufs take_svd(Carver& ws, int64_t rows, int l) {
@@ -123,6 +128,7 @@ SvdBufs take_svd(Carver& ws, int64_t rows, int l) {
   b.sigma = ws.take<double>((size_t)l);
   b.Ubar = ws.take<double>((size_t)l * l);
   b.J = ws.take<double>((size_t)l * l);
+  b.Ux = ws.take<double>((size_t)rows * l);
   return b;
 }
 
@@ -130,30 +136,34 @@ template <typename T>
 size_t svd_scratch(const rmm_ctx* h, int64_t rows, int l) {
   size_t w = orth_scratch<T>(h, rows, l);
   w = smax(w, gemm_workspace<double>(h, l, l, rows));
+  w = smax(w, gemm_workspace<double>(h, (int)rows, l, l));
   w = smax(w, jacobi_svd_workspace(l));
   return w;
 }
 
 template <typename T>
-int tall_svd(rmm_ctx* h, int64_t rows, int l, const T* X, int64_t ldx, const SvdBufs& b,
+int tall_svd(rmm_ctx* h, int64_t rows, int l, int kk, const T* X, int64_t ldx, const SvdBufs& b,
              int32_t* status, Carver& ws) {
+  if (jacobi_svd_direct_ok(rows, l))
+    return jacobi_svd_direct<T>(h, rows, l, X, ldx, b.sigma, b.Ux, b.J, status, ws);
   const double tau = 64.0 * kEps * (double)(rows > l ? rows : l);
   RMM_TRY((orth<T, double>(h, rows, l, X, ldx, b.Qx, rows, b.ob, tau, status, ws, 3)));
   RMM_TRY((gemm<double, T, double, double>(h, true, false, l, l, rows, b.Qx, rows, X, ldx, 1.0, b.Mx,
                                            l, ws)));
-  return jacobi_svd(h, l, b.Mx, l, b.sigma, b.Ubar, b.J, status, ws);
+  RMM_TRY(jacobi_svd(h, l, b.Mx, l, b.sigma, b.Ubar, b.J, status, ws));
+  return gemm<double, double, double, double>(h, false, false, (int)rows, kk, l, b.Qx, rows, b.Ubar, l,
+                                              1.0, b.Ux, rows, ws);
 }
 
 // ---- randomized SVD --------------------------------------------------------------
 
-// U = Q J[:, :k], V = Qz Ubar[:, :k], sigma = sigma_B[:k] from the small SVD
-// of Z = A^T Q (see the header comment); then the sign convention.
+// U = Q J[:, :k], V = Ux[:, :k], sigma = sigma[:k] from the small SVD of
+// Z = A^T Q = Ux diag(sigma) J^T; then the sign convention.
 template <typename T>
 int finish_rsvd(rmm_ctx* h, int64_t m, int64_t n, int l, int k, const T* Q, const SvdBufs& sb,
                 T* U, int64_t ldu, T* sigma, T* V, int64_t ldv, Carver& ws) {
   RMM_TRY((gemm<T, double, double, T>(h, false, false, (int)m, k, l, Q, m, sb.J, l, 1.0, U, ldu, ws)));
-  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)n, k, l, sb.Qx, n, sb.Ubar, l, 1.0, V,
-                                           ldv, ws)));
+  RMM_TRY((copy_cast<double, T>(h, n, k, sb.Ux, n, V, ldv)));
   RMM_TRY((copy_cast<double, T>(h, k, 1, sb.sigma, k, sigma, k)));
   return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
 }
@@ -200,7 +210,7 @@ int rsvd_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t ld
   RMM_TRY((orth<T, T>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws, 3)));
   // projection: Z = A^T Q = B^T, and the small SVD of B from that of Z
   RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Q, m, l, Z, n, ws));
-  RMM_TRY(tall_svd<T>(h, n, l, Z, n, sb, status, ws));
+  RMM_TRY(tall_svd<T>(h, n, l, k, Z, n, sb, status, ws));
   return finish_rsvd<T>(h, m, n, l, k, Q, sb, U, ldu, sigma, V, ldv, ws);
 }
 
@@ -257,7 +267,7 @@ int lanczos_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, const T* A, int64_t
   }
   // Z = A^T Q_C = B^T and the small SVD of B from that of Z
   RMM_TRY(project_tn<T>(h, m, (int)n, A, lda, Qc, m, L, Z, n, ws));
-  RMM_TRY(tall_svd<T>(h, n, L, Z, n, sb, status, ws));
+  RMM_TRY(tall_svd<T>(h, n, L, k, Z, n, sb, status, ws));
   return finish_rsvd<T>(h, m, n, L, k, Qc, sb, U, ldu, sigma, V, ldv, ws);
 }
 
@@ -319,7 +329,7 @@ int rsvd_mixed(rmm_ctx* h, bool run, rmm_precision prec, int64_t m, int64_t n, c
   RMM_TRY((orth<float, float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws, 3)));
   RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq));
   RMM_TRY(mp_gemm_tn(h, prec, (int)n, l, pm, Aq, Qq, sc, uq, Z, n, ws));
-  RMM_TRY(tall_svd<float>(h, n, l, Z, n, sb, status, ws));
+  RMM_TRY(tall_svd<float>(h, n, l, k, Z, n, sb, status, ws));
   return finish_rsvd<float>(h, m, n, l, k, Q, sb, U, ldu, sigma, V, ldv, ws);
 }
 
@@ -555,7 +565,6 @@ int rsvd_faster_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind2, int64_t m, int
   SvdBufs sz = take_svd(ws, n, s);
   double* T1 = ws.take<double>((size_t)s * k);
   double* T2 = ws.take<double>((size_t)s * k);
-  double* Vb = ws.take<double>((size_t)n * k);
   double* M = ws.take<double>((size_t)m * k);
   SvdBufs sm = take_svd(ws, m, k);
   size_t scratch = countsketch_cols_workspace(n);
@@ -596,26 +605,23 @@ int rsvd_faster_impl(rmm_ctx* h, bool run, rmm_sketch_kind kind2, int64_t m, int
   RMM_TRY(rank_check(h, s, lb.d1, lb.d2, 10.0 * (double)p * kEps, status));
   RMM_TRY((gemm<double, double, double, double>(h, false, false, s, s, s, lb.R1, s, lb.R2, s, 1.0, Ri,
                                                 s, ws)));
-  // step 4: Z^T = L^T Q_D = (Qx Ubar_z) Sigma_z J_z^T, so that Z = J_z Sigma_z
-  // (Qx Ubar_z)^T: Ubar = J_z[:, :k], Sigmabar = Sigma_z[:k], Vbar = Qx Ubar_z[:, :k]
+  // step 4: Z^T = L^T Q_D = Ux_z Sigma_z J_z^T, so that Z = J_z Sigma_z Ux_z^T:
+  // Ubar = J_z[:, :k], Sigmabar = Sigma_z[:k], Vbar = Ux_z[:, :k]
   RMM_TRY((gemm<T, double, double, double>(h, true, false, (int)n, s, p, L, p, lb.Q, p, 1.0, Zt, n,
                                            ws)));
-  RMM_TRY(tall_svd<double>(h, n, s, Zt, n, sz, status, ws));
-  RMM_TRY((gemm<double, double, double, double>(h, false, false, (int)n, k, s, sz.Qx, n, sz.Ubar, s,
-                                                1.0, Vb, n, ws)));
-  // step 5: M = C R_D^{-1} Ubar Sigmabar = (Qm Ubar_m) Sigma J_m^T
+  RMM_TRY(tall_svd<double>(h, n, s, k, Zt, n, sz, status, ws));
+  // step 5: M = C R_D^{-1} Ubar Sigmabar = Ux_m Sigma J_m^T
   hipLaunchKernelGGL(scale_cols_kernel, dim3((s * k + 255) / 256), dim3(256), 0, h->stream, s, k, sz.J,
                      (int64_t)s, sz.sigma, T1);
   RMM_TRY(launch_status());
   RMM_TRY((gemm<double, double, double, double>(h, false, false, s, k, s, Ri, s, T1, s, 1.0, T2, s, ws)));
   RMM_TRY((gemm<T, double, double, double>(h, false, false, (int)m, k, s, C, m, T2, s, 1.0, M, m, ws)));
-  RMM_TRY(tall_svd<double>(h, m, k, M, m, sm, status, ws));
-  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)m, k, k, sm.Qx, m, sm.Ubar, k, 1.0, U,
-                                           ldu, ws)));
+  RMM_TRY(tall_svd<double>(h, m, k, k, M, m, sm, status, ws));
+  RMM_TRY((copy_cast<double, T>(h, m, k, sm.Ux, m, U, ldu)));
   RMM_TRY((copy_cast<double, T>(h, k, 1, sm.sigma, k, sigma, k)));
   // step 6: V = Vbar Vhat, Vhat = J_m
-  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)n, k, k, Vb, n, sm.J, k, 1.0, V, ldv,
-                                           ws)));
+  RMM_TRY((gemm<double, double, double, T>(h, false, false, (int)n, k, k, sz.Ux, n, sm.J, k, 1.0, V,
+                                           ldv, ws)));
   return sign_fix<T>(h, m, n, k, U, ldu, V, ldv);
 }
 

@@ -356,6 +356,35 @@ __device__ __forceinline__ void rr_pair(int i, int r, int L, int& p, int& q) {
   q = a < b ? b : a;
 }
 
+// Pair order of osj_kernel.  L is a power of two and the P = L/2 lane groups
+// work on L/2 disjoint pairs per round.  Level t of a sweep (t = 0, 1, ...)
+// splits the columns into blocks of 2Q with Q = P >> t; the Q groups of a
+// block b keep its first Q columns ("residents") and pass its last Q
+// columns ("travellers") around: in round u of the level, group i = bQ + j
+// pairs resident 2Qb + j with traveller 2Qb + Q + (j + u) mod Q, then hands
+// its traveller to group j - 1 of the block.  Level t covers every
+// resident-traveller pair of its blocks once, and the residents and the
+// travellers of a block become the two blocks of level t + 1, so a sweep
+// (levels Q = P, P/2, ..., 1: P + P/2 + ... + 1 = L - 1 rounds) meets
+// every pair exactly once, while a group reads and writes only one column
+// per round.
+__device__ __forceinline__ void hier_pair(int i, int r, int L, int& p, int& q) {
+  int Q = L / 2, u = r;
+  while (u >= Q) {
+    u -= Q;
+    Q >>= 1;
+  }
+  const int b = i / Q, j = i & (Q - 1);
+  p = 2 * Q * b + j;
+  q = 2 * Q * b + Q + ((j + u) & (Q - 1));
+}
+
+__host__ __device__ inline int pow2_ceil(int l) {
+  int L = 2;
+  while (L < l) L <<= 1;
+  return L;
+}
+
 __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const double* __restrict__ G,
                                                                int64_t ldg, double* __restrict__ evals,
                                                                int* __restrict__ perm,
@@ -522,12 +551,13 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
 // One wave owns kVecRows rows of V in LDS; lane i applies pair i of every
 // round to those rows (the pairs of a round are disjoint, and one wave's LDS
 // accesses are performed in program order, so no barrier is needed).
+template <bool HIER>
 __global__ __launch_bounds__(256) void jacobi_vectors_kernel(int l, const double2* __restrict__ rlog,
                                                              const int* __restrict__ nrounds,
                                                              const int* __restrict__ perm,
                                                              double* __restrict__ Vout) {
   extern __shared__ double vs[];  // 4 waves x kVecRows x L, then the pair tables
-  const int L = (l + 1) & ~1;
+  const int L = HIER ? pow2_ceil(l) : (l + 1) & ~1;
   const int npairs = L / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* V = vs + (size_t)wave * kVecRows * L;
@@ -535,7 +565,10 @@ __global__ __launch_bounds__(256) void jacobi_vectors_kernel(int l, const double
   unsigned char* qtab = ptab + (size_t)(L - 1) * npairs;
   for (int e = threadIdx.x; e < (L - 1) * npairs; e += blockDim.x) {
     int p, q;
-    rr_pair(e % npairs, e / npairs, L, p, q);
+    if (HIER)
+      hier_pair(e % npairs, e / npairs, L, p, q);
+    else
+      rr_pair(e % npairs, e / npairs, L, p, q);
     ptab[e] = (unsigned char)p;
     qtab[e] = (unsigned char)q;
   }
@@ -910,11 +943,11 @@ int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* ev
                      perm, rlog, nr, status, kJacobiMaxSweeps);
   RMM_TRY(launch_status());
   const size_t vlds = (size_t)4 * kVecRows * L * sizeof(double) + 2 * (size_t)(L - 1) * npairs;
-  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel,
+  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel<false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
   const int groups = (l + 4 * kVecRows - 1) / (4 * kVecRows);
-  hipLaunchKernelGGL(jacobi_vectors_kernel, dim3(groups), dim3(256), vlds, h->stream, l, rlog, nr,
-                     perm, V);
+  hipLaunchKernelGGL(jacobi_vectors_kernel<false>, dim3(groups), dim3(256), vlds, h->stream, l, rlog,
+                     nr, perm, V);
   ws.off = mark;
   return launch_status();
 }
@@ -933,18 +966,17 @@ int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* ev
 //   zeta = (b - a) / (2 c),  t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 //   cs = 1 / sqrt(1 + t^2),  sn = t cs,
 //   col_p <- cs col_p - sn col_q,  col_q <- sn col_p + cs col_q.
-// The pairs of a round follow the same circle method as the eigensolver, and
-// the (cs, sn) of every pair of every round go to the same log, so J is
-// accumulated by jacobi_vectors_kernel.  A sweep without a rotation ends the
+// The (cs, sn) of every pair of every round go to a log from which
+// jacobi_vectors_kernel accumulates J.  A sweep without a rotation ends the
 // iteration (the columns are orthogonal to the test's precision).
 //
-// osj_kernel (l <= 128, one workgroup): M sits in LDS column-major; a group
-// of g lanes (a power of two, 16 at l = 128) owns one pair per round, holds
-// R <= 8 rows of each of its two columns in registers and forms a, b, c with
-// a butterfly reduction over the group.  Each butterfly step adds two lanes'
-// values in both lanes, so every lane of a group ends with bitwise the same
-// sums and takes the same decision.  One barrier per round: within a round
-// the pairs are disjoint.
+// osj_kernel (l <= 128, one workgroup): the columns are padded with zeros to
+// L = 2^ceil(log2 l) and visited in the resident/traveller order of
+// hier_pair.  A group of 16 lanes holds R <= 8 rows of its resident and of
+// its current traveller in registers and forms a, b, c with a butterfly
+// reduction over the group.  One barrier per round (the traveller hand-over
+// through LDS), three per level change.  The big path (l > 128) keeps the
+// circle order of the eigensolver.
 constexpr int kOsjMaxRows = 8;
 
 // DPP lane permutations inside a row of 16 lanes
@@ -990,74 +1022,117 @@ __device__ __forceinline__ bool osj_rotation(double a, double b, double c, doubl
   return true;
 }
 
-__global__ __launch_bounds__(kSmallThreads) void osj_kernel(int l, const double* __restrict__ M,
-                                                            int64_t ldm, int gl2,
-                                                            double* __restrict__ sigma,
+// Sums of a, b, c over each row of 16 lanes, the three reductions in
+// lockstep (DPP only; every step's partner is an involution, so both lanes
+// of a step add the same two values and the row ends bitwise uniform).
+__device__ __forceinline__ void row16_sum3(double& a, double& b, double& c) {
+  a += dpp_f64<kDppQuad1032>(a);
+  b += dpp_f64<kDppQuad1032>(b);
+  c += dpp_f64<kDppQuad1032>(c);
+  a += dpp_f64<kDppQuad2301>(a);
+  b += dpp_f64<kDppQuad2301>(b);
+  c += dpp_f64<kDppQuad2301>(c);
+  a += dpp_f64<kDppRowHalfMirror>(a);
+  b += dpp_f64<kDppRowHalfMirror>(b);
+  c += dpp_f64<kDppRowHalfMirror>(c);
+  a += dpp_f64<kDppRowMirror>(a);
+  b += dpp_f64<kDppRowMirror>(b);
+  c += dpp_f64<kDppRowMirror>(c);
+}
+
+// One group of 16 lanes per pair; lane t holds rows t, t + 16, ...,
+// t + 16 (R - 1) of its two columns.  In LDS every column has 16 R entries
+// (rows past `rows` are zero and stay zero under rotations), so the round
+// loop needs no bounds checks.
+template <typename TI, int R>
+__global__ __launch_bounds__(kSmallThreads) void osj_kernel(int rows, int l, const TI* __restrict__ M,
+                                                            int64_t ldm, double* __restrict__ sigma,
                                                             int* __restrict__ perm,
                                                             double* __restrict__ Ubar,
                                                             double2* __restrict__ rlog,
                                                             int* __restrict__ nrounds,
                                                             int32_t* status, int max_sweeps) {
-  extern __shared__ double S[];  // L columns of L rows
+  // L columns of LD entries (16 R, padded by 128 bytes from R = 2 on so that
+  // the columns of neighbouring groups start in opposite halves of the LDS
+  // banks): the whole matrix between levels; within a level its two halves
+  // are the alternating buffers through which the travellers move
+  constexpr int LD = R == 1 ? 16 : 16 * R + 16;
+  extern __shared__ double S[];
   __shared__ double nrm[kLdsMaxL];
   __shared__ int sperm[kLdsMaxL];
   __shared__ int rotated[2];
-  const int L = (l + 1) & ~1;
-  const int npairs = L / 2;
-  const int g = 1 << gl2;
-  const int tid = threadIdx.x, pair = tid >> gl2, t = tid & (g - 1);
-  for (int e = tid; e < L * L; e += blockDim.x) {
-    const int a = e % L, b = e / L;
-    S[e] = (a < l && b < l) ? M[a + (int64_t)b * ldm] : 0.0;
+  const int L = pow2_ceil(l);
+  const int P = L / 2;
+  const int tid = threadIdx.x, grp = tid >> 4, t = tid & 15;
+  double x[R], y[R];  // resident and traveller rows t, t + 16, ...
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int i = t + 16 * k;
+    x[k] = (i < rows && grp < l) ? (double)M[i + (int64_t)grp * ldm] : 0.0;
+    y[k] = (i < rows && P + grp < l) ? (double)M[i + (int64_t)(P + grp) * ldm] : 0.0;
   }
   if (tid < 2) rotated[tid] = 0;
   __syncthreads();
   const double tol2 = (double)l * 0x1p-104;
   int rounds = 0, sweep = 0;
   bool conv = false;
-  for (; sweep < max_sweeps; ++sweep) {
+  for (; sweep < max_sweeps && !conv; ++sweep) {
     const int fl = sweep & 1;
-    for (int r = 0; r < L - 1; ++r, ++rounds) {
-      int p, q;
-      rr_pair(pair, r, L, p, q);
-      double x[kOsjMaxRows], y[kOsjMaxRows];
-      double a = 0.0, b = 0.0, c = 0.0;
+    for (int Q = P; Q >= 1; Q >>= 1) {
+      const int b = grp / Q, j = grp & (Q - 1);
+      for (int u = 0; u < Q; ++u, ++rounds) {
+        double a = 0.0, bb = 0.0, c = 0.0;
 #pragma unroll
-      for (int k = 0; k < kOsjMaxRows; ++k) {
-        const int i = t + (k << gl2);
-        const bool in = i < L;
-        x[k] = in ? S[i + p * L] : 0.0;
-        y[k] = in ? S[i + q * L] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < kOsjMaxRows; ++k) {
-        a = fma(x[k], x[k], a);
-        b = fma(y[k], y[k], b);
-        c = fma(x[k], y[k], c);
-      }
-      a = group_sum(a, gl2);
-      b = group_sum(b, gl2);
-      c = group_sum(c, gl2);
-      double cs, sn;
-      const bool rot = osj_rotation(a, b, c, tol2, cs, sn);
-      if (rot) {
-#pragma unroll
-        for (int k = 0; k < kOsjMaxRows; ++k) {
-          const int i = t + (k << gl2);
-          if (i < L) {
-            S[i + p * L] = cs * x[k] - sn * y[k];
-            S[i + q * L] = sn * x[k] + cs * y[k];
-          }
+        for (int k = 0; k < R; ++k) {
+          a = fma(x[k], x[k], a);
+          bb = fma(y[k], y[k], bb);
+          c = fma(x[k], y[k], c);
         }
-        if (t == 0) rotated[fl] = 1;
+        row16_sum3(a, bb, c);
+        double cs, sn;
+        if (osj_rotation(a, bb, c, tol2, cs, sn)) {
+#pragma unroll
+          for (int k = 0; k < R; ++k) {
+            const double xv = x[k], yv = y[k];
+            x[k] = cs * xv - sn * yv;
+            y[k] = sn * xv + cs * yv;
+          }
+          if (t == 0) rotated[fl] = 1;
+        }
+        if (t == 0) rlog[(size_t)rounds * P + grp] = make_double2(cs, sn);
+        if (u + 1 < Q) {
+          double* buf = S + (size_t)(rounds & 1) * P * LD;
+          const int dst = b * Q + ((j + Q - 1) & (Q - 1));
+#pragma unroll
+          for (int k = 0; k < R; ++k) buf[dst * LD + t + 16 * k] = y[k];
+          lds_barrier();
+#pragma unroll
+          for (int k = 0; k < R; ++k) y[k] = buf[grp * LD + t + 16 * k];
+        }
       }
-      if (t == 0) rlog[(size_t)rounds * npairs + pair] = make_double2(cs, sn);
+      // end of the level: every column to its place (after the last
+      // traveller reads), then the pairs of the next level
       lds_barrier();
+      const int pc = 2 * Q * b + j, qc = 2 * Q * b + Q + ((j + Q - 1) & (Q - 1));
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        S[pc * LD + t + 16 * k] = x[k];
+        S[qc * LD + t + 16 * k] = y[k];
+      }
+      lds_barrier();
+      if (Q == 1) conv = rotated[fl] == 0;  // every flag of the sweep is set by now
+      if (conv) break;                      // S holds the final matrix
+      const int Q1 = Q > 1 ? Q >> 1 : P;   // next level, or level 0 of the next sweep
+      const int b1 = grp / Q1, j1 = grp & (Q1 - 1);
+      const int pn = 2 * Q1 * b1 + j1, qn = pn + Q1;
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        x[k] = S[pn * LD + t + 16 * k];
+        y[k] = S[qn * LD + t + 16 * k];
+      }
+      lds_barrier();
+      if (Q == 1 && tid == 0) rotated[fl] = 0;  // read by all before the barrier above
     }
-    conv = rotated[fl] == 0;
-    lds_barrier();
-    if (tid == 0) rotated[fl] = 0;  // next read in sweep + 2, after more barriers
-    if (conv) break;
   }
   if (tid == 0) {
     // the sweep that found no rotation logged identities only
@@ -1065,23 +1140,19 @@ __global__ __launch_bounds__(kSmallThreads) void osj_kernel(int l, const double*
     if (!conv) or_status(status, RMM_STATUS_NOT_CONVERGED);
   }
   {
-    // column norms of the final M J (pairs of round 0 cover every column)
-    int p, q;
-    rr_pair(pair, 0, L, p, q);
-    double a = 0.0, b = 0.0;
+    // column norms of the final M J: group grp takes columns grp and P + grp
+    double a = 0.0, bb = 0.0, c = 0.0;
 #pragma unroll
-    for (int k = 0; k < kOsjMaxRows; ++k) {
-      const int i = t + (k << gl2);
-      const double xv = i < L ? S[i + p * L] : 0.0;
-      const double yv = i < L ? S[i + q * L] : 0.0;
+    for (int k = 0; k < R; ++k) {
+      const double xv = S[grp * LD + t + 16 * k];
+      const double yv = S[(P + grp) * LD + t + 16 * k];
       a = fma(xv, xv, a);
-      b = fma(yv, yv, b);
+      bb = fma(yv, yv, bb);
     }
-    a = group_sum(a, gl2);
-    b = group_sum(b, gl2);
+    row16_sum3(a, bb, c);
     if (t == 0) {
-      nrm[p] = sqrt(a);
-      nrm[q] = sqrt(b);
+      nrm[grp] = sqrt(a);
+      nrm[P + grp] = sqrt(bb);
     }
   }
   __syncthreads();
@@ -1098,11 +1169,11 @@ __global__ __launch_bounds__(kSmallThreads) void osj_kernel(int l, const double*
     sperm[rank] = tid;
   }
   __syncthreads();
-  for (int e = tid; e < l * l; e += blockDim.x) {
-    const int a = e % l, rank = e / l;
+  for (int e = tid; e < rows * l; e += blockDim.x) {
+    const int a = e % rows, rank = e / rows;
     const int j = sperm[rank];
     const double nj = nrm[j];
-    Ubar[a + (int64_t)rank * l] = nj > 0.0 ? S[a + j * L] / nj : 0.0;
+    Ubar[a + (int64_t)rank * rows] = nj > 0.0 ? S[j * LD + a] / nj : 0.0;
   }
 }
 
@@ -1227,7 +1298,7 @@ __global__ void osj_big_finish_kernel(int l, int L, const double* __restrict__ M
 }
 
 size_t jacobi_svd_workspace(int l) {
-  const int L = (l + 1) & ~1;
+  const int L = l <= kLdsMaxL ? pow2_ceil(l) : (l + 1) & ~1;
   Carver c(nullptr, 0);
   if (l <= kLdsMaxL) {
     c.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * (L / 2));
@@ -1285,37 +1356,74 @@ static int jacobi_svd_big(const rmm_ctx* h, int l, const double* M, int64_t ldm,
   return launch_status();
 }
 
+// Direct one-sided Jacobi on a tall X (rows <= 128, rows <= 2 L): every
+// round moves half the matrix through LDS, so beyond that the QR route is
+// cheaper.
+bool jacobi_svd_direct_ok(int64_t rows, int l) {
+  if (l > kLdsMaxL || rows < l) return false;
+  return rows <= kLdsMaxL && rows <= 2 * (int64_t)pow2_ceil(l);
+}
+
+template <typename TI, int R>
+static int osj_launch_r(const rmm_ctx* h, int rows, int l, const TI* M, int64_t ldm, double* sigma,
+                        int* perm, double* Ubar, double2* rlog, int* nr, int32_t* status) {
+  const int L = pow2_ceil(l);
+  const size_t lds = (size_t)L * (R == 1 ? 16 : 16 * R + 16) * sizeof(double);
+  RMM_HIP(hipFuncSetAttribute((const void*)osj_kernel<TI, R>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL((osj_kernel<TI, R>), dim3(1), dim3(L / 2 * 16), lds, h->stream, rows, l, M, ldm,
+                     sigma, perm, Ubar, rlog, nr, status, kJacobiMaxSweeps);
+  return launch_status();
+}
+
+template <typename TI>
+static int osj_launch(const rmm_ctx* h, int rows, int l, const TI* M, int64_t ldm, double* sigma,
+                      double* Ubar, double* J, int32_t* status, Carver& ws) {
+  const int L = pow2_ceil(l);
+  const int P = L / 2;
+  const size_t mark = ws.off;
+  double2* rlog = ws.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * P);
+  int* perm = ws.take<int>((size_t)l);
+  int* nr = ws.take<int>(1);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  if (rows <= 16)
+    RMM_TRY((osj_launch_r<TI, 1>(h, rows, l, M, ldm, sigma, perm, Ubar, rlog, nr, status)));
+  else if (rows <= 32)
+    RMM_TRY((osj_launch_r<TI, 2>(h, rows, l, M, ldm, sigma, perm, Ubar, rlog, nr, status)));
+  else if (rows <= 64)
+    RMM_TRY((osj_launch_r<TI, 4>(h, rows, l, M, ldm, sigma, perm, Ubar, rlog, nr, status)));
+  else
+    RMM_TRY((osj_launch_r<TI, 8>(h, rows, l, M, ldm, sigma, perm, Ubar, rlog, nr, status)));
+  const size_t vlds = (size_t)4 * kVecRows * L * sizeof(double) + 2 * (size_t)(L - 1) * P;
+  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
+  const int groups = (l + 4 * kVecRows - 1) / (4 * kVecRows);
+  hipLaunchKernelGGL(jacobi_vectors_kernel<true>, dim3(groups), dim3(256), vlds, h->stream, l, rlog,
+                     nr, perm, J);
+  ws.off = mark;
+  return launch_status();
+}
+
 int jacobi_svd(const rmm_ctx* h, int l, const double* M, int64_t ldm, double* sigma, double* Ubar,
                double* J, int32_t* status, Carver& ws) {
   if (l == 0) return RMM_OK;
   if (l > kBigMaxL) return RMM_ERR_UNSUPPORTED;
   if (l > kLdsMaxL) return jacobi_svd_big(h, l, M, ldm, sigma, Ubar, J, status, ws);
-  const int L = (l + 1) & ~1;
-  const int npairs = L / 2;
-  const size_t mark = ws.off;
-  double2* rlog = ws.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * npairs);
-  int* perm = ws.take<int>((size_t)l);
-  int* nr = ws.take<int>(1);
-  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
-  const size_t lds = (size_t)L * L * sizeof(double);
-  RMM_HIP(hipFuncSetAttribute((const void*)osj_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds));
-  // lanes per pair: the largest power of two with npairs * g <= 1024, at
-  // most 64 and at least 4 (the quad step of the butterfly)
-  int gl2 = 6;
-  while (gl2 > 2 && (npairs << gl2) > kSmallThreads) --gl2;
-  hipLaunchKernelGGL(osj_kernel, dim3(1), dim3(npairs << gl2), lds, h->stream, l, M, ldm, gl2, sigma,
-                     perm, Ubar, rlog, nr, status, kJacobiMaxSweeps);
-  RMM_TRY(launch_status());
-  const size_t vlds = (size_t)4 * kVecRows * L * sizeof(double) + 2 * (size_t)(L - 1) * npairs;
-  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
-  const int groups = (l + 4 * kVecRows - 1) / (4 * kVecRows);
-  hipLaunchKernelGGL(jacobi_vectors_kernel, dim3(groups), dim3(256), vlds, h->stream, l, rlog, nr,
-                     perm, J);
-  ws.off = mark;
-  return launch_status();
+  return osj_launch<double>(h, l, l, M, ldm, sigma, Ubar, J, status, ws);
 }
+
+template <typename TI>
+int jacobi_svd_direct(const rmm_ctx* h, int64_t rows, int l, const TI* X, int64_t ldx, double* sigma,
+                      double* Ux, double* J, int32_t* status, Carver& ws) {
+  if (l == 0) return RMM_OK;
+  if (!jacobi_svd_direct_ok(rows, l)) return RMM_ERR_UNSUPPORTED;
+  return osj_launch<TI>(h, (int)rows, l, X, ldx, sigma, Ux, J, status, ws);
+}
+
+template int jacobi_svd_direct<float>(const rmm_ctx*, int64_t, int, const float*, int64_t, double*,
+                                      double*, double*, int32_t*, Carver&);
+template int jacobi_svd_direct<double>(const rmm_ctx*, int64_t, int, const double*, int64_t, double*,
+                                       double*, double*, int32_t*, Carver&);
 
 // G_jj += c * trace(G) for the l x l matrix G (one workgroup): the shift of
 // the first pass of shifted CholeskyQR

@@ -61,8 +61,10 @@ def test_gaussian_values(h, dtype, stream, tag):
 
 # ---- sketch parity on small shapes -------------------------------------------
 
+# (2048, 512, 256): the sketches of the 2048 x 512 rsvd workload; (5000, 3, 6000):
+# SRHT with 4096 < s <= 8192 (the kernel's second sample-accumulator width)
 SHAPES = [(1, 1, 1), (7, 5, 2), (33, 3, 17), (1000, 5, 64), (5000, 64, 256), (70001, 9, 300),
-          (4096, 17, 4096), (12345, 2, 1)]
+          (4096, 17, 4096), (12345, 2, 1), (2048, 512, 256), (5000, 3, 6000)]
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])

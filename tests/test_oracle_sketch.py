@@ -228,3 +228,15 @@ def test_composite_rows_are_signed_rows_of_the_second_factor():
 def test_composite_rejects_countsketch_second_factor():
     with pytest.raises(ValueError):
         sk.composite_matrix(10, 4, 2, sk.COUNTSKETCH, 1)
+
+
+@pytest.mark.parametrize("kind", [sk.GAUSSIAN, sk.SRHT, sk.COUNTSKETCH])
+def test_sketch_matrix_row_blocks(kind):
+    """A block of rows of S built with global row indices is exactly that
+    block of the full matrix (what the row-blocked golden generator relies
+    on), for a ragged split of a non-power-of-two m."""
+    m, s, seed = 1000, 48, 17
+    full = sk.sketch_matrix(kind, m, s, seed, fp64=False)
+    parts = [sk.sketch_matrix(kind, m, s, seed, fp64=False, rows=np.arange(r0, min(r0 + 300, m)))
+             for r0 in range(0, m, 300)]
+    assert np.array_equal(np.vstack(parts), full)
