@@ -20,6 +20,9 @@ as plain, slow, obviously-correct numpy in float64:
 * ``nystrom``  - the RBF kernel (Sec. 6.1.1) and the Nystrom method (Sec. 6.4).
 * ``mixed``    - BF16 / FP8 rounding and the per-column-scaled quantized
                  products of the mixed-precision subspace iteration.
+* ``spsd``     - leverage scores and leverage-score sampling (Sec. 3.3.2), the
+                 faster SPSD sketching of Alg. 6.1 (Sec. 6.3) and the faster
+                 CUR decomposition (Sec. 6.6.3).
 
 Inputs reach the oracle as the exact bits the GPU path sees (float32 data is
 promoted exactly to float64).  Shared with the GPU path: nothing but the
@@ -28,4 +31,4 @@ arithmetic) and the written RNG contract, which both sides implement
 independently.
 """
 
-from . import rng, sketch, rsvd, lsr, nystrom, mixed  # noqa: F401
+from . import rng, sketch, rsvd, lsr, nystrom, mixed, spsd  # noqa: F401

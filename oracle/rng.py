@@ -53,6 +53,12 @@ TAG_GAUSS_SKETCH = 4
 TAG_GAUSS_RSVD = 5
 TAG_NYSTROM_SAMPLE = 6
 TAG_GAUSS_NYSTROM = 7
+TAG_SPSD_SAMPLE = 8
+TAG_LEVERAGE = 9
+TAG_CUR_COLS = 10
+TAG_CUR_ROWS = 11
+TAG_CUR_PC = 12
+TAG_CUR_PR = 13
 
 _M0 = np.uint64(0xD2511F53)
 _M1 = np.uint64(0xCD9E8D57)
@@ -236,3 +242,35 @@ def gaussian(rows, cols, tag: int, seed: int, fp64: bool):
 
 def gaussian_matrix(nrows: int, ncols: int, tag: int, seed: int, fp64: bool):
     return gaussian(np.arange(nrows), np.arange(ncols), tag, seed, fp64)
+
+
+def uniform_u64(j, tag: int, seed: int):
+    """64-bit uniform integers (w0 << 32 | w1) of philox(j, tag, 0), as Python ints."""
+    j = np.asarray(j, dtype=np.uint64)
+    lo, hi = _split64(j)
+    w0, w1, _, _ = philox4x32_10(lo, hi, tag, 0, seed)
+    return [(int(a) << 32) | int(b) for a, b in zip(w0.reshape(-1), w1.reshape(-1))]
+
+
+def weighted_sample(q, p: int, tag: int, seed: int):
+    """p indices of [0, n) drawn independently, with replacement, with
+    probability proportional to q_i >= 0 (randsample(n, p, true, q)).
+
+    Reading (the paper leaves the mechanics to MATLAB): the weights are
+    quantized to integers w_i = floor(q_i * 2^32 + 1/2) (q_i <= 1 for the
+    leverage scores of an orthonormal basis), so the cumulative sums are
+    exact integers; draw j takes the 64-bit uniform r_j of (j, tag) and the
+    target t_j = floor(r_j * W / 2^64), W = sum w_i, and returns the smallest
+    i with w_0 + ... + w_i > t_j.  Entries with w_i = 0 are never drawn.
+    """
+    q = np.asarray(q, dtype=np.float64)
+    w = np.floor(q * 2.0 ** 32 + 0.5).astype(np.int64)
+    if np.any(w < 0):
+        raise ValueError("weights must be non-negative")
+    cdf = np.cumsum(w)  # exact: every partial sum is below 2^63
+    W = int(cdf[-1])
+    if W <= 0:
+        raise ValueError("all weights are zero")
+    r = uniform_u64(np.arange(p), tag, seed)
+    t = np.array([(x * W) >> 64 for x in r], dtype=np.int64)
+    return np.searchsorted(cdf, t, side="right").astype(np.int64)
