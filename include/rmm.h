@@ -356,6 +356,64 @@ int rmm_nystrom_gaussian(rmm_handle h, int64_t n, int64_t d, const float* X,
                          float* C, int64_t ldc, float* L, int64_t ldl, double* evals,
                          int32_t* status);
 
+/* ---- faster SPSD sketching (Sec. 6.3, Alg. 6.1) of the RBF kernel ----------
+ * K_ij = exp(-||x_i - x_j||^2 / (2 sigma^2)) on the rows of X (n x d, dtype
+ * dt, row-major, ldx >= d, d <= 64, n <= 2^20), never formed:
+ *   S  (s int64, device): sorted uniform sample of [n] without replacement
+ *   C = K[:, S] (in dt), Q_C (n x s FP64, ldq >= n): its orthonormal basis
+ *      by shifted CholeskyQR (three passes)
+ *   q_i = ||Q_C[i, :]||^2 (the leverage scores of the columns of C^T,
+ *      Sec. 3.3.2); p draws with replacement with probability ~ q_i, by an
+ *      inverse CDF over the integer weights floor(q_i 2^32 + 1/2) (stream
+ *      seed, see rmm_leverage_sample)
+ *   P  (capacity p + s int64): unique([draws; S]), sorted, padded with -1;
+ *      *np (one int64, device) its length
+ *   Z (s x s FP64, ld s) = (Q_C[P, :])^+ K[P, P] ((Q_C[P, :])^+)^T, K[P, P]
+ *      in FP64, the pseudo-inverse from CholeskyQR2 of Q_C[P, :]
+ * so that K ~ Q_C Z Q_C^T.  status: RANK_DEFICIENT if Q_C[P, :] is
+ * numerically rank deficient (then Z uses a generalized inverse),
+ * QR_FALLBACK if C is.  Requires 1 <= s <= n, s <= 4096, 0 <= p <= 2^20. */
+int rmm_spsd_faster_workspace(rmm_handle h, rmm_dtype dt, int64_t n, int64_t d, int64_t s,
+                              int64_t p, size_t* bytes);
+int rmm_spsd_faster(rmm_handle h, rmm_dtype dt, int64_t n, int64_t d, const void* X, int64_t ldx,
+                    double sigma, int64_t s, int64_t p, uint64_t seed, int64_t* S, int64_t* P,
+                    int64_t* np, double* Qc, int64_t ldq, double* Z, int32_t* status);
+
+/* ---- faster CUR decomposition (Sec. 6.6.3) of the RBF kernel ------------------
+ * A = K(Xtest, Xtrain) (m x n; Xtest m x d and Xtrain n x d row-major, dtype
+ * dt, m, n <= 2^20, d <= 64), never formed:
+ *   SC (c of n) and SR (r of m): sorted uniform samples (int64, device)
+ *   C = A[:, SC] (m x c, dt, ldc >= m); Rt = A[SR, :]^T (n x r, dt,
+ *      ldrt >= n: R returned transposed, column-major)
+ *   P_C (capacity p_c + r) and P_R (capacity p_r + c): mode 0 (the curFaster
+ *      listing) draws p_c of m and p_r of n uniformly without replacement;
+ *      mode 1 (the remark) draws them with replacement by the leverage scores
+ *      of C^T and R (as rmm_spsd_faster does); then P_C = unique([P_C; SR]),
+ *      P_R = unique([P_R; SC]), sorted, padded with -1; lens[0], lens[1]
+ *      (int64, device) their lengths
+ *   U (c x r FP64, ldu >= c) = (C[P_C, :])^+ A[P_C, P_R] (R[:, P_R])^+, the
+ *      block A[P_C, P_R] in FP64, pseudo-inverses from CholeskyQR2
+ * so that A ~ C U R.  status as rmm_spsd_faster.  Requires 1 <= c <= n,
+ * 1 <= r <= m, c, r <= 4096; mode 0 needs p_c <= m, p_r <= n. */
+int rmm_cur_faster_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, int64_t d, int64_t c,
+                             int64_t r, int64_t pc, int64_t pr, int mode, size_t* bytes);
+int rmm_cur_faster(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, int64_t d, const void* Xtest,
+                   int64_t ldte, const void* Xtrain, int64_t ldtr, double sigma, int64_t c,
+                   int64_t r, int64_t pc, int64_t pr, int mode, uint64_t seed, int64_t* SC,
+                   int64_t* SR, int64_t* PC, int64_t* PR, int64_t* lens, void* C, int64_t ldc,
+                   double* U, int64_t ldu, void* Rt, int64_t ldrt, int32_t* status);
+
+/* Leverage-score sampling (Sec. 3.3.2), test hook: out[j] (j < p) is drawn
+ * with probability ~ q_i from q (n FP64 >= 0, device): weights w_i =
+ * floor(q_i 2^32 + 1/2), target t_j = floor(r_j W / 2^64) with r_j the 64-bit
+ * uniform (w0 << 32 | w1) of Philox at counter (j, tag, 0) and W = sum w_i,
+ * out[j] = the first i with w_0 + ... + w_i > t_j.  Integer arithmetic
+ * throughout, so the indices are exact.  Needs
+ * rmm_leverage_sample_workspace bytes of workspace. */
+int rmm_leverage_sample_workspace(rmm_handle h, int64_t n, size_t* bytes);
+int rmm_leverage_sample(rmm_handle h, int64_t n, const double* q, int64_t p, int32_t tag,
+                        uint64_t seed, int64_t* out);
+
 /* ---- mixed-precision product (test hook for the BF16 / FP8 passes of rsvd) --
  * A (m x n fp32, lda >= m) is quantized per column (scale = max |A_ij| / QMAX,
  * QMAX = 1 for BF16 and 448 for FP8 e4m3, round to nearest even) and the

@@ -86,6 +86,17 @@ def lib():
                          _vp, _i64, _vp, _vp, _i64, _vp],
             "rmm_lsr_workspace": [_vp, _i32, _i32, _i64, _i64, _i64, ctypes.POINTER(ctypes.c_size_t)],
             "rmm_sketched_lsr": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp, _vp, _vp],
+            "rmm_spsd_faster_workspace": [_vp, _i32, _i64, _i64, _i64, _i64,
+                                          ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_spsd_faster": [_vp, _i32, _i64, _i64, _vp, _i64, ctypes.c_double, _i64, _i64, _u64,
+                                _vp, _vp, _vp, _vp, _i64, _vp, _vp],
+            "rmm_cur_faster_workspace": [_vp, _i32, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _i32,
+                                         ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_cur_faster": [_vp, _i32, _i64, _i64, _i64, _vp, _i64, _vp, _i64, ctypes.c_double,
+                               _i64, _i64, _i64, _i64, _i32, _u64, _vp, _vp, _vp, _vp, _vp, _vp, _i64,
+                               _vp, _i64, _vp, _i64, _vp],
+            "rmm_leverage_sample_workspace": [_vp, _i64, ctypes.POINTER(ctypes.c_size_t)],
+            "rmm_leverage_sample": [_vp, _i64, _vp, _i64, _i32, _u64, _vp],
             "rmm_sketched_lsr_noalloc": [_vp, _i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _u64, _vp,
                                          _vp, _vp],
             "rmm_precise_lsr_workspace": [_vp, _i32, _i32, _i64, _i64, _i64,
@@ -554,6 +565,73 @@ class Handle:
                                  _ptr(C), _ld(C), _ptr(L), _ld(L), _ptr(evals), _ptr(status)),
                "rmm_nystrom")
         return L, idx, C, evals, status
+
+    def spsd_faster(self, X: torch.Tensor, sigma: float, s: int, p: int, seed: int):
+        """Alg. 6.1 on the RBF kernel of the rows of X (n x d, fp32 or fp64,
+        row-major).  Returns (Qc (n x s fp64), Z (s x s fp64), S (s), P
+        (sorted, P[:np]), status); K ~ Qc Z Qc^T."""
+        if X.dtype not in (torch.float32, torch.float64) or X.dim() != 2 or X.stride(1) != 1:
+            X = X.to(torch.float32).contiguous()
+        n, d = X.shape
+        dt = _dt(X)
+        S = torch.empty(s, dtype=torch.int64, device=X.device)
+        P = torch.empty(p + s, dtype=torch.int64, device=X.device)
+        npd = torch.empty(1, dtype=torch.int64, device=X.device)
+        Qc = torch.empty(s, n, dtype=torch.float64, device=X.device).t()
+        Z = torch.empty(s, s, dtype=torch.float64, device=X.device).t()
+        status = torch.zeros(1, dtype=torch.int32, device=X.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_spsd_faster_workspace(self._h, dt, n, d, s, p, ctypes.byref(ws)),
+               "rmm_spsd_faster_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_spsd_faster(self._h, dt, n, d, _ptr(X), X.stride(0), float(sigma), s, p, seed,
+                                     _ptr(S), _ptr(P), _ptr(npd), _ptr(Qc), _ld(Qc), _ptr(Z),
+                                     _ptr(status)), "rmm_spsd_faster")
+        return Qc, Z, S, P[:int(npd.item())], status
+
+    def cur_faster(self, Xtest: torch.Tensor, Xtrain: torch.Tensor, sigma: float, c: int, r: int,
+                   pc: int, pr: int, seed: int, mode: str = "uniform"):
+        """Faster CUR of the RBF kernel K(Xtest, Xtrain) (Sec. 6.6.3).  Returns
+        (C (m x c), U (c x r fp64), R (r x n), SC, SR, PC, PR, status)."""
+        dt0 = Xtest.dtype if Xtest.dtype in (torch.float32, torch.float64) else torch.float32
+        Xtest = Xtest.to(dt0).contiguous()
+        Xtrain = Xtrain.to(dt0).contiguous()
+        m, d = Xtest.shape
+        n = Xtrain.shape[0]
+        dt = _dt(Xtest)
+        md = {"uniform": 0, "leverage": 1}[mode]
+        dev = Xtest.device
+        SC = torch.empty(c, dtype=torch.int64, device=dev)
+        SR = torch.empty(r, dtype=torch.int64, device=dev)
+        PC = torch.empty(pc + r, dtype=torch.int64, device=dev)
+        PR = torch.empty(pr + c, dtype=torch.int64, device=dev)
+        lens = torch.empty(2, dtype=torch.int64, device=dev)
+        C = torch.empty(c, m, dtype=dt0, device=dev).t()
+        U = torch.empty(r, c, dtype=torch.float64, device=dev).t()
+        Rt = torch.empty(r, n, dtype=dt0, device=dev).t()
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_cur_faster_workspace(self._h, dt, m, n, d, c, r, pc, pr, md, ctypes.byref(ws)),
+               "rmm_cur_faster_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_cur_faster(self._h, dt, m, n, d, _ptr(Xtest), Xtest.stride(0), _ptr(Xtrain),
+                                    Xtrain.stride(0), float(sigma), c, r, pc, pr, md, seed, _ptr(SC),
+                                    _ptr(SR), _ptr(PC), _ptr(PR), _ptr(lens), _ptr(C), _ld(C), _ptr(U),
+                                    _ld(U), _ptr(Rt), _ld(Rt), _ptr(status)), "rmm_cur_faster")
+        ln = lens.tolist()
+        return C, U, Rt.t(), SC, SR, PC[:ln[0]], PR[:ln[1]], status
+
+    def leverage_sample(self, q: torch.Tensor, p: int, tag: int, seed: int):
+        """p indices drawn with probability ~ q (the sampler of Alg. 6.1)."""
+        q = q.to(torch.float64).contiguous()
+        out = torch.empty(p, dtype=torch.int64, device=q.device)
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_leverage_sample_workspace(self._h, q.numel(), ctypes.byref(ws)),
+               "rmm_leverage_sample_workspace")
+        self._prepare(ws.value)
+        _check(lib().rmm_leverage_sample(self._h, q.numel(), _ptr(q), p, tag, seed, _ptr(out)),
+               "rmm_leverage_sample")
+        return out
 
     def nystrom_gaussian(self, X: torch.Tensor, sigma: float, c: int, seed: int, k: int = None):
         """Gaussian-projection Nystrom: returns (L (n x k), C = K Omega (n x c), evals, status)."""

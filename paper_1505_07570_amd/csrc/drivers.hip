@@ -648,6 +648,199 @@ int rsvd_args(rmm_handle h, rmm_dtype dt, rmm_precision prec, int64_t m, int64_t
   return RMM_OK;
 }
 
+// ---- faster SPSD sketching (Sec. 6.3, Alg. 6.1) on the RBF kernel -----------------------
+//
+// S: s sorted uniform indices (stream TAG_SPSD_SAMPLE); C = K[:, S] in the
+// points' type; Q_C (n x s, FP64) by shifted CholeskyQR with three passes;
+// q = squared row norms of Q_C; p draws with replacement with probability
+// ~ q (TAG_LEVERAGE); P = unique([draws; S]) (length np <= p + s, stored
+// padded to pm = p + s); G = Q_C[P, :] (zero rows past np), K[P, P] in FP64
+// (zero past np); G = Q_G R_G by CholeskyQR2, G^+ = R_G^{-1} Q_G^T; Z~ =
+// G^+ K[P, P] G^+T = R_G^{-1} (Q_G^T K[P, P] Q_G) R_G^{-T}.
+template <typename T>
+int rbf_cols_any(rmm_ctx* h, int64_t n, int d, const T* X, int64_t ldx, int c, const int64_t* idx,
+                 const T* Y, int64_t ldy, double g, T* C, int64_t ldc) {
+  if constexpr (sizeof(T) == 4)
+    return launch_rbf(h, n, d, X, ldx, c, idx, Y, ldy, 0, g, C, ldc);
+  else
+    return rbf_cols_f64(h, n, d, X, ldx, c, idx, Y, ldy, g, C, ldc);
+}
+
+template <typename T>
+int spsd_impl(rmm_ctx* h, bool run, int64_t n, int d, const T* X, int64_t ldx, double sigma, int s,
+              int64_t p, uint64_t seed, int64_t* S, int64_t* P, int64_t* np, double* Qc, int64_t ldq,
+              double* Z, int32_t* status, size_t* bytes) {
+  const int64_t pm = p + s;
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  T* C = ws.take<T>((size_t)n * s);
+  OrthBufs ob = take_orth(ws, n, s);
+  double* q = ws.take<double>((size_t)n);
+  uint64_t* cdf = ws.take<uint64_t>((size_t)n);
+  int64_t* draws = ws.take<int64_t>((size_t)(p > 0 ? p : 1));
+  double* G = ws.take<double>((size_t)pm * s);
+  double* Kp = ws.take<double>((size_t)pm * pm);
+  LsBufs lb = take_ls(ws, pm, s);
+  double* Ri = ws.take<double>((size_t)s * s);
+  double* T1 = ws.take<double>((size_t)pm * s);
+  double* T2 = ws.take<double>((size_t)s * s);
+  double* T3 = ws.take<double>((size_t)s * s);
+  size_t scratch = orth_scratch<T>(h, n, s);
+  scratch = smax(scratch, ls_scratch(h, pm, s));
+  scratch = smax(scratch, gemm_workspace<double>(h, s, s, s));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)pm, s, pm));
+  scratch = smax(scratch, gemm_workspace<double>(h, s, s, pm));
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const double g = 1.0 / (2.0 * sigma * sigma);
+  RMM_TRY(zero_status(h, status));
+  RMM_TRY(launch_sample_indices_i64(h, (uint64_t)n, ceil_log2((uint64_t)n), s, TAG_SPSD_SAMPLE, seed, S));
+  RMM_TRY(rbf_cols_any<T>(h, n, d, X, ldx, s, S, X, ldx, g, C, n));
+  RMM_TRY((orth<T, double>(h, n, s, C, n, Qc, ldq, ob, 64.0 * kEps * (double)(n > s ? n : s), status,
+                           ws, 3)));
+  RMM_TRY(leverage_scores(h, n, s, Qc, ldq, q));
+  RMM_TRY(weighted_sample(h, n, q, p, TAG_LEVERAGE, seed, cdf, draws));
+  RMM_TRY(union_sorted(h, n, draws, p, S, s, pm, P, np));
+  RMM_TRY(gather_rows<double>(h, pm, s, P, np, Qc, ldq, G));
+  RMM_TRY(rbf_block_f64<T>(h, d, X, ldx, P, np, pm, X, ldx, P, np, pm, g, Kp));
+  RMM_TRY(cholqr2(h, pm, s, G, lb, ws));
+  RMM_TRY(rank_check(h, s, lb.d1, lb.d2, 10.0 * (double)pm * kEps, status));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, s, s, s, lb.R1, s, lb.R2, s, 1.0, Ri,
+                                                s, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, (int)pm, s, pm, Kp, pm, lb.Q, pm, 1.0,
+                                                T1, pm, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, s, s, pm, lb.Q, pm, T1, pm, 1.0, T2, s,
+                                                ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, s, s, s, Ri, s, T2, s, 1.0, T3, s, ws)));
+  return gemm<double, double, double, double>(h, false, true, s, s, s, T3, s, Ri, s, 1.0, Z, s, ws);
+}
+
+// ---- faster CUR (Sec. 6.6.3) of the RBF kernel A = K(Xtest, Xtrain) ---------------------
+//
+// SC: c of the n training points, SR: r of the m test points (sorted
+// uniform, TAG_CUR_COLS / TAG_CUR_ROWS); C = A[:, SC] (m x c), R^T =
+// A[SR, :]^T (n x r), both in the points' type; P_C (p_c of m, TAG_CUR_PC)
+// and P_R (p_r of n, TAG_CUR_PR) uniform without replacement (the
+// listing) or by the leverage scores of C and R^T with replacement (the
+// remark), joined with SR and SC; U = (C[P_C, :])^+ A[P_C, P_R]
+// (R[:, P_R])^+ with both pseudo-inverses from CholeskyQR2 of the gathered
+// tall blocks: (C[P_C, :])^+ = R_a^{-1} Q_a^T and (R[:, P_R])^+ =
+// ((R^T)[P_R, :])^{+T} = Q_b R_b^{-T}.
+template <typename T>
+int cur_impl(rmm_ctx* h, bool run, int64_t m, int64_t n, int d, const T* Xte, int64_t ldte,
+             const T* Xtr, int64_t ldtr, double sigma, int c, int r, int64_t pc, int64_t pr, int mode,
+             uint64_t seed, int64_t* SC, int64_t* SR, int64_t* PC, int64_t* PR, int64_t* lens, T* C,
+             int64_t ldc, double* U, int64_t ldu, T* Rt, int64_t ldrt, int32_t* status, size_t* bytes) {
+  const int64_t pcm = pc + r, prm = pr + c;
+  const int64_t big = m * c > n * r ? m * c : n * r;
+  Carver ws(run ? h->ws : nullptr, run ? h->ws_bytes : 0);
+  int64_t* dC = ws.take<int64_t>((size_t)(pc > 0 ? pc : 1));
+  int64_t* dR = ws.take<int64_t>((size_t)(pr > 0 ? pr : 1));
+  double* Gc = ws.take<double>((size_t)pcm * c);
+  double* Gr = ws.take<double>((size_t)prm * r);
+  double* Ab = ws.take<double>((size_t)pcm * prm);
+  LsBufs la = take_ls(ws, pcm, c);
+  LsBufs lr = take_ls(ws, prm, r);
+  double* Ria = ws.take<double>((size_t)c * c);
+  double* Rib = ws.take<double>((size_t)r * r);
+  double* T1 = ws.take<double>((size_t)pcm * r);
+  double* T2 = ws.take<double>((size_t)c * r);
+  double* T3 = ws.take<double>((size_t)c * r);
+  double *Qb = nullptr, *q = nullptr;
+  uint64_t* cdf = nullptr;
+  OrthBufs ob{};
+  const int kmax = c > r ? c : r;
+  if (mode == 1) {
+    Qb = ws.take<double>((size_t)big);
+    q = ws.take<double>((size_t)(m > n ? m : n));
+    cdf = ws.take<uint64_t>((size_t)(m > n ? m : n));
+    ob.G = ws.take<double>((size_t)kmax * kmax);
+    ob.Rinv = ws.take<double>((size_t)kmax * kmax);
+    ob.diag = ws.take<double>((size_t)kmax);
+    ob.Xd = ws.take<double>((size_t)big);
+    ob.Xd2 = ws.take<double>((size_t)big);
+  }
+  size_t scratch = ls_scratch(h, pcm, c);
+  scratch = smax(scratch, ls_scratch(h, prm, r));
+  scratch = smax(scratch, gemm_workspace<double>(h, c, c, c));
+  scratch = smax(scratch, gemm_workspace<double>(h, r, r, r));
+  scratch = smax(scratch, gemm_workspace<double>(h, (int)pcm, r, prm));
+  scratch = smax(scratch, gemm_workspace<double>(h, c, r, pcm));
+  scratch = smax(scratch, gemm_workspace<double>(h, c, r, c));
+  scratch = smax(scratch, gemm_workspace<double>(h, c, r, r));
+  if (mode == 1) {
+    scratch = smax(scratch, orth_scratch<T>(h, m, c));
+    scratch = smax(scratch, orth_scratch<T>(h, n, r));
+  }
+  if (!run) {
+    *bytes = ws.off + scratch + 8 * kAlign;
+    return RMM_OK;
+  }
+  if (ws.off + scratch + 8 * kAlign > ws.cap) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  const double g = 1.0 / (2.0 * sigma * sigma);
+  RMM_TRY(zero_status(h, status));
+  RMM_TRY(launch_sample_indices_i64(h, (uint64_t)n, ceil_log2((uint64_t)n), c, TAG_CUR_COLS, seed, SC));
+  RMM_TRY(launch_sample_indices_i64(h, (uint64_t)m, ceil_log2((uint64_t)m), r, TAG_CUR_ROWS, seed, SR));
+  RMM_TRY(rbf_cols_any<T>(h, m, d, Xte, ldte, c, SC, Xtr, ldtr, g, C, ldc));
+  RMM_TRY(rbf_cols_any<T>(h, n, d, Xtr, ldtr, r, SR, Xte, ldte, g, Rt, ldrt));
+  if (mode == 0) {
+    RMM_TRY(launch_sample_indices_i64(h, (uint64_t)m, ceil_log2((uint64_t)m), pc, TAG_CUR_PC, seed, dC));
+    RMM_TRY(launch_sample_indices_i64(h, (uint64_t)n, ceil_log2((uint64_t)n), pr, TAG_CUR_PR, seed, dR));
+  } else {
+    RMM_TRY((orth<T, double>(h, m, c, C, ldc, Qb, m, ob, 64.0 * kEps * (double)(m > c ? m : c), status,
+                             ws, 3)));
+    RMM_TRY(leverage_scores(h, m, c, Qb, m, q));
+    RMM_TRY(weighted_sample(h, m, q, pc, TAG_CUR_PC, seed, cdf, dC));
+    RMM_TRY((orth<T, double>(h, n, r, Rt, ldrt, Qb, n, ob, 64.0 * kEps * (double)(n > r ? n : r),
+                             status, ws, 3)));
+    RMM_TRY(leverage_scores(h, n, r, Qb, n, q));
+    RMM_TRY(weighted_sample(h, n, q, pr, TAG_CUR_PR, seed, cdf, dR));
+  }
+  RMM_TRY(union_sorted(h, m, dC, pc, SR, r, pcm, PC, lens));
+  RMM_TRY(union_sorted(h, n, dR, pr, SC, c, prm, PR, lens + 1));
+  RMM_TRY(gather_rows<T>(h, pcm, c, PC, lens, C, ldc, Gc));
+  RMM_TRY(gather_rows<T>(h, prm, r, PR, lens + 1, Rt, ldrt, Gr));
+  RMM_TRY(rbf_block_f64<T>(h, d, Xte, ldte, PC, lens, pcm, Xtr, ldtr, PR, lens + 1, prm, g, Ab));
+  RMM_TRY(cholqr2(h, pcm, c, Gc, la, ws));
+  RMM_TRY(rank_check(h, c, la.d1, la.d2, 10.0 * (double)pcm * kEps, status));
+  RMM_TRY(cholqr2(h, prm, r, Gr, lr, ws));
+  RMM_TRY(rank_check(h, r, lr.d1, lr.d2, 10.0 * (double)prm * kEps, status));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, c, c, c, la.R1, c, la.R2, c, 1.0, Ria,
+                                                c, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, r, r, r, lr.R1, r, lr.R2, r, 1.0, Rib,
+                                                r, ws)));
+  // U = R_a^{-1} Q_a^T A[P_C, P_R] Q_b R_b^{-T}
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, (int)pcm, r, prm, Ab, pcm, lr.Q, prm,
+                                                1.0, T1, pcm, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, true, false, c, r, pcm, la.Q, pcm, T1, pcm, 1.0, T2,
+                                                c, ws)));
+  RMM_TRY((gemm<double, double, double, double>(h, false, false, c, r, c, Ria, c, T2, c, 1.0, T3, c,
+                                                ws)));
+  return gemm<double, double, double, double>(h, false, true, c, r, r, T3, c, Rib, r, 1.0, U, ldu, ws);
+}
+
+int spsd_args(rmm_handle h, rmm_dtype dt, int64_t n, int64_t d, double sigma, int64_t s, int64_t p) {
+  if (!h || !dt_ok(dt) || n < 1 || d < 1 || s < 1 || s > n || p < 0 || !(sigma > 0.0) ||
+      !(sigma < 1e300))
+    return RMM_ERR_INVALID_ARG;
+  if (n > kUnionMaxDomain || s > 4096 || p > (1 << 20) || d > 64) return RMM_ERR_UNSUPPORTED;
+  return RMM_OK;
+}
+
+int cur_args(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, int64_t d, double sigma, int64_t c,
+             int64_t r, int64_t pc, int64_t pr, int mode) {
+  if (!h || !dt_ok(dt) || m < 1 || n < 1 || d < 1 || c < 1 || r < 1 || c > n || r > m || pc < 0 ||
+      pr < 0 || !(sigma > 0.0) || !(sigma < 1e300) || (mode != 0 && mode != 1))
+    return RMM_ERR_INVALID_ARG;
+  if (mode == 0 && (pc > m || pr > n)) return RMM_ERR_INVALID_ARG;  // without replacement
+  if (m > kUnionMaxDomain || n > kUnionMaxDomain || c > 4096 || r > 4096 || pc > (1 << 20) ||
+      pr > (1 << 20) || d > 64)
+    return RMM_ERR_UNSUPPORTED;
+  return RMM_OK;
+}
+
 int lsr_args(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d, int64_t s) {
   if (!h || !dt_ok(dt) || m < 1 || d < 1 || s < d || d > m) return RMM_ERR_INVALID_ARG;
   if (d > 4096 || s >= (1ll << 30) || m >= (1ll << 31)) return RMM_ERR_UNSUPPORTED;
@@ -860,6 +1053,81 @@ int rmm_plain_lsr(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d, const void* 
                              status, nullptr);
   return plain_impl<double>(h, true, m, (int)d, (const double*)A, lda, (const double*)b, x, resid,
                             status, nullptr);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int rmm_spsd_faster_workspace(rmm_handle h, rmm_dtype dt, int64_t n, int64_t d, int64_t s,
+                              int64_t p, size_t* bytes) {
+  RMM_TRY(spsd_args(h, dt, n, d, 1.0, s, p));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return spsd_impl<float>(h, false, n, (int)d, nullptr, d, 1.0, (int)s, p, 0, nullptr, nullptr,
+                            nullptr, nullptr, n, nullptr, nullptr, bytes);
+  return spsd_impl<double>(h, false, n, (int)d, nullptr, d, 1.0, (int)s, p, 0, nullptr, nullptr,
+                           nullptr, nullptr, n, nullptr, nullptr, bytes);
+}
+
+int rmm_spsd_faster(rmm_handle h, rmm_dtype dt, int64_t n, int64_t d, const void* X, int64_t ldx,
+                    double sigma, int64_t s, int64_t p, uint64_t seed, int64_t* S, int64_t* P,
+                    int64_t* np, double* Qc, int64_t ldq, double* Z, int32_t* status) {
+  RMM_TRY(spsd_args(h, dt, n, d, sigma, s, p));
+  if (!X || !S || !P || !np || !Qc || !Z || ldx < d || ldq < n) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return spsd_impl<float>(h, true, n, (int)d, (const float*)X, ldx, sigma, (int)s, p, seed, S, P, np,
+                            Qc, ldq, Z, status, nullptr);
+  return spsd_impl<double>(h, true, n, (int)d, (const double*)X, ldx, sigma, (int)s, p, seed, S, P, np,
+                           Qc, ldq, Z, status, nullptr);
+}
+
+int rmm_cur_faster_workspace(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, int64_t d, int64_t c,
+                             int64_t r, int64_t pc, int64_t pr, int mode, size_t* bytes) {
+  RMM_TRY(cur_args(h, dt, m, n, d, 1.0, c, r, pc, pr, mode));
+  if (!bytes) return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return cur_impl<float>(h, false, m, n, (int)d, nullptr, d, nullptr, d, 1.0, (int)c, (int)r, pc, pr,
+                           mode, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, m, nullptr,
+                           c, nullptr, n, nullptr, bytes);
+  return cur_impl<double>(h, false, m, n, (int)d, nullptr, d, nullptr, d, 1.0, (int)c, (int)r, pc, pr,
+                          mode, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, m, nullptr, c,
+                          nullptr, n, nullptr, bytes);
+}
+
+int rmm_cur_faster(rmm_handle h, rmm_dtype dt, int64_t m, int64_t n, int64_t d, const void* Xtest,
+                   int64_t ldte, const void* Xtrain, int64_t ldtr, double sigma, int64_t c,
+                   int64_t r, int64_t pc, int64_t pr, int mode, uint64_t seed, int64_t* SC,
+                   int64_t* SR, int64_t* PC, int64_t* PR, int64_t* lens, void* C, int64_t ldc,
+                   double* U, int64_t ldu, void* Rt, int64_t ldrt, int32_t* status) {
+  RMM_TRY(cur_args(h, dt, m, n, d, sigma, c, r, pc, pr, mode));
+  if (!Xtest || !Xtrain || !SC || !SR || !PC || !PR || !lens || !C || !U || !Rt || ldte < d ||
+      ldtr < d || ldc < m || ldu < c || ldrt < n)
+    return RMM_ERR_INVALID_ARG;
+  if (dt == RMM_F32)
+    return cur_impl<float>(h, true, m, n, (int)d, (const float*)Xtest, ldte, (const float*)Xtrain, ldtr,
+                           sigma, (int)c, (int)r, pc, pr, mode, seed, SC, SR, PC, PR, lens, (float*)C,
+                           ldc, U, ldu, (float*)Rt, ldrt, status, nullptr);
+  return cur_impl<double>(h, true, m, n, (int)d, (const double*)Xtest, ldte, (const double*)Xtrain,
+                          ldtr, sigma, (int)c, (int)r, pc, pr, mode, seed, SC, SR, PC, PR, lens,
+                          (double*)C, ldc, U, ldu, (double*)Rt, ldrt, status, nullptr);
+}
+
+int rmm_leverage_sample_workspace(rmm_handle h, int64_t n, size_t* bytes) {
+  if (!h || !bytes || n < 1) return RMM_ERR_INVALID_ARG;
+  Carver c(nullptr, 0);
+  c.take<uint64_t>((size_t)n);
+  *bytes = c.off + kAlign;
+  return RMM_OK;
+}
+
+int rmm_leverage_sample(rmm_handle h, int64_t n, const double* q, int64_t p, int32_t tag,
+                        uint64_t seed, int64_t* out) {
+  if (!h || !q || !out || n < 1 || p < 0 || tag < 0) return RMM_ERR_INVALID_ARG;
+  Carver ws(h->ws, h->ws_bytes);
+  uint64_t* cdf = ws.take<uint64_t>((size_t)n);
+  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
+  return weighted_sample(h, n, q, p, (uint32_t)tag, seed, cdf, out);
 }
 
 }  // extern "C"

@@ -30,7 +30,8 @@ constexpr int kRbfMaxD = 64;   // point dimension held in registers
 template <int D>
 __global__ __launch_bounds__(kRbfRows) void rbf_columns_kernel(int64_t n, int d, const float* __restrict__ X,
                                                                int64_t ldx, int c, const int64_t* __restrict__ idx,
-                                                               const float* __restrict__ Y, int64_t col_base,
+                                                               const float* __restrict__ Y, int64_t ldy,
+                                                               int64_t col_base,
                                                                float g, float* __restrict__ C, int64_t ldc) {
   __shared__ __align__(16) float ys[D][kRbfCols];
   __shared__ float xs[kRbfRows][D + 1];
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(kRbfRows) void rbf_columns_kernel(int64_t n, int d,
       const int jj = e / D, k = e % D;
       const int j = j0 + jj;
       const int64_t pt = idx ? idx[j < c ? j : 0] : col_base + j;  // sampled or contiguous points
-      ys[k][jj] = (j < c && k < d) ? Y[pt * ldx + k] : 0.0f;
+      ys[k][jj] = (j < c && k < d) ? Y[pt * ldy + k] : 0.0f;
     }
     __syncthreads();
     const int jn = (c - j0) < kRbfCols ? (c - j0) : kRbfCols;
@@ -103,19 +104,21 @@ __global__ void nystrom_scale_kernel(int c, int k, const double* __restrict__ la
   F[a + (int64_t)t * c] = (l > cut && l > 0.0) ? V[a + (int64_t)t * c] / sqrt(l) : 0.0;
 }
 
-namespace {
-
 int launch_rbf(const rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, int c,
-               const int64_t* idx, const float* Y, int64_t col_base, double g, float* C, int64_t ldc) {
+               const int64_t* idx, const float* Y, int64_t ldy, int64_t col_base, double g, float* C,
+               int64_t ldc) {
+  if (n == 0 || c == 0) return RMM_OK;
   const unsigned blocks = (unsigned)((n + kRbfRows - 1) / kRbfRows);
   if (d <= 32)
     hipLaunchKernelGGL(rbf_columns_kernel<32>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n, d, X,
-                       ldx, c, idx, Y, col_base, (float)g, C, ldc);
+                       ldx, c, idx, Y, ldy, col_base, (float)g, C, ldc);
   else
     hipLaunchKernelGGL(rbf_columns_kernel<kRbfMaxD>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n,
-                       d, X, ldx, c, idx, Y, col_base, (float)g, C, ldc);
+                       d, X, ldx, c, idx, Y, ldy, col_base, (float)g, C, ldc);
   return launch_status();
 }
+
+namespace {
 
 struct NysBufs {
   double* W;
@@ -153,7 +156,7 @@ int nystrom_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, doubl
   RMM_TRY(launch_sample_indices_i64(h, (uint64_t)n, ceil_log2((uint64_t)n), c, TAG_NYSTROM_SAMPLE,
                                     seed, idx));
   const double g = 1.0 / (2.0 * sigma * sigma);
-  RMM_TRY(launch_rbf(h, n, d, X, ldx, c, idx, X, 0, g, C, ldc));
+  RMM_TRY(launch_rbf(h, n, d, X, ldx, c, idx, X, ldx, 0, g, C, ldc));
   hipLaunchKernelGGL(rbf_gram_f64_kernel, dim3((unsigned)((c + 127) / 128), (unsigned)c), dim3(128), 0,
                      h->stream, d, X, ldx, c, idx, g, b.W);
   RMM_TRY(launch_status());
@@ -220,7 +223,7 @@ int nystrom_gauss_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx,
     for (int64_t l0 = 0; l0 < n; l0 += bc) {
       const int64_t cols = (n - l0) < bc ? (n - l0) : bc;
       // K[i0:i0+rows, l0:l0+cols] (rows x cols, ld rows)
-      RMM_TRY(launch_rbf(h, rows, d, X + i0 * ldx, ldx, (int)cols, nullptr, X, l0, g, Kt, rows));
+      RMM_TRY(launch_rbf(h, rows, d, X + i0 * ldx, ldx, (int)cols, nullptr, X, ldx, l0, g, Kt, rows));
       // C[i0:, :] (+)= K_tile Omega[l0:l0+cols, :]
       RMM_TRY((gemm<float, float, float, float>(h, false, false, (int)rows, c, cols, Kt, rows, Om + l0, n,
                                                 1.0, C + i0, ldc, ws, l0 == 0 ? 0.0 : 1.0)));

@@ -65,6 +65,30 @@ int pcg_step(const rmm_ctx* h, int d, const double* part, const double* M, doubl
              double* y, double* p, double* sc);
 int pass_resid(const rmm_ctx* h, int d, const double* part, double* out);
 
+// Leverage-score sampling and the index/gather kernels of the faster SPSD
+// sketching and CUR (spsd.hip).
+constexpr int64_t kUnionMaxDomain = 1 << 20;  // domain of union_sorted (LDS bitmap)
+int leverage_scores(const rmm_ctx* h, int64_t n, int k, const double* Q, int64_t ldq, double* q);
+// p draws with replacement, probability ~ q_i (cdf: n uint64 of workspace)
+int weighted_sample(const rmm_ctx* h, int64_t n, const double* q, int64_t p, uint32_t tag,
+                    uint64_t seed, uint64_t* cdf, int64_t* out);
+// out[0:cap] = sorted unique(a u b) padded with -1, *len = its length
+int union_sorted(const rmm_ctx* h, int64_t n, const int64_t* a, int64_t na, const int64_t* b,
+                 int64_t nb, int64_t cap, int64_t* out, int64_t* len);
+template <typename T>
+int gather_rows(const rmm_ctx* h, int64_t pm, int k, const int64_t* P, const int64_t* np, const T* X,
+                int64_t ldx, double* G);
+template <typename T>
+int rbf_block_f64(const rmm_ctx* h, int d, const T* X, int64_t ldx, const int64_t* A,
+                  const int64_t* na, int64_t ma, const T* Y, int64_t ldy, const int64_t* B,
+                  const int64_t* nb, int64_t mb, double g, double* K);
+int rbf_cols_f64(const rmm_ctx* h, int64_t n, int d, const double* X, int64_t ldx, int c,
+                 const int64_t* idx, const double* Y, int64_t ldy, double g, double* C, int64_t ldc);
+// RBF columns in FP32 (nystrom.hip): C[:, j] = K(X rows, point idx[j] of Y)
+int launch_rbf(const rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, int c,
+               const int64_t* idx, const float* Y, int64_t ldy, int64_t col_base, double g, float* C,
+               int64_t ldc);
+
 // Device address of the static scratch array of rmm_sketched_lsr_noalloc on
 // `device` (looked up once per device; null when the lookup failed).
 void* noalloc_scratch(int device);

@@ -31,6 +31,12 @@ enum : uint32_t {
   TAG_GAUSS_RSVD = 5,
   TAG_NYSTROM_SAMPLE = 6,
   TAG_GAUSS_NYSTROM = 7,
+  TAG_SPSD_SAMPLE = 8,
+  TAG_LEVERAGE = 9,
+  TAG_CUR_COLS = 10,
+  TAG_CUR_ROWS = 11,
+  TAG_CUR_PC = 12,
+  TAG_CUR_PR = 13,
 };
 
 struct Words4 {
