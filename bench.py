@@ -318,6 +318,53 @@ def nystrom_leg(h, reps):
         "ms": ms, "status": int(stg.item()),
         "rel_err_LLt_vs_K_sampled_1e6": float(torch.linalg.vector_norm(K - Ag) / torch.linalg.vector_norm(K)),
         "mfma_tflops": 2.0 * n * n * c / (ms * 1e-3) / 1e12}
+    del Lg, Cg
+    # faster SPSD sketching (Alg. 6.1) on the same points: s = 1024 uniform
+    # columns, p = 4 s leverage-score draws joined with S; error of
+    # Q_C Z Q_C^T on the same sampled entries
+    s_, p_ = 1024, 4096
+    h.spsd_faster(Xd, sigma, s_, p_, synth.sketch_seed(4))
+    ts = []
+    for _ in range(reps):
+        a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        Qc, Z, S, P, st = h.spsd_faster(Xd, sigma, s_, p_, synth.sketch_seed(4))
+        z.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(z))
+    As = ((Qc[i] @ Z) * Qc[j]).sum(1)
+    out["spsd_faster"] = {"s": s_, "p": p_, "P_len": int(P.numel()), "p50_ms": serve.percentile(ts, 50),
+                          "status": int(st.item()),
+                          "rel_err_vs_K_sampled_1e6": float(torch.linalg.vector_norm(K - As) /
+                                                            torch.linalg.vector_norm(K))}
+    del Qc, Z
+    # faster CUR (Sec. 6.6.3) of K(Xtest, Xtrain): the first 20,000 points as
+    # test points, the other 180,000 as training points; c = r = 512,
+    # p_c = p_r = 2 (c + r) as in the listing; uniform and leverage P_C, P_R
+    mt = 20000
+    Xte, Xtr = Xd[:mt], Xd[mt:]
+    ci = torch.from_numpy(g.integers(0, mt, 10 ** 6)).cuda()
+    cj = torch.from_numpy(g.integers(0, n - mt, 10 ** 6)).cuda()
+    Kc = torch.exp(-((Xte[ci].double() - Xtr[cj].double()) ** 2).sum(1) / (2 * sigma * sigma))
+    cc = rr = 512
+    pcr = 2 * (cc + rr)
+    out["cur_faster"] = {"m": mt, "n": n - mt, "c": cc, "r": rr, "p_c": pcr, "p_r": pcr}
+    for mode in ("uniform", "leverage"):
+        h.cur_faster(Xte, Xtr, sigma, cc, rr, pcr, pcr, synth.sketch_seed(4), mode)
+        ts = []
+        for _ in range(reps):
+            a, z = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            C, U, R, SC, SR, PC, PR, st = h.cur_faster(Xte, Xtr, sigma, cc, rr, pcr, pcr,
+                                                       synth.sketch_seed(4), mode)
+            z.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(z))
+        Ac = ((C[ci].double() @ U) * R.t()[cj].double()).sum(1)
+        out["cur_faster"][mode] = {"p50_ms": serve.percentile(ts, 50), "status": int(st.item()),
+                                   "rel_err_vs_K_sampled_1e6": float(torch.linalg.vector_norm(Kc - Ac) /
+                                                                     torch.linalg.vector_norm(Kc))}
+        del C, U, R
     return out
 
 
@@ -388,8 +435,10 @@ def main():
         print(json.dumps({"rsvd_65536x8192": rsvd_spectrum(h, args.rsvd_reps, lat)}), flush=True)
         return
     if args.only_extras:
-        print(json.dumps({"nystrom_200000x32_c1024": nystrom_leg(h, args.rsvd_reps),
-                          "serving": serving_leg(args.serve_requests)}), flush=True)
+        ex = {"nystrom_200000x32_c1024": nystrom_leg(h, args.rsvd_reps)}
+        if args.serve_requests > 0:
+            ex["serving"] = serving_leg(args.serve_requests)
+        print(json.dumps(ex), flush=True)
         return
 
     kinds = [k.strip() for k in args.kinds.split(",") if k.strip()]
