@@ -233,14 +233,16 @@ def rsvd_spectrum(h, reps, lat):
     return out
 
 
-def serving_leg(count, budget_scale=1.0):
+def serving_leg(count, factors=(1.0,)):
     """Serving workload: `count` requests (half rsvd, half CountSketch LSR,
     m log-uniform in [4096, 262144], n in [32, 512], matrices generated on
-    the device from per-request seeds).  First the plain comparator (one
-    request at a time, same library calls) with all requests arriving at
-    once gives the saturation throughput; then both are run with Poisson
-    arrivals at that rate.  The memory budget is 200 GB scaled by
-    count / 10000 (the share of a 10,000-request run)."""
+    the device from per-request seeds, inside both paths' latency).  First
+    the plain comparator (one request at a time, same library calls) with
+    all requests arriving at once gives its saturation throughput; then both
+    are run with Poisson arrivals at each factor times that rate.  The memory
+    budget is 200 GB scaled by count / 10000 (the share of a 10,000-request
+    run); it covers the server's stream workspaces (reserved at start) and
+    the admitted requests.  Results leave the device as they complete."""
     import numpy as np
 
     import synth
@@ -252,15 +254,16 @@ def serving_leg(count, budget_scale=1.0):
     for q in reqs[:4]:
         A, b = make(q)
         serve._solve_one(h0, q, A, b)
+    del h0
     import torch
     torch.cuda.synchronize()
-    _, _, wall_sat = serve.run_plain(reqs, np.zeros(count), make)
+
+    def drop(rid, o):
+        pass
+
+    _, _, wall_sat = serve.run_plain(reqs, np.zeros(count), make, on_done=drop)
     rate = count / wall_sat
-    arrivals = synth.poisson_arrivals(count, rate)
-    _, lat_p, wall_p = serve.run_plain(reqs, arrivals, make)
-    budget = int(200e9 * count / 10000 * budget_scale)
-    srv = serve.Server(budget, streams=4)
-    _, lat_s, wall_s = srv.run(reqs, arrivals, make)
+    budget = int(200e9 * count / 10000)
     req_bytes = sum(4 * q["m"] * q["n"] for q in reqs)
 
     def summary(lat, wall):
@@ -268,10 +271,20 @@ def serving_leg(count, budget_scale=1.0):
         return {"p50_ms": serve.percentile(v, 50), "p99_ms": serve.percentile(v, 99),
                 "solves_per_s": len(v) / wall, "hbm_gbs_of_A": req_bytes / wall / 1e9}
 
-    return {"requests": count, "arrival_rate_per_s": rate, "budget_bytes": budget,
-            "peak_admitted_bytes": srv.peak_bytes, "rejected": len(srv.rejected),
-            "plain_one_at_a_time": summary(lat_p, wall_p), "served": summary(lat_s, wall_s),
-            "saturation_solves_per_s_plain": rate}
+    out = {"requests": count, "saturation_solves_per_s_plain": rate, "budget_bytes": budget,
+           "latency_includes": "on-device generation of each request's matrix", "by_arrival_rate": {}}
+    for f in factors:
+        arrivals = synth.poisson_arrivals(count, f * rate)
+        _, lat_p, wall_p = serve.run_plain(reqs, arrivals, make, on_done=drop)
+        srv = serve.Server(budget, streams=4)
+        _, lat_s, wall_s = srv.run(reqs, arrivals, make, on_done=drop)
+        out["by_arrival_rate"][f"{f:g}x"] = {
+            "arrival_rate_per_s": f * rate, "plain_one_at_a_time": summary(lat_p, wall_p),
+            "served": summary(lat_s, wall_s), "peak_admitted_bytes": srv.peak_bytes,
+            "reserved_workspace_bytes": srv.reserved, "rejected": len(srv.rejected)}
+        del srv
+        torch.cuda.empty_cache()
+    return out
 
 
 def nystrom_leg(h, reps):
@@ -379,7 +392,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip latency / rsvd side measurements")
     ap.add_argument("--rsvd-reps", type=int, default=5)
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=500)
+    ap.add_argument("--serving-sweep", type=int, default=0, metavar="N",
+                    help="run only the serving workload on N requests at 0.5, 1, 2 and 4 times "
+                         "the plain path's saturation rate")
     ap.add_argument("--only-rsvd-spectrum", action="store_true",
                     help="run only the 65536 x 8192 rsvd leg (for profiling)")
     ap.add_argument("--only-extras", action="store_true",
@@ -431,6 +447,9 @@ def main():
         torch.cuda.synchronize()
         h.set_autotune(False)
 
+    if args.serving_sweep > 0:
+        print(json.dumps({"serving": serving_leg(args.serving_sweep, (0.5, 1.0, 2.0, 4.0))}), flush=True)
+        return
     if args.only_rsvd_spectrum:
         print(json.dumps({"rsvd_65536x8192": rsvd_spectrum(h, args.rsvd_reps, lat)}), flush=True)
         return

@@ -519,6 +519,19 @@ class Handle:
                                        _ptr(out), _ld(out)), "rmm_mixed_product")
         return out
 
+    def sketch_batch_workspace(self, kind, shapes, dtype=torch.float32) -> int:
+        """Workspace bytes of sketch_batch for problems of the given
+        (m, n, with_b, s) shapes (the size query reads no operand: the
+        descriptors carry placeholder addresses)."""
+        descs = (SketchDesc * max(1, len(shapes)))()
+        for i, (m, n, with_b, s) in enumerate(shapes):
+            descs[i] = SketchDesc(m, n, 256, max(1, m), 256 if with_b else None, s, 0, 256, max(1, s))
+        dt = F32 if dtype == torch.float32 else F64
+        ws = ctypes.c_size_t()
+        _check(lib().rmm_sketch_batch_workspace(self._h, dt, _kind(kind), len(shapes), descs,
+                                                ctypes.byref(ws)), "rmm_sketch_batch_workspace")
+        return ws.value
+
     def sketch_batch(self, kind, problems, dtype=torch.float32):
         """Sketches of several problems in one grouped call.
 

@@ -56,21 +56,49 @@ def test_sketch_batch_other_kinds_equal_solo(h, kind):
 
 
 def test_server_mix_equals_solo():
+    """A burst of 24 requests admitted under a budget: every result bitwise
+    equal to the request run alone, and the device memory the run allocates
+    (requests, outputs, the streams' workspaces) never above the budget."""
     reqs = synth.serving_mix(24, seed=11, m_range=(4096, 65536), n_range=(32, 256))
-    total = sum(serve.request_bytes(rmm.handle(), q) for q in reqs)
-    biggest = max(serve.request_bytes(rmm.handle(), q) for q in reqs)
-    budget = max(biggest, int(0.3 * total))
-    srv = serve.Server(budget, streams=3)
+    total = sum(serve.request_bytes(q) for q in reqs)
+    biggest = max(serve.request_bytes(q) for q in reqs)
+    shape = (65536, 256)
+    h0 = rmm.Handle()
+    ws = max(serve.workspace_bytes(h0, kind, *shape) for kind in ("lsr", "rsvd"))
+    budget = 3 * ws + max(biggest, int(0.3 * total))
+    # warm the generator and the library (code objects, BLAS handles)
+    for q in reqs[:2]:
+        A, b = synth.serving_request(q)
+        serve._solve_one(h0, q, A, b)
+    del A, b, h0
+    srv = serve.Server(budget, streams=3, max_shape=shape)
+    # torch keeps a BLAS workspace per stream (the input generator's matrix
+    # product): create those before the baseline, they are not the server's
+    for st in srv.streams:
+        with torch.cuda.stream(st):
+            synth.serving_request(reqs[0])
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    base = torch.cuda.memory_allocated() - srv.reserved  # the workspaces count against the budget
+    torch.cuda.reset_peak_memory_stats()
+    got = {}
+
+    def take(rid, o):  # results leave the device as they complete
+        got[rid] = {k: v.cpu() for k, v in o.items()}
+
     arrivals = np.zeros(len(reqs))                 # a burst: admission decides
-    out, lat, wall = srv.run(reqs, arrivals, synth.serving_request)
-    assert sorted(out) == list(range(len(reqs))) and not srv.rejected
+    out, lat, wall = srv.run(reqs, arrivals, synth.serving_request, on_done=take)
+    torch.cuda.synchronize()
+    used = torch.cuda.max_memory_allocated() - base
+    assert used <= budget, (used, budget, srv.reserved, srv.peak_bytes)
+    assert sorted(got) == list(range(len(reqs))) and not srv.rejected and not out
     assert srv.peak_bytes <= budget
     solo = rmm.Handle()
     for rid, q in enumerate(reqs):
         A, b = synth.serving_request(q)
         ref = serve._solve_one(solo, q, A, b)
         for key in ref:
-            assert torch.equal(out[rid][key], ref[key]), (rid, key)
+            assert torch.equal(got[rid][key], ref[key].cpu()), (rid, key)
     assert all(v >= 0 for v in lat.values())
 
 
