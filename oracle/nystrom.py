@@ -96,14 +96,23 @@ def nystrom_rows(X, sigma: float, c: int, seed: int, rows, k=None):
     return rbf(X[np.asarray(rows)], X[S], sigma) @ F, S, W, lam
 
 
-def nystrom_gaussian(X, sigma: float, c: int, seed: int, k=None, fp64=True):
-    """Gaussian-projection variant; returns (L, Omega, C, W, eigenvalues)."""
+def nystrom_projected(X, sigma: float, Om, k=None):
+    """The SPSD sketch of Sec. 6.4 with a general n x c sketch Omega:
+    C = K Omega, W = Omega^T K Omega; returns (L, C, W, eigenvalues)."""
     X = np.asarray(X, dtype=np.float64)
-    n = X.shape[0]
-    k = default_rank(c) if k is None else int(k)
-    Om = rng.gaussian_matrix(n, c, rng.TAG_GAUSS_NYSTROM, seed, fp64)
+    Om = np.asarray(Om, dtype=np.float64)
+    k = default_rank(Om.shape[1]) if k is None else int(k)
     K = rbf(X, X, sigma)
     C = K @ Om
     W = Om.T @ C
     L, lam = _factor(C, W, k)
+    return L, C, W, lam
+
+
+def nystrom_gaussian(X, sigma: float, c: int, seed: int, k=None, fp64=True):
+    """Gaussian-projection variant; returns (L, Omega, C, W, eigenvalues)."""
+    X = np.asarray(X, dtype=np.float64)
+    n = X.shape[0]
+    Om = rng.gaussian_matrix(n, c, rng.TAG_GAUSS_NYSTROM, seed, fp64)
+    L, C, W, lam = nystrom_projected(X, sigma, Om, k)
     return L, Om, C, W, lam

@@ -173,6 +173,33 @@ def test_nystrom_gaussian_variant():
     np.testing.assert_allclose(Om.T @ L @ L.T @ Om, W, rtol=0, atol=1e-6 * np.abs(W).max())
 
 
+def test_nystrom_projected_with_a_selection_is_column_sampling():
+    """Omega = I[:, S] turns the projected sketch into the column-sampling
+    Nystrom method (C = K[:, S], W = K[S, S]); the Gaussian variant is the
+    same function with a Gaussian Omega."""
+    X, sigma = synth.gmm_points(seed=12, n=300, d=4, pairs=500)
+    L0, S, C0, W0, lam0 = nystrom.nystrom(X, sigma, 16, seed=3, k=12)
+    Om = np.zeros((300, 16))
+    Om[S, np.arange(16)] = 1.0
+    L1, C1, W1, lam1 = nystrom.nystrom_projected(X, sigma, Om, k=12)
+    np.testing.assert_allclose(C1, C0, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(W1, W0, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(lam1, lam0, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(np.abs(L1), np.abs(L0), rtol=0, atol=1e-10)
+
+
+def test_nystrom_gaussian_recovers_low_rank_kernel():
+    """n points drawn from only r distinct locations make K of rank r; with a
+    Gaussian Omega of c >= r columns range(K Omega) = range(K), so the
+    untruncated L L^T equals K (up to the eigenvalue cut)."""
+    r = np.random.default_rng(4)
+    base = r.standard_normal((6, 3))
+    X = base[r.integers(0, 6, 150)]
+    L, Om, C, W, lam = nystrom.nystrom_gaussian(X, 1.0, 10, seed=2, k=10)
+    K = nystrom.rbf(X, X, 1.0)
+    assert np.linalg.norm(L @ L.T - K) <= 1e-8 * np.linalg.norm(K)
+
+
 def test_nystrom_rows_and_zero_eigenvalues():
     X, sigma = synth.gmm_points(seed=8, n=500, d=5, pairs=500)
     X = X.copy()

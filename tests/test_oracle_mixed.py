@@ -59,3 +59,38 @@ def test_quantized_product_structure(prec, mode):
     A2[:, 5] *= 8
     s1, s2 = mixed.column_scales(A, prec), mixed.column_scales(A2, prec)
     assert s2[5] == 8 * s1[5]
+
+
+@pytest.mark.parametrize("prec", [mixed.BF16, mixed.FP8])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_quantized_product_elementwise(prec, mode):
+    """Every entry against an explicit construction from the stated reading:
+    per-column scales of A (float32 amax / QMAX) and of the small operand
+    (after A's scales are folded into its rows for A X), each operand cast by
+    torch's own bfloat16 / float8_e4m3fn conversion, the product of the cast
+    values summed exactly (float64 over at most 2^11 terms of 16-bit-mantissa
+    products), then the scales applied.  A column scale taken per row, or the
+    small operand scaled before folding, changes entries well beyond 1e-12."""
+    r = np.random.default_rng(5)
+    A = (r.standard_normal((200, 40)) * np.exp2(r.integers(-6, 6, 40))[None, :]).astype(np.float32)
+    X = (r.standard_normal((40 if mode == 0 else 200, 7)) *
+         np.exp2(r.integers(-4, 4, 7))[None, :]).astype(np.float32)
+    tdt = torch.bfloat16 if prec == mixed.BF16 else torch.float8_e4m3fn
+    qmax = torch.tensor(1.0 if prec == mixed.BF16 else 448.0, dtype=torch.float32)
+    At, Xt = torch.from_numpy(A), torch.from_numpy(X)
+    sc = At.abs().amax(dim=0) / qmax
+    Aq = (At / sc[None, :]).to(tdt).to(torch.float64)
+    Xs = Xt * sc[:, None] if mode == 0 else Xt
+    u = Xs.abs().amax(dim=0) / qmax
+    Xq = (Xs / u[None, :]).to(tdt).to(torch.float64)
+    ref = np.empty((A.shape[1] if mode == 1 else A.shape[0], X.shape[1]))
+    for i in range(ref.shape[0]):
+        for j in range(ref.shape[1]):
+            if mode == 0:
+                acc = sum(float(Aq[i, t]) * float(Xq[t, j]) for t in range(A.shape[1]))
+                ref[i, j] = acc * float(u[j])
+            else:
+                acc = sum(float(Aq[t, i]) * float(Xq[t, j]) for t in range(A.shape[0]))
+                ref[i, j] = float(sc[i]) * acc * float(u[j])
+    P = mixed.quantized_product(A, X, prec, mode)
+    np.testing.assert_allclose(P, ref, rtol=1e-12, atol=0)
