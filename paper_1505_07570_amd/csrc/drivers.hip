@@ -291,6 +291,7 @@ int rsvd_mixed(rmm_ctx* h, bool run, rmm_precision prec, int64_t m, int64_t n, c
   unsigned char* Xq = ws.take<unsigned char>((size_t)pn * l * eb);
   float* uq = ws.take<float>((size_t)l);
   float* ux = ws.take<float>((size_t)l);
+  unsigned* umax = ws.take<unsigned>((size_t)l);
   float* Om = ws.take<float>((size_t)n * l);
   float* Y = ws.take<float>((size_t)m * l);
   float* Q = ws.take<float>((size_t)m * l);
@@ -316,18 +317,18 @@ int rsvd_mixed(rmm_ctx* h, bool run, rmm_precision prec, int64_t m, int64_t n, c
   RMM_TRY(mp_quantize_matrix(h, prec, m, n, A, lda, sc, Aq, Aqt));
   RMM_TRY(launch_gaussian<float>(h, TAG_GAUSS_RSVD, n, l, seed, Om, n));
   // Y = A Omega = Aq_t^T q(diag(sc) Omega)
-  RMM_TRY(mp_quantize_cols(h, prec, n, l, Om, n, sc, Xq, ux));
+  RMM_TRY(mp_quantize_cols(h, prec, n, l, Om, n, sc, Xq, ux, umax));
   RMM_TRY(mp_gemm_tn(h, prec, (int)m, l, pn, Aqt, Xq, nullptr, ux, Y, m, ws));
   for (int t = 0; t < q; ++t) {
     RMM_TRY((orth<float, float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws, 2)));
-    RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq));
+    RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq, umax));
     RMM_TRY(mp_gemm_tn(h, prec, (int)n, l, pm, Aq, Qq, sc, uq, Z, n, ws));
     RMM_TRY((orth<float, float>(h, n, l, Z, n, Qz, n, ob, tau_n, status, ws, 2)));
-    RMM_TRY(mp_quantize_cols(h, prec, n, l, Qz, n, sc, Xq, ux));
+    RMM_TRY(mp_quantize_cols(h, prec, n, l, Qz, n, sc, Xq, ux, umax));
     RMM_TRY(mp_gemm_tn(h, prec, (int)m, l, pn, Aqt, Xq, nullptr, ux, Y, m, ws));
   }
   RMM_TRY((orth<float, float>(h, m, l, Y, m, Q, m, ob, tau_m, status, ws, 3)));
-  RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq));
+  RMM_TRY(mp_quantize_cols(h, prec, m, l, Q, m, nullptr, Qq, uq, umax));
   RMM_TRY(mp_gemm_tn(h, prec, (int)n, l, pm, Aq, Qq, sc, uq, Z, n, ws));
   RMM_TRY(tall_svd<float>(h, n, l, k, Z, n, sb, status, ws));
   return finish_rsvd<float>(h, m, n, l, k, Q, sb, U, ldu, sigma, V, ldv, ws);

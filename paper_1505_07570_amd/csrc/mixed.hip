@@ -26,7 +26,6 @@ typedef short shortx4 __attribute__((ext_vector_type(4)));
 struct Bf16Fmt {
   using store_t = uint16_t;
   static constexpr float QMAX = 1.0f;  // scaling keeps |x| <= 1; bf16 has fp32's range
-  static constexpr int KPL = 4;        // K elements per lane per MFMA (16x16x16)
   static __device__ __forceinline__ uint16_t enc(float x) {
     // round to nearest even
     const uint32_t u = __float_as_uint(x);
@@ -37,25 +36,35 @@ struct Bf16Fmt {
 struct Fp8Fmt {
   using store_t = uint8_t;
   static constexpr float QMAX = 448.0f;  // OCP e4m3 largest finite value
-  static constexpr int KPL = 8;          // 16x16x32
   static __device__ __forceinline__ uint8_t enc(float x) {
     return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF);
   }
 };
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// One MFMA of each format: 16 x 16 outputs, K = 32 per instruction, each lane
+// holding 8 K-consecutive elements of one row of each operand (16 bytes for
+// BF16, gfx950's 16x16x32 BF16 MFMA; 8 bytes for FP8).
 template <typename F>
-__device__ __forceinline__ floatx4 qmfma(uint64_t a, uint64_t b, floatx4 c);
+struct QOp;
 template <>
-__device__ __forceinline__ floatx4 qmfma<Bf16Fmt>(uint64_t a, uint64_t b, floatx4 c) {
-  shortx4 x, y;
-  __builtin_memcpy(&x, &a, 8);
-  __builtin_memcpy(&y, &b, 8);
-  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(x, y, c, 0, 0, 0);
-}
+struct QOp<Bf16Fmt> {
+  using op_t = uint4;
+  static __device__ __forceinline__ floatx4 mfma(uint4 a, uint4 b, floatx4 c) {
+    bf16x8 x, y;
+    __builtin_memcpy(&x, &a, 16);
+    __builtin_memcpy(&y, &b, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
+  }
+};
 template <>
-__device__ __forceinline__ floatx4 qmfma<Fp8Fmt>(uint64_t a, uint64_t b, floatx4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)a, (long)b, c, 0, 0, 0);
-}
+struct QOp<Fp8Fmt> {
+  using op_t = uint64_t;
+  static __device__ __forceinline__ floatx4 mfma(uint64_t a, uint64_t b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)a, (long)b, c, 0, 0, 0);
+  }
+};
 
 // ---- quantization ----------------------------------------------------------------
 
@@ -168,116 +177,162 @@ __global__ __launch_bounds__(256) void quantize_tile_kernel(int64_t m, int64_t n
   }
 }
 
-// Xq[:, c] = q(rs .* X[:, c] / u_c), u_c = max_k |rs_k X_kc| / QMAX; one workgroup per column
-template <typename F>
-__global__ __launch_bounds__(256) void quantize_cols_kernel(int64_t rows, const float* __restrict__ X,
-                                                            int64_t ldx, const float* __restrict__ rs,
-                                                            typename F::store_t* __restrict__ Xq,
-                                                            float* __restrict__ u) {
+// Xq[:, c] = q(rs .* X[:, c] / u_c), u_c = max_k |rs_k X_kc| / QMAX (1 for a
+// zero column), in three launches spread over the whole device: clear the
+// column maxima, take them with atomicMax on the bit patterns (non-negative
+// floats order as their bits), then quantize element-parallel.
+constexpr int kQcRows = 4096;  // rows per workgroup of the max pass
+
+__global__ void colmax_clear_kernel(int cols, unsigned* __restrict__ umax) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < cols) umax[c] = 0u;
+}
+
+__global__ __launch_bounds__(256) void colmax_kernel(int64_t rows, const float* __restrict__ X, int64_t ldx,
+                                                     const float* __restrict__ rs,
+                                                     unsigned* __restrict__ umax) {
   __shared__ float red[256];
   const float* col = X + (int64_t)blockIdx.x * ldx;
+  const int64_t r0 = (int64_t)blockIdx.y * kQcRows;
+  const int64_t r1 = (r0 + kQcRows < rows) ? r0 + kQcRows : rows;
   float mx = 0.f;
-  for (int64_t i = threadIdx.x; i < rows; i += 256) mx = fmaxf(mx, fabsf(col[i] * (rs ? rs[i] : 1.f)));
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += 256) mx = fmaxf(mx, fabsf(col[i] * (rs ? rs[i] : 1.f)));
   red[threadIdx.x] = mx;
   __syncthreads();
   for (int st = 128; st > 0; st >>= 1) {
-    if (threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
+    if ((int)threadIdx.x < st) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + st]);
     __syncthreads();
   }
-  const float uc = red[0] > 0.f ? red[0] / F::QMAX : 1.f;
-  if (threadIdx.x == 0) u[blockIdx.x] = uc;
+  if (threadIdx.x == 0 && red[0] > 0.f) atomicMax(&umax[blockIdx.x], __float_as_uint(red[0]));
+}
+
+template <typename F>
+__global__ __launch_bounds__(256) void quantize_cols_kernel(int64_t rows, const float* __restrict__ X,
+                                                            int64_t ldx, const float* __restrict__ rs,
+                                                            const unsigned* __restrict__ umax,
+                                                            typename F::store_t* __restrict__ Xq,
+                                                            float* __restrict__ u) {
+  const int64_t c = blockIdx.y;
+  const float m = __uint_as_float(umax[c]);
+  const float uc = m > 0.f ? m / F::QMAX : 1.f;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i == 0) u[c] = uc;
   const int64_t ldq = (rows + 15) / 16 * 16;
-  typename F::store_t* out = Xq + (int64_t)blockIdx.x * ldq;
-  for (int64_t i = threadIdx.x; i < ldq; i += 256)
-    out[i] = i < rows ? F::enc(col[i] * (rs ? rs[i] : 1.f) / uc) : (typename F::store_t)0;
+  if (i >= ldq) return;
+  const float* col = X + c * ldx;
+  Xq[c * ldq + i] = i < rows ? F::enc(col[i] * (rs ? rs[i] : 1.f) / uc) : (typename F::store_t)0;
 }
 
 // ---- C = X^T Y with quantized, K-contiguous operands ----------------------------------
 //
-// X: K x M, Y: K x N (column-major, ld = K).  Workgroup tile 64 x 128, 4 waves
-// (2 x 2), wave tile 32 x 64 = 2 x 4 MFMA tiles.  Stages of BK = 64 K through
-// LDS, each operand row of the tile stored K-contiguous with an 8-byte pad.
+// X: K x M, Y: K x N (column-major, ld = K).  Workgroup tile 256 x 128 (so
+// the small operand Y is re-read once per 256 rows of A), 8 waves of 64 x 64
+// (4 x 4 MFMA tiles).  Stages of 128 bytes of K per operand row go through
+// two LDS buffers (rows padded to 144 bytes: the 16-byte operand reads of a
+// quarter wave hit distinct banks); the 16-byte global loads of the next two
+// stages sit in registers while the current stage is multiplied, and each
+// stage needs one barrier (a buffer is rewritten two stages after its last
+// reads, behind the barrier of the stage in between).  Split-K over blockIdx.z, partials reduced in FP64 by
+// qgemm_reduce_kernel.
+constexpr int kQBM = 256, kQBN = 128;
+constexpr int kQRow = 128;  // bytes of K per staged row
+constexpr int kQPad = 144;  // padded row pitch in LDS
+constexpr int kQThreads = 512;
+constexpr size_t kQLds = 2 * (size_t)(kQBM + kQBN) * kQPad;
+
 template <typename F>
-__global__ __launch_bounds__(256) void qgemm_tn_kernel(int M, int N, int64_t K,
-                                                       const typename F::store_t* __restrict__ X,
-                                                       const typename F::store_t* __restrict__ Y,
-                                                       float* __restrict__ P, int64_t kchunk) {
+__global__ __launch_bounds__(kQThreads) void qgemm_tn_kernel(int M, int N, int64_t K,
+                                                             const typename F::store_t* __restrict__ X,
+                                                             const typename F::store_t* __restrict__ Y,
+                                                             float* __restrict__ P, int64_t kchunk) {
   using S = typename F::store_t;
-  constexpr int BM = 64, BN = 128, BK = 64;
-  constexpr int KPL = F::KPL;                 // elements per lane per MFMA
-  constexpr int KM = 4 * KPL;                 // K per MFMA
-  constexpr int RB = BK * (int)sizeof(S);     // bytes per staged row
-  constexpr int RP = RB + 8;                  // padded
-  __shared__ __align__(16) unsigned char xs[BM * RP];
-  __shared__ __align__(16) unsigned char ys[BN * RP];
+  using op_t = typename QOp<F>::op_t;
+  constexpr int ES = (int)sizeof(S);
+  constexpr int BK = kQRow / ES;                        // K elements per stage
+  constexpr int V16 = 16 / ES;                          // elements per 16-byte chunk
+  constexpr int CPR = kQRow / 16;                       // chunks per staged row
+  constexpr int ROWS = kQBM + kQBN;
+  constexpr int CH = ROWS * CPR / kQThreads;            // chunks per thread
+  constexpr int KPL = (int)sizeof(op_t) / ES;           // elements per lane per MFMA
+  constexpr int KM = 4 * KPL;                           // K per MFMA
+  static_assert(ROWS * CPR % kQThreads == 0, "chunks per thread");
+  extern __shared__ __align__(16) unsigned char qlds[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int g = lane >> 4, c16 = lane & 15;
+  const int m0 = blockIdx.x * kQBM, n0 = blockIdx.y * kQBN;
   const int64_t k0 = (int64_t)blockIdx.z * kchunk;
-  int64_t k1 = k0 + kchunk;
-  if (k1 > K) k1 = K;
-  floatx4 acc[2][4];
+  const int64_t k1 = (k0 + kchunk < K) ? k0 + kchunk : K;
+  floatx4 acc[4][4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = floatx4{0, 0, 0, 0};
-  const int g = lane >> 4, c16 = lane & 15;
-  constexpr int V16 = 16 / (int)sizeof(S);  // elements per 16-byte load
-  constexpr int CPR = BK / V16;             // 16-byte chunks per staged row
-  for (int64_t kb = k0; kb < k1; kb += BK) {
-    const bool full = kb + BK <= k1;
-    // stage X rows (m0 .. m0+BM) and Y rows (n0 .. n0+BN), K kb .. kb+BK
-    for (int e = tid; e < (BM + BN) * CPR; e += 256) {
-      const int row = e / CPR, ch = e % CPR;
-      const bool isx = row < BM;
-      const int r = isx ? row : row - BM;
-      const int64_t gr = (isx ? m0 : n0) + r;
-      const S* src = isx ? X : Y;
-      const int lim = isx ? M : N;
-      unsigned char* dst = (isx ? xs : ys) + r * RP + ch * 16;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (gr < lim) {
-        const S* p = src + gr * K + kb + ch * V16;
-        if (full) {
-          v = *reinterpret_cast<const uint4*>(p);
-        } else {
-          S tmp[V16];
+  // chunk e = tid + q * kQThreads: staged row e / CPR (X rows first), chunk e % CPR
+  const S* src[CH];
+  int lds_off[CH];
+  bool live[CH];
 #pragma unroll
-          for (int q = 0; q < V16; ++q) tmp[q] = (kb + ch * V16 + q < k1) ? p[q] : (S)0;
-          __builtin_memcpy(&v, tmp, 16);
-        }
-      }
-      *reinterpret_cast<uint2*>(dst) = make_uint2(v.x, v.y);
-      *reinterpret_cast<uint2*>(dst + 8) = make_uint2(v.z, v.w);
+  for (int q = 0; q < CH; ++q) {
+    const int e = tid + q * kQThreads;
+    const int row = e / CPR, ch = e % CPR;
+    const bool isx = row < kQBM;
+    const int r = isx ? row : row - kQBM;
+    const int64_t gr = (int64_t)(isx ? m0 : n0) + r;
+    live[q] = gr < (isx ? M : N);
+    src[q] = (isx ? X : Y) + (live[q] ? gr : 0) * K + ch * V16;
+    lds_off[q] = row * kQPad + ch * 16;
+  }
+  // two stages of loads in flight: stage t + 2 is issued while stage t is
+  // multiplied (the loop is unrolled by two so that both register sets keep
+  // constant indices)
+  uint4 pa[CH], pb[CH];
+  auto load = [&](uint4 (&pre)[CH], int64_t kb) {
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int64_t ko = kb + (int64_t)((tid + q * kQThreads) % CPR) * V16;
+      pre[q] = (live[q] && ko < k1) ? *reinterpret_cast<const uint4*>(src[q] + kb)
+                                    : make_uint4(0, 0, 0, 0);
     }
+  };
+  auto stage = [&](uint4 (&pre)[CH], int64_t kb, int parity) {
+    unsigned char* buf = qlds + (size_t)parity * ROWS * kQPad;
+#pragma unroll
+    for (int q = 0; q < CH; ++q) *reinterpret_cast<uint4*>(buf + lds_off[q]) = pre[q];
     __syncthreads();
+    if (kb + 2 * BK < k1) load(pre, kb + 2 * BK);
+    const unsigned char* xb = buf;
+    const unsigned char* yb = buf + kQBM * kQPad;
 #pragma unroll
     for (int ks = 0; ks < BK; ks += KM) {
-      uint64_t av[2], bv[4];
+      op_t av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-        av[a] = *reinterpret_cast<const uint64_t*>(xs + (wm * 32 + a * 16 + c16) * RP +
-                                                   (ks + g * KPL) * (int)sizeof(S));
+      for (int a = 0; a < 4; ++a)
+        av[a] = *reinterpret_cast<const op_t*>(xb + (wm * 64 + a * 16 + c16) * kQPad + (ks + g * KPL) * ES);
 #pragma unroll
       for (int b = 0; b < 4; ++b)
-        bv[b] = *reinterpret_cast<const uint64_t*>(ys + (wn * 64 + b * 16 + c16) * RP +
-                                                   (ks + g * KPL) * (int)sizeof(S));
+        bv[b] = *reinterpret_cast<const op_t*>(yb + (wn * 64 + b * 16 + c16) * kQPad + (ks + g * KPL) * ES);
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = qmfma<F>(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < 4; ++b) acc[a][b] = QOp<F>::mfma(av[a], bv[b], acc[a][b]);
     }
-    __syncthreads();
+  };
+  load(pa, k0);
+  if (k0 + BK < k1) load(pb, k0 + BK);
+  for (int64_t kb = k0; kb < k1; kb += 2 * BK) {
+    stage(pa, kb, 0);
+    if (kb + BK < k1) stage(pb, kb + BK, 1);
   }
   float* dst = P + (int64_t)blockIdx.z * M * N;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
       const int j = n0 + wn * 64 + b * 16 + c16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int i = m0 + wm * 32 + a * 16 + 4 * g + v;
+        const int i = m0 + wm * 64 + a * 16 + 4 * g + v;
         if (i < M && j < N) dst[i + (int64_t)j * M] = acc[a][b][v];
       }
     }
@@ -302,14 +357,16 @@ struct QShape {
   int64_t kchunk;
 };
 
+// one workgroup per CU (each holds 108 KB of LDS): split K until the tiles
+// times the splits reach the CU count, with at least 2048 K per split
 QShape qshape(const rmm_ctx* h, int M, int N, int64_t K) {
-  const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 127) / 128);
-  int64_t want = (4ll * h->cus + tiles - 1) / tiles;
+  const int64_t tiles = (int64_t)((M + kQBM - 1) / kQBM) * ((N + kQBN - 1) / kQBN);
+  int64_t want = ((int64_t)h->cus + tiles - 1) / tiles;
   const int64_t maxsplit = (K + 2047) / 2048;
   if (want > maxsplit) want = maxsplit;
   if (want < 1) want = 1;
   int64_t kc = (K + want - 1) / want;
-  kc = (kc + 63) / 64 * 64;
+  kc = (kc + 127) / 128 * 128;  // whole stages of both formats
   QShape q;
   q.kchunk = kc;
   q.splits = (int)((K + kc - 1) / kc);
@@ -335,8 +392,10 @@ int qgemm_tn(rmm_ctx* h, int M, int N, int64_t K, const void* X, const void* Y, 
   const size_t mark = ws.off;
   float* P = ws.take<float>((size_t)q.splits * M * N);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
-  dim3 grid((unsigned)((M + 63) / 64), (unsigned)((N + 127) / 128), (unsigned)q.splits);
-  hipLaunchKernelGGL(qgemm_tn_kernel<F>, grid, dim3(256), 0, h->stream, M, N, K,
+  dim3 grid((unsigned)((M + kQBM - 1) / kQBM), (unsigned)((N + kQBN - 1) / kQBN), (unsigned)q.splits);
+  RMM_HIP(hipFuncSetAttribute((const void*)qgemm_tn_kernel<F>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kQLds));
+  hipLaunchKernelGGL(qgemm_tn_kernel<F>, grid, dim3(kQThreads), kQLds, h->stream, M, N, K,
                      (const typename F::store_t*)X, (const typename F::store_t*)Y, P, q.kchunk);
   RMM_TRY(launch_status());
   dim3 g2((unsigned)((M + 255) / 256), (unsigned)N);
@@ -361,9 +420,16 @@ int quantize_matrix(const rmm_ctx* h, int64_t m, int64_t n, const float* A, int6
 
 template <typename F>
 int quantize_cols(const rmm_ctx* h, int64_t rows, int64_t cols, const float* X, int64_t ldx,
-                  const float* rs, void* Xq, float* u) {
-  hipLaunchKernelGGL(quantize_cols_kernel<F>, dim3((unsigned)cols), dim3(256), 0, h->stream, rows, X,
-                     ldx, rs, (typename F::store_t*)Xq, u);
+                  const float* rs, void* Xq, float* u, unsigned* umax) {
+  if (cols == 0) return RMM_OK;
+  hipLaunchKernelGGL(colmax_clear_kernel, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, h->stream,
+                     (int)cols, umax);
+  hipLaunchKernelGGL(colmax_kernel, dim3((unsigned)cols, (unsigned)((rows + kQcRows - 1) / kQcRows)),
+                     dim3(256), 0, h->stream, rows, X, ldx, rs, umax);
+  const int64_t ldq = (rows + 15) / 16 * 16;
+  hipLaunchKernelGGL(quantize_cols_kernel<F>, dim3((unsigned)((ldq + 255) / 256), (unsigned)cols),
+                     dim3(256), 0, h->stream, rows, X, ldx, rs, (const unsigned*)umax,
+                     (typename F::store_t*)Xq, u);
   return launch_status();
 }
 
@@ -374,9 +440,9 @@ int mp_quantize_matrix(const rmm_ctx* h, rmm_precision p, int64_t m, int64_t n, 
                             : quantize_matrix<Fp8Fmt>(h, m, n, A, lda, sc, Aq, Aqt);
 }
 int mp_quantize_cols(const rmm_ctx* h, rmm_precision p, int64_t rows, int64_t cols, const float* X,
-                     int64_t ldx, const float* rs, void* Xq, float* u) {
-  return p == RMM_PREC_BF16 ? quantize_cols<Bf16Fmt>(h, rows, cols, X, ldx, rs, Xq, u)
-                            : quantize_cols<Fp8Fmt>(h, rows, cols, X, ldx, rs, Xq, u);
+                     int64_t ldx, const float* rs, void* Xq, float* u, unsigned* umax) {
+  return p == RMM_PREC_BF16 ? quantize_cols<Bf16Fmt>(h, rows, cols, X, ldx, rs, Xq, u, umax)
+                            : quantize_cols<Fp8Fmt>(h, rows, cols, X, ldx, rs, Xq, u, umax);
 }
 int mp_gemm_tn(rmm_ctx* h, rmm_precision p, int M, int N, int64_t K, const void* X, const void* Y,
                const float* rs, const float* cs, float* C, int64_t ldc, Carver& ws) {
@@ -396,6 +462,7 @@ size_t mp_product_workspace(const rmm_ctx* h, rmm_precision p, int64_t m, int64_
   c.take<unsigned char>((size_t)pn * m * eb);
   c.take<unsigned char>((size_t)(pm > pn ? pm : pn) * l * eb);
   c.take<float>((size_t)l);
+  c.take<unsigned>((size_t)l);
   const size_t a = qgemm_workspace(h, (int)m, l, pn), b = qgemm_workspace(h, (int)n, l, pm);
   return c.off + (a > b ? a : b) + 4 * kAlign;
 }
@@ -411,13 +478,14 @@ int mp_product(rmm_ctx* h, rmm_precision p, int mode, int64_t m, int64_t n, cons
   unsigned char* Aqt = ws.take<unsigned char>((size_t)pn * m * eb);
   unsigned char* Xq = ws.take<unsigned char>((size_t)(pm > pn ? pm : pn) * l * eb);
   float* u = ws.take<float>((size_t)l);
+  unsigned* umax = ws.take<unsigned>((size_t)l);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
   RMM_TRY(mp_quantize_matrix(h, p, m, n, A, lda, sc, Aq, Aqt));
   if (mode == 0) {
-    RMM_TRY(mp_quantize_cols(h, p, n, l, X, ldx, sc, Xq, u));
+    RMM_TRY(mp_quantize_cols(h, p, n, l, X, ldx, sc, Xq, u, umax));
     return mp_gemm_tn(h, p, (int)m, l, pn, Aqt, Xq, nullptr, u, out, ldo, ws);
   }
-  RMM_TRY(mp_quantize_cols(h, p, m, l, X, ldx, nullptr, Xq, u));
+  RMM_TRY(mp_quantize_cols(h, p, m, l, X, ldx, nullptr, Xq, u, umax));
   return mp_gemm_tn(h, p, (int)n, l, pm, Aq, Xq, sc, u, out, ldo, ws);
 }
 

@@ -13,9 +13,10 @@ size_t mp_elem_bytes(rmm_precision p);
 // Aqt: ldqt = mp_pad(n) x m column-major (A^T), zero padded.
 int mp_quantize_matrix(const rmm_ctx* h, rmm_precision p, int64_t m, int64_t n, const float* A,
                        int64_t lda, float* sc, void* Aq, void* Aqt);
-// Xq (ld = mp_pad(rows)) = q(rs .* X[:, c] / u_c) per column, zero padded.
+// Xq (ld = mp_pad(rows)) = q(rs .* X[:, c] / u_c) per column, zero padded;
+// umax: cols words of scratch for the column maxima.
 int mp_quantize_cols(const rmm_ctx* h, rmm_precision p, int64_t rows, int64_t cols, const float* X,
-                     int64_t ldx, const float* rs, void* Xq, float* u);
+                     int64_t ldx, const float* rs, void* Xq, float* u, unsigned* umax);
 // C (M x N) = diag(rs) * X^T Y * diag(cs) with X (Kpad x M) and Y (Kpad x N),
 // ld = Kpad (a multiple of 16); rs may be null.
 int mp_gemm_tn(rmm_ctx* h, rmm_precision p, int M, int N, int64_t Kpad, const void* X, const void* Y,
