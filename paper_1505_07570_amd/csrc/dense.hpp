@@ -40,6 +40,10 @@ size_t cholinv_workspace(const rmm_ctx* h, int l);
 int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals, double* V,
                int32_t* status, Carver& ws);
 size_t jacobi_workspace(int l);
+// Block Jacobi used by jacobi_eig for 128 < l <= 1024 (blockjacobi.hip).
+int jacobi_eig_block(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals, double* V,
+                     int32_t* status, Carver& ws);
+size_t jacobi_block_workspace(int l);
 
 // SVD of an l x l FP64 matrix by one-sided Jacobi: M J = Ubar diag(sigma)
 // with sigma (l, descending, ties by index) the column norms of M J, Ubar

@@ -617,18 +617,13 @@ __global__ __launch_bounds__(256) void jacobi_vectors_kernel(int l, const double
   }
 }
 
-// ---- multi-workgroup cyclic Jacobi for 128 < l <= 1024 -------------------------------
+// ---- shared pieces of the global-memory Jacobi paths (l up to 1024) --------------------
 //
-// Same rotations, ordering, thresholds and stopping rule as jacobi_kernel,
-// with the matrix in global memory: one launch per round, whose workgroups
-// each take a 32 x 32 tile of the (i <= j) pair grid, compute the rotations
-// of their tile's pairs from the matrix of the previous round (two buffers,
-// read one, write the other) and write every element of their blocks.
-// Before each sweep a scan of the matrix decides convergence (no pair passes
-// the rotation test, i.e. the sweep would rotate nothing) and later launches
-// return at once; the sweep's rotation log is applied to the rows of V
-// (row-major in the workspace) by a row-parallel kernel.  A final kernel sorts the eigenvalues and writes V's columns.
-constexpr int kBigTile = 32;
+// The one-sided SVD below for l > 128 runs one launch per round of the
+// parallel cyclic order, logs the round's rotations, and applies a sweep's log
+// to the rows of its vector matrix (row-major in the workspace) with
+// big_vectors_kernel.  The symmetric eigensolver for l > 128 is the block
+// Jacobi of blockjacobi.hip.
 constexpr int kBigMaxL = 1024;
 constexpr int kBigMaxSweeps = 30;
 
@@ -639,144 +634,6 @@ struct BigState {
   int parity;      // buffer holding the current matrix
   int sweeps;      // sweeps run
 };
-
-__global__ void big_tol_kernel(int l, const double* __restrict__ G, int64_t ldg, BigState* st) {
-  __shared__ double red[256];
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < l; i += 256) mx = fmax(mx, fabs(G[i + (int64_t)i * ldg]));
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *st = BigState{1e-17 * red[0], 0, 0, 0, 0};
-}
-
-__global__ void big_init_kernel(int l, int L, const double* __restrict__ G, int64_t ldg,
-                                double* __restrict__ G0, double* __restrict__ Vr,
-                                uint16_t* __restrict__ ptab, uint16_t* __restrict__ qtab,
-                                BigState* st) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int npairs = L / 2;
-  if (e < (int64_t)L * L) {
-    const int a = (int)(e % L), b = (int)(e / L);
-    G0[e] = (a <= b && b < l) ? G[a + (int64_t)b * ldg] : 0.0;
-    Vr[e] = (a == b) ? 1.0 : 0.0;  // row-major identity, L x L
-  }
-  if (e < (int64_t)(L - 1) * npairs) {
-    int p, q;
-    rr_pair((int)(e % npairs), (int)(e / npairs), L, p, q);
-    ptab[e] = (uint16_t)p;
-    qtab[e] = (uint16_t)q;
-  }
-}
-
-__global__ __launch_bounds__(256) void big_round_kernel(int l, int L, int r, const double* __restrict__ Gin,
-                                                        double* __restrict__ Gout,
-                                                        const uint16_t* __restrict__ ptab,
-                                                        const uint16_t* __restrict__ qtab,
-                                                        double2* __restrict__ rlog, BigState* st,
-                                                        int out_parity) {
-  if (st->converged) return;
-  const double abs_tol = st->abs_tol;
-  const int npairs = L / 2;
-  const int T = (npairs + kBigTile - 1) / kBigTile;
-  // tile (ti, tj), ti <= tj, from the linear block index
-  int ti = 0, rem = blockIdx.x;
-  while (rem >= T - ti) {
-    rem -= T - ti;
-    ++ti;
-  }
-  const int tj = ti + rem;
-  __shared__ double cs[2][kBigTile], sn[2][kBigTile], tn[2][kBigTile];
-  __shared__ int pp[2][kBigTile], qq[2][kBigTile];
-  const int tid = threadIdx.x;
-  if (tid < 2 * kBigTile) {
-    const int side = tid / kBigTile, k = tid % kBigTile;
-    const int pair = (side == 0 ? ti : tj) * kBigTile + k;
-    int p = 0, q = 0;
-    double c = 1.0, s = 0.0, tt = 0.0;
-    if (pair < npairs) {
-      p = ptab[(size_t)r * npairs + pair];
-      q = qtab[(size_t)r * npairs + pair];
-      if (q < l) {
-        const double gpq = Gin[p + (int64_t)q * L];
-        const double gpp = Gin[p + (int64_t)p * L], gqq = Gin[q + (int64_t)q * L];
-        if (fabs(gpq) > abs_tol && fabs(gpq) > 0x1p-52 * sqrt(fabs(gpp * gqq))) {
-          const double theta = (gqq - gpp) / (2.0 * gpq);
-          tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(tt * tt + 1.0);
-          s = tt * c;
-        }
-      }
-      if (side == 0 && ti == tj) rlog[pair] = make_double2(c, s);
-    }
-    pp[side][k] = p;
-    qq[side][k] = q;
-    cs[side][k] = c;
-    sn[side][k] = s;
-    tn[side][k] = tt;
-  }
-  __syncthreads();
-  if (blockIdx.x == 0 && tid == 0) st->parity = out_parity;
-  for (int b = tid; b < kBigTile * kBigTile; b += blockDim.x) {
-    const int ii = b / kBigTile, jj = b % kBigTile;
-    const int i = ti * kBigTile + ii, j = tj * kBigTile + jj;
-    if (i >= npairs || j >= npairs || (ti == tj && ii > jj)) continue;
-    const int pi = pp[0][ii], qi = qq[0][ii], pj = pp[1][jj], qj = qq[1][jj];
-    const int64_t a0 = pi < pj ? pi + (int64_t)pj * L : pj + (int64_t)pi * L;
-    const int64_t a1 = pi < qj ? pi + (int64_t)qj * L : qj + (int64_t)pi * L;
-    const int64_t a2 = qi < pj ? qi + (int64_t)pj * L : pj + (int64_t)qi * L;
-    const int64_t a3 = qi < qj ? qi + (int64_t)qj * L : qj + (int64_t)qi * L;
-    const double x00 = Gin[a0], x01 = Gin[a1], x10 = Gin[a2], x11 = Gin[a3];
-    const double ci = cs[0][ii], si = sn[0][ii], cj = cs[1][jj], sj = sn[1][jj];
-    if (i == j) {
-      // (pp, pq, qp, qq) of the pair; qp and pq share an address
-      if (si != 0.0) {
-        const double t = tn[0][ii];
-        Gout[a0] = x00 - t * x01;
-        Gout[a3] = x11 + t * x01;
-        Gout[a1] = 0.0;
-      } else {
-        Gout[a0] = x00;
-        Gout[a3] = x11;
-        Gout[a1] = x01;
-      }
-      continue;
-    }
-    const double y00 = ci * x00 - si * x10, y01 = ci * x01 - si * x11;
-    const double y10 = si * x00 + ci * x10, y11 = si * x01 + ci * x11;
-    Gout[a0] = cj * y00 - sj * y01;
-    Gout[a1] = sj * y00 + cj * y01;
-    Gout[a2] = cj * y10 - sj * y11;
-    Gout[a3] = sj * y10 + cj * y11;
-  }
-}
-
-// pending |= some upper off-diagonal element of the current matrix passes the
-// rotation test (then the next sweep rotates something)
-__global__ void big_scan_kernel(int l, int L, const double* __restrict__ G0,
-                                const double* __restrict__ G1, BigState* st) {
-  if (st->converged) return;
-  const double* G = st->parity ? G1 : G0;
-  const double abs_tol = st->abs_tol;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)l * l) return;
-  const int a = (int)(e % l), b = (int)(e / l);
-  if (a >= b) return;
-  const double gpq = G[a + (int64_t)b * L];
-  if (fabs(gpq) > abs_tol &&
-      fabs(gpq) > 0x1p-52 * sqrt(fabs(G[a + (int64_t)a * L] * G[b + (int64_t)b * L])))
-    atomicOr(&st->pending, 1);
-}
-
-__global__ void big_decide_kernel(BigState* st) {
-  if (st->converged) return;
-  if (st->pending == 0) st->converged = 1;
-  else st->sweeps += 1;
-  st->pending = 0;
-}
 
 // Apply one sweep's logged rotations to rows of V (row-major L x L): wave =
 // 2 rows, lane handles pairs lane, lane + 64, ...; the next round's
@@ -829,100 +686,21 @@ __global__ __launch_bounds__(256) void big_vectors_kernel(int L, const double2* 
       for (int c = lane; c < L; c += 64) Vr[(int64_t)(row0 + rr) * L + c] = V[rr * L + c];
 }
 
-// eigenvalues (diagonal of the current buffer), descending with ties by index;
-// Vout[:, rank] = V[:, j] (V row-major: V[k][j] = Vr[k * L + j])
-__global__ void big_finish_kernel(int l, int L, const double* __restrict__ G0,
-                                  const double* __restrict__ G1, const double* __restrict__ Vr,
-                                  double* __restrict__ evals, double* __restrict__ Vout,
-                                  const BigState* st, int32_t* status) {
-  const double* G = st->parity ? G1 : G0;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j == 0 && !st->converged) or_status(status, RMM_STATUS_NOT_CONVERGED);
-  if (j >= l) return;
-  const double v = G[j + (int64_t)j * L];
-  int rank = 0;
-  for (int i = 0; i < l; ++i) {
-    const double u = G[i + (int64_t)i * L];
-    rank += (u > v) || (u == v && i < j);
-  }
-  evals[rank] = v;
-  for (int k = 0; k < l; ++k) Vout[k + (int64_t)rank * l] = Vr[(int64_t)k * L + j];
-}
-
 size_t jacobi_workspace(int l) {
   const int L = (l + 1) & ~1;
+  if (l > kLdsMaxL) return jacobi_block_workspace(l);
   Carver c(nullptr, 0);
-  if (l <= kLdsMaxL) {
-    c.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * (L / 2));
-    c.take<int>((size_t)l);
-    c.take<int>(1);
-    return c.off + 3 * kAlign;
-  }
-  c.take<double>((size_t)L * L);  // G0
-  c.take<double>((size_t)L * L);  // G1
-  c.take<double>((size_t)L * L);  // Vr
-  c.take<double2>((size_t)(L - 1) * (L / 2));
-  c.take<uint16_t>((size_t)(L - 1) * (L / 2));
-  c.take<uint16_t>((size_t)(L - 1) * (L / 2));
-  c.take<BigState>(1);
-  return c.off + 8 * kAlign;
-}
-
-static int jacobi_eig_big(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals,
-                          double* V, int32_t* status, Carver& ws) {
-  const int L = (l + 1) & ~1;
-  const int npairs = L / 2;
-  const size_t mark = ws.off;
-  double* G0 = ws.take<double>((size_t)L * L);
-  double* G1 = ws.take<double>((size_t)L * L);
-  double* Vr = ws.take<double>((size_t)L * L);
-  double2* rlog = ws.take<double2>((size_t)(L - 1) * npairs);
-  uint16_t* ptab = ws.take<uint16_t>((size_t)(L - 1) * npairs);
-  uint16_t* qtab = ws.take<uint16_t>((size_t)(L - 1) * npairs);
-  BigState* st = ws.take<BigState>(1);
-  if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
-  const int64_t init_n = (int64_t)L * L;
-  hipLaunchKernelGGL(big_init_kernel, dim3((unsigned)((init_n + 255) / 256)), dim3(256), 0, h->stream,
-                     l, L, G, ldg, G0, Vr, ptab, qtab, st);
-  RMM_TRY(launch_status());
-  hipLaunchKernelGGL(big_tol_kernel, dim3(1), dim3(256), 0, h->stream, l, G, ldg, st);
-  RMM_TRY(launch_status());
-  const int T = (npairs + kBigTile - 1) / kBigTile;
-  const unsigned tiles = (unsigned)(T * (T + 1) / 2);
-  const size_t vlds = (size_t)4 * kBigVecRows * L * sizeof(double);
-  RMM_HIP(hipFuncSetAttribute((const void*)big_vectors_kernel,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
-  const unsigned vgroups = (unsigned)((L + 4 * kBigVecRows - 1) / (4 * kBigVecRows));
-  int parity = 0;
-  const unsigned sgroups = (unsigned)(((int64_t)l * l + 255) / 256);
-  for (int sweep = 0; sweep <= kBigMaxSweeps; ++sweep) {
-    hipLaunchKernelGGL(big_scan_kernel, dim3(sgroups), dim3(256), 0, h->stream, l, L, G0, G1, st);
-    hipLaunchKernelGGL(big_decide_kernel, dim3(1), dim3(1), 0, h->stream, st);
-    RMM_TRY(launch_status());
-    if (sweep == kBigMaxSweeps) break;  // the last scan only decides convergence
-    for (int r = 0; r < L - 1; ++r) {
-      const double* gin = parity ? G1 : G0;
-      double* gout = parity ? G0 : G1;
-      hipLaunchKernelGGL(big_round_kernel, dim3(tiles), dim3(256), 0, h->stream, l, L, r, gin, gout,
-                         ptab, qtab, rlog + (size_t)r * npairs, st, parity ^ 1);
-      parity ^= 1;
-    }
-    RMM_TRY(launch_status());
-    hipLaunchKernelGGL(big_vectors_kernel, dim3(vgroups), dim3(256), vlds, h->stream, L, rlog, ptab,
-                       qtab, Vr, st);
-    RMM_TRY(launch_status());
-  }
-  hipLaunchKernelGGL(big_finish_kernel, dim3((unsigned)((l + 255) / 256)), dim3(256), 0, h->stream, l,
-                     L, G0, G1, Vr, evals, V, st, status);
-  ws.off = mark;
-  return launch_status();
+  c.take<double2>((size_t)kJacobiMaxSweeps * (L - 1) * (L / 2));
+  c.take<int>((size_t)l);
+  c.take<int>(1);
+  return c.off + 3 * kAlign;
 }
 
 int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals, double* V,
                int32_t* status, Carver& ws) {
   if (l == 0) return RMM_OK;
   if (l > kBigMaxL) return RMM_ERR_UNSUPPORTED;
-  if (l > kLdsMaxL) return jacobi_eig_big(h, l, G, ldg, evals, V, status, ws);
+  if (l > kLdsMaxL) return jacobi_eig_block(h, l, G, ldg, evals, V, status, ws);
   const int L = (l + 1) & ~1;
   const int npairs = L / 2;
   const size_t mark = ws.off;
