@@ -148,6 +148,8 @@ int rmm_create(rmm_handle* h, int device) {
     c->lds_bytes = (size_t)v;
   if (const char* path = getenv("RMM_TUNE_CACHE")) (void)rmm_autotune_load(c, path);
   (void)noalloc_scratch(device);  // rmm_sketched_lsr_noalloc reports a failed lookup
+  void* flag = nullptr;
+  if (hipHostMalloc(&flag, 64, hipHostMallocDefault) == hipSuccess) c->hflag = static_cast<int*>(flag);
   *h = c;
   return RMM_OK;
 }

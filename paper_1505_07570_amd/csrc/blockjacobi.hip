@@ -2,22 +2,25 @@
 // (the c x c matrix W = K[S, S] of the Nystrom method).
 //
 // The index set is cut into nb blocks of 32 (padded with zero rows and
-// columns, which never rotate).  A sweep pairs the blocks by the circle
-// method (nb - 1 rounds of nb / 2 disjoint block pairs).  In a round, for
-// every pair (I, J):
-//   1. the 64 x 64 subproblem W[IJ, IJ] (IJ = I u J) is copied to LDS and
-//      one cyclic Jacobi sweep of 63 rounds of 32 disjoint rotations is run
-//      on it, with the rotation test and angles of the scalar solver; the
-//      product of its rotations, re-orthogonalized, is the 64 x 64 Q;
-//   2. W[IJ, :] <- Q^T W[IJ, :]  (all pairs at once: their rows are disjoint);
-//   3. W[:, IJ] <- W[:, IJ] Q and V[:, IJ] <- V[:, IJ] Q.
-// So W <- P^T W P and V <- V P with P block orthogonal, and every sweep
-// visits every pair of indices.  Before each sweep a scan decides
-// convergence exactly as the scalar solver does (no off-diagonal element
-// passes the rotation test); after it, all later launches return at once.
-// Then the eigenvalues (the diagonal, descending, ties by index) and V's
-// columns are sorted out.  Compared with one launch per scalar round
-// (l - 1 rounds per sweep), a sweep here is nb - 1 = 31 rounds at l = 1024.
+// columns, which never rotate).  One sweep visits every pair of indices
+// once, in two kinds of steps:
+//   * intra step: the blocks, paired as (0, 1), (2, 3), ..., each rotate the
+//     pairs inside themselves in 31 rounds of 16 disjoint rotations (a
+//     hierarchical order: the two halves of 16 against each other in 16
+//     rounds, then the quarters of each half in 8, and so on);
+//   * nb - 1 cross steps: the blocks are paired by the circle method and each
+//     pair (I, J) rotates every (i in I, j in J) in 32 rounds of 32 disjoint
+//     rotations (i against j = (i + round) mod 32 of J).
+// A step works on the 64 x 64 subproblem W[IJ, IJ] (IJ = I u J) in LDS:
+// rotation angles and the rotation test are those of the scalar solver, and
+// the product Q of the step's rotations, re-orthogonalized, is applied to
+// the whole matrix afterwards by tiles, W[IJ, IJ'] <- Q^T W[IJ, IJ'] Q' and
+// V[:, IJ] <- V[:, IJ] Q (all pairs of a step at once: their index sets are
+// disjoint).  So W <- P^T W P and V <- V P with P block orthogonal.
+// Before each sweep a scan decides convergence exactly as the scalar solver
+// does (no off-diagonal element passes the rotation test).  Then the
+// eigenvalues (the diagonal, descending, ties by index) and V's columns are
+// sorted out.
 #include <math.h>
 
 #include "common.hpp"
@@ -82,6 +85,43 @@ __device__ __forceinline__ bool rot_test(double gpq, double gpp, double gqq, dou
   return fabs(gpq) > abs_tol && fabs(gpq) > 1e-300 && gpq * gpq > 0x1p-104 * fabs(gpp * gqq);
 }
 
+// Reciprocal and reciprocal square root from the hardware seeds refined by
+// two Newton steps (a few ulps; the rotations they feed are re-orthogonalized
+// as a product, so correct rounding is not needed).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double h = 0.5 * x;
+  double y = __builtin_amdgcn_rsq(x);
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return fma(y, fma(-h * y, y, 0.5), y);
+}
+
+// Rotation annihilating gpq of [[gpp, gpq], [gpq, gqq]] when it passes the
+// rotation test (else c = 1, s = t = 0): theta = (gqq - gpp) / (2 gpq),
+// t = sign(theta) / (|theta| + sqrt(theta^2 + 1)), c = 1 / sqrt(t^2 + 1),
+// s = t c.  For |theta| > 2^500, t = 1 / (2 theta) (theta^2 would overflow;
+// |theta| is capped at 2^1000 so that t stays finite and nonzero-safe).
+__device__ __forceinline__ void jacobi_rotation(double gpq, double gpp, double gqq, double abs_tol, double& c,
+                                                double& s, double& t) {
+  const bool rot = rot_test(gpq, gpp, gqq, abs_tol);
+  const double y = rot ? 2.0 * gpq : 1.0;
+  const double theta = (gqq - gpp) * rcp_nr(y);
+  const double at = fabs(theta);
+  const bool big = at > 0x1p500;
+  const double u = fma(theta, theta, 1.0);
+  const double den = big ? 2.0 * fmin(at, 0x1p1000) : at + u * rsq_nr(big ? 1.0 : u);
+  const double tt = copysign(rcp_nr(den), theta);
+  const double cc = rsq_nr(fma(tt, tt, 1.0));
+  t = rot ? tt : 0.0;
+  c = rot ? cc : 1.0;
+  s = rot ? tt * cc : 0.0;
+}
+
 // pending |= an off-diagonal element (a < b < l) passes the rotation test
 __global__ void blk_scan_kernel(int l, int L, const double* __restrict__ W, BlkState* st) {
   if (st->converged) return;
@@ -100,93 +140,139 @@ __global__ void blk_decide_kernel(BlkState* st) {
   st->pending = 0;
 }
 
-// Step 1: one Jacobi sweep on the subproblem of block pair blockIdx.x of
-// round r; D = Q - I (64 x 64, column-major) to Qbuf[pair].
-__global__ __launch_bounds__(256) void blk_inner_kernel(int nb, int r, int L, const double* __restrict__ W,
-                                                        double* __restrict__ Qbuf, const BlkState* st) {
+// Blocks of step pair x: cross steps pair the blocks by the circle method
+// (round r), intra steps take (2x, 2x + 1).
+template <int MODE>
+__device__ __forceinline__ void step_blocks(int x, int r, int nb, int& bi, int& bj) {
+  if (MODE == 0) {
+    circle_pair(x, r, nb, bi, bj);
+  } else {
+    bi = 2 * x;
+    bj = 2 * x + 1;
+  }
+}
+
+// Rotation u (0..31) of round rr of a step on a 64-index subproblem (local
+// indices 0..31 = block I, 32..63 = block J).  Cross (MODE 0, 32 rounds):
+// (u, 32 + (u + rr) mod 32).  Intra (MODE 1, 31 rounds): inside each half of
+// 32, at level h = 16, 8, 4, 2, 1 the groups of 2h split into two halves of
+// h, index a of the first half against (a + rho) mod h of the second, rho <
+// h.
+constexpr int kCrossRounds = kBB;
+constexpr int kIntraRounds = kBB - 1;
+
+template <int MODE>
+__device__ __forceinline__ void step_pair(int u, int rr, int& p, int& q) {
+  if (MODE == 0) {
+    p = u;
+    q = kBB + ((u + rr) & (kBB - 1));
+    return;
+  }
+  int lh, rho;  // log2 h, round within the level
+  if (rr < 16) { lh = 4; rho = rr; }
+  else if (rr < 24) { lh = 3; rho = rr - 16; }
+  else if (rr < 28) { lh = 2; rho = rr - 24; }
+  else if (rr < 30) { lh = 1; rho = rr - 28; }
+  else { lh = 0; rho = 0; }
+  const int h = 1 << lh;
+  const int half = u >> 4, w = u & 15;
+  const int base = half * kBB + ((w >> lh) << (lh + 1));
+  const int a = w & (h - 1);
+  p = base + a;
+  q = base + h + ((a + rho) & (h - 1));
+}
+
+// Step kernel: the rounds of one step on the subproblem of step pair
+// blockIdx.x; D = Q - I (64 x 64, column-major) to Dbuf[pair].
+//
+// Thread (u = tid mod 32, g = tid / 32) computes rotation u of each round
+// and updates the 2 x 2 blocks (u, v) of the subproblem, v = g, g + 8,
+// g + 16, g + 24 (rows {p_u, q_u}, columns {p_v, q_v}: every element once),
+// and rows u and u + 32 of Q at the column pairs v; rotation v comes from
+// lane v of the same wave.  The subproblem is double-buffered in LDS (read
+// one, write the other), so one barrier per round suffices.
+template <int MODE>
+__global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, const double* __restrict__ W,
+                                                       double* __restrict__ Dbuf, const BlkState* st) {
   if (st->converged) return;
-  __shared__ double S[kBS * kBLd];
+  __shared__ double S[2][kBS * kBLd];
   __shared__ double Q[kBS * kBLd];
-  __shared__ double cs[kBB], sn[kBB], tn[kBB];
-  __shared__ int pp[kBB], qq[kBB];
   const int tid = threadIdx.x;
   int bi, bj;
-  circle_pair(blockIdx.x, r, nb, bi, bj);
-  for (int e = tid; e < kBS * kBS; e += 256) {
-    const int a = e % kBS, b = e / kBS;
-    S[a + b * kBLd] = W[gidx(a, bi, bj) + (int64_t)gidx(b, bi, bj) * L];
-    Q[a + b * kBLd] = a == b ? 1.0 : 0.0;
+  step_blocks<MODE>(blockIdx.x, r, nb, bi, bj);
+  {
+    double v[16];  // all loads in flight before the LDS stores
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + 256 * k, a = e % kBS, b = e / kBS;
+      v[k] = W[gidx(a, bi, bj) + (int64_t)gidx(b, bi, bj) * L];
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int e = tid + 256 * k, a = e % kBS, b = e / kBS;
+      S[0][a + b * kBLd] = v[k];
+      Q[a + b * kBLd] = a == b ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   const double abs_tol = st->abs_tol;
-  for (int rr = 0; rr < kBS - 1; ++rr) {
-    if (tid < kBB) {
-      int p, q;
-      circle_pair(tid, rr, kBS, p, q);
-      double c = 1.0, s = 0.0, t = 0.0;
-      const double gpq = S[p + q * kBLd], gpp = S[p + p * kBLd], gqq = S[q + q * kBLd];
-      if (rot_test(gpq, gpp, gqq, abs_tol)) {
-        const double theta = (gqq - gpp) / (2.0 * gpq);
-        t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        c = 1.0 / sqrt(t * t + 1.0);
-        s = t * c;
+  const int u = tid & 31, g = tid >> 5;
+  constexpr int rounds = MODE == 0 ? kCrossRounds : kIntraRounds;
+  for (int rr = 0; rr < rounds; ++rr) {
+    const double* Sc = S[rr & 1];
+    double* Sn = S[(rr & 1) ^ 1];
+    int p, q, pv[4], qv[4];
+    step_pair<MODE>(u, rr, p, q);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) step_pair<MODE>(g + 8 * m, rr, pv[m], qv[m]);
+    // every LDS read of the round first (the compiler cannot tell the stores
+    // below from these addresses)
+    const double gpq = Sc[p + q * kBLd], gpp = Sc[p + p * kBLd], gqq = Sc[q + q * kBLd];
+    double x[4][4], y[4][2][2];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      x[m][0] = Sc[p + pv[m] * kBLd];
+      x[m][1] = Sc[p + qv[m] * kBLd];
+      x[m][2] = Sc[q + pv[m] * kBLd];
+      x[m][3] = Sc[q + qv[m] * kBLd];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        y[m][h][0] = Q[u + 32 * h + pv[m] * kBLd];
+        y[m][h][1] = Q[u + 32 * h + qv[m] * kBLd];
       }
-      pp[tid] = p;
-      qq[tid] = q;
-      cs[tid] = c;
-      sn[tid] = s;
-      tn[tid] = t;
     }
-    __syncthreads();
-    // S <- J^T S J, one 2 x 2 block (pair i rows, pair j columns) per item
-    double v[4][4];
-    int ad[4][4];
+    double c, s, t;
+    jacobi_rotation(gpq, gpp, gqq, abs_tol, c, s, t);
+    double cv[4], sv[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int item = tid + 256 * k;  // 1024 = 32 x 32 block pairs
-      const int i = item & 31, j = item >> 5;
-      const int pi = pp[i], qi = qq[i], pj = pp[j], qj = qq[j];
-      ad[k][0] = pi + pj * kBLd;
-      ad[k][1] = pi + qj * kBLd;
-      ad[k][2] = qi + pj * kBLd;
-      ad[k][3] = qi + qj * kBLd;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) v[k][e] = S[ad[k][e]];
+    for (int m = 0; m < 4; ++m) {
+      cv[m] = __shfl(c, g + 8 * m);
+      sv[m] = __shfl(s, g + 8 * m);
     }
-    __syncthreads();
+    // blocks (u, v): R_u^T X R_v; the rotated block itself (v = u) takes the
+    // scalar solver's update.  A zero rotation (c = 1, s = 0) leaves values
+    // unchanged exactly, so nothing branches on it.
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int item = tid + 256 * k;
-      const int i = item & 31, j = item >> 5;
-      const double ci = cs[i], si = sn[i], cj = cs[j], sj = sn[j];
-      if (i == j) {
-        if (si != 0.0) {
-          const double t = tn[i];
-          S[ad[k][0]] = v[k][0] - t * v[k][1];
-          S[ad[k][3]] = v[k][3] + t * v[k][1];
-          S[ad[k][1]] = 0.0;
-          S[ad[k][2]] = 0.0;
-        }
-        continue;
+    for (int m = 0; m < 4; ++m) {
+      const double y00 = c * x[m][0] - s * x[m][2], y01 = c * x[m][1] - s * x[m][3];
+      const double y10 = s * x[m][0] + c * x[m][2], y11 = s * x[m][1] + c * x[m][3];
+      double z00 = cv[m] * y00 - sv[m] * y01, z01 = sv[m] * y00 + cv[m] * y01;
+      double z10 = cv[m] * y10 - sv[m] * y11, z11 = sv[m] * y10 + cv[m] * y11;
+      if (g + 8 * m == u) {
+        const bool rot = s != 0.0;
+        z00 = rot ? x[m][0] - t * x[m][1] : x[m][0];
+        z11 = rot ? x[m][3] + t * x[m][1] : x[m][3];
+        z01 = rot ? 0.0 : x[m][1];
+        z10 = rot ? 0.0 : x[m][2];
       }
-      const double y00 = ci * v[k][0] - si * v[k][2], y01 = ci * v[k][1] - si * v[k][3];
-      const double y10 = si * v[k][0] + ci * v[k][2], y11 = si * v[k][1] + ci * v[k][3];
-      S[ad[k][0]] = cj * y00 - sj * y01;
-      S[ad[k][1]] = sj * y00 + cj * y01;
-      S[ad[k][2]] = cj * y10 - sj * y11;
-      S[ad[k][3]] = sj * y10 + cj * y11;
-    }
-    // Q <- Q J: row a, pair j
+      Sn[p + pv[m] * kBLd] = z00;
+      Sn[p + qv[m] * kBLd] = z01;
+      Sn[q + pv[m] * kBLd] = z10;
+      Sn[q + qv[m] * kBLd] = z11;
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int item = tid + 256 * k;  // 2048 = 64 rows x 32 pairs
-      const int a = item & 63, j = item >> 6;
-      const double c = cs[j], s = sn[j];
-      if (s != 0.0) {
-        const int pj = pp[j], qj = qq[j];
-        const double x = Q[a + pj * kBLd], y = Q[a + qj * kBLd];
-        Q[a + pj * kBLd] = c * x - s * y;
-        Q[a + qj * kBLd] = s * x + c * y;
+      for (int h = 0; h < 2; ++h) {
+        Q[u + 32 * h + pv[m] * kBLd] = cv[m] * y[m][h][0] - sv[m] * y[m][h][1];
+        Q[u + 32 * h + qv[m] * kBLd] = sv[m] * y[m][h][0] + cv[m] * y[m][h][1];
       }
     }
     __syncthreads();
@@ -196,106 +282,179 @@ __global__ __launch_bounds__(256) void blk_inner_kernel(int nb, int r, int L, co
   // re-orthogonalized, Q <- Q (I - E / 2) with E = Q^T Q - I (orthogonal to
   // second order in E), and stored as D = Q - I: the updates then add a
   // small correction D^T W or W D to W, rounding relative to its size.
-  const int a = tid & 63;
-  double acc[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+  double* E = S[0];
+  const int a1 = tid & 15, b0 = (tid >> 4) * 4;  // rows a1 + 16 i, columns b0 + j
+  double acc[4][4] = {};
   for (int t = 0; t < kBS; ++t) {
-    const double qa = Q[t + a * kBLd];
+    double qa[4], qb[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = fma(qa, Q[t + ((tid >> 6) + 4 * k) * kBLd], acc[k]);
+    for (int i = 0; i < 4; ++i) {
+      qa[i] = Q[t + (a1 + 16 * i) * kBLd];
+      qb[i] = Q[t + (b0 + i) * kBLd];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(qa[i], qb[j], acc[i][j]);
   }
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int b = (tid >> 6) + 4 * k;
-    S[a + b * kBLd] = acc[k] - (a == b ? 1.0 : 0.0);  // E, symmetric
-    acc[k] = 0.0;
-  }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      E[a1 + 16 * i + (b0 + j) * kBLd] = acc[i][j] - (a1 + 16 * i == b0 + j ? 1.0 : 0.0);
+      acc[i][j] = 0.0;
+    }
   __syncthreads();
   for (int t = 0; t < kBS; ++t) {
-    const double qa = Q[a + t * kBLd];
+    double qa[4], eb[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = fma(qa, S[t + ((tid >> 6) + 4 * k) * kBLd], acc[k]);
-  }
-  double* out = Qbuf + (size_t)blockIdx.x * kBS * kBS;
+    for (int i = 0; i < 4; ++i) {
+      qa[i] = Q[a1 + 16 * i + t * kBLd];
+      eb[i] = E[t + (b0 + i) * kBLd];
+    }
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int b = (tid >> 6) + 4 * k;
-    out[a + b * kBS] = (Q[a + b * kBLd] - (a == b ? 1.0 : 0.0)) - 0.5 * acc[k];
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(qa[i], eb[j], acc[i][j]);
   }
+  double* out = Dbuf + (size_t)blockIdx.x * kBS * kBS;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = a1 + 16 * i, b = b0 + j;
+      out[a + b * kBS] = (Q[a + b * kBLd] - (a == b ? 1.0 : 0.0)) - 0.5 * acc[i][j];
+    }
 }
 
-// Step 2: W[IJ, c0:c0+64] <- W[IJ, c0:c0+64] + D^T W[IJ, c0:c0+64]
-// (= Q^T W[IJ, ...]) for pair blockIdx.x, column tile blockIdx.y (in place:
-// the tile is read into LDS first).
-__global__ __launch_bounds__(256) void blk_rows_kernel(int nb, int r, int L, double* __restrict__ W,
-                                                       const double* __restrict__ Qbuf, const BlkState* st) {
-  if (st->converged) return;
-  __shared__ double Qs[kBS * kBLd];
-  __shared__ double T[kBS * kBLd];
-  const int tid = threadIdx.x;
-  int bi, bj;
-  circle_pair(blockIdx.x, r, nb, bi, bj);
-  const double* Qg = Qbuf + (size_t)blockIdx.x * kBS * kBS;
-  const int c0 = blockIdx.y * kBS;
-  for (int e = tid; e < kBS * kBS; e += 256) {
-    const int a = e % kBS, b = e / kBS;
-    Qs[a + b * kBLd] = Qg[e];
-    T[a + b * kBLd] = W[gidx(a, bi, bj) + (int64_t)(c0 + b) * L];
-  }
-  __syncthreads();
-  // thread: output rows a = tid & 63, columns b = (tid >> 6) + 4 k
-  const int a = tid & 63;
-  double acc[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-  for (int t = 0; t < kBS; ++t) {
-    const double qa = Qs[t + a * kBLd];  // Q^T[a][t]
-#pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = fma(qa, T[t + ((tid >> 6) + 4 * k) * kBLd], acc[k]);
-  }
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int b = (tid >> 6) + 4 * k;
-    W[gidx(a, bi, bj) + (int64_t)(c0 + b) * L] = T[a + b * kBLd] + acc[k];
-  }
-}
+// Update of W and V after a step: W <- P^T W P, V <- V P with P the block
+// orthogonal matrix of the step's Q = I + D.  Workgroup (x, y): for y < np
+// the W tile (rows IJ_y, columns IJ_x), Z = (I + D_y)^T X (I + D_x) formed
+// as Y = X + D_y^T X, Z = Y + Y D_x; for y >= np the V tile (rows
+// 64 (y - np) .. + 64, columns IJ_x), Z = X + X D_x.  The tiles partition W
+// and V, so each is updated in place.  Thread (a1 = tid mod 16,
+// b0 = 4 (tid / 16)) owns rows a1, a1 + 16, a1 + 32, a1 + 48 and columns
+// b0 .. b0 + 3 of the tile; per summation index that is one read per owned
+// row and two 16-byte reads of the owned columns.
+constexpr int kULd = kBS + 2;  // even: 16-byte aligned rows; 2-way bank conflicts on the fills
 
-// Step 3: X[r0:r0+64, IJ] <- X[r0:r0+64, IJ] + X[r0:r0+64, IJ] D (= X Q) for
-// X = W (blockIdx.z = 0) and V (1)
-__global__ __launch_bounds__(256) void blk_cols_kernel(int nb, int r, int L, double* __restrict__ W,
-                                                       double* __restrict__ V, const double* __restrict__ Qbuf,
-                                                       const BlkState* st) {
+template <int MODE>
+__global__ __launch_bounds__(256) void blk_update_kernel(int nb, int r, int L, double* __restrict__ W,
+                                                         double* __restrict__ V, const double* __restrict__ Dbuf,
+                                                         const BlkState* st) {
   if (st->converged) return;
-  __shared__ double Qs[kBS * kBLd];
-  __shared__ double T[kBS * kBLd];
-  const int tid = threadIdx.x;
-  int bi, bj;
-  circle_pair(blockIdx.x, r, nb, bi, bj);
-  double* X = blockIdx.z == 0 ? W : V;
-  const double* Qg = Qbuf + (size_t)blockIdx.x * kBS * kBS;
-  const int r0 = blockIdx.y * kBS;
-  for (int e = tid; e < kBS * kBS; e += 256) {
-    const int a = e % kBS, b = e / kBS;
-    Qs[a + b * kBLd] = Qg[e];
-    T[a + b * kBLd] = X[(r0 + a) + (int64_t)gidx(b, bi, bj) * L];
-  }
-  __syncthreads();
-  // thread: output row a = tid & 63, columns b = (tid >> 6) + 4 k
-  const int a = tid & 63;
-  double acc[16];
+  __shared__ __align__(16) double B0[kBS * kULd];
+  __shared__ __align__(16) double B1[kBS * kULd];
+  const int np = nb / 2;
+  const int tid = threadIdx.x, a1 = tid & 15, b0 = (tid >> 4) * 4;
+  int xi, xj;
+  step_blocks<MODE>(blockIdx.x, r, nb, xi, xj);
+  const double* Dx = Dbuf + (size_t)blockIdx.x * kBS * kBS;
+  double yv[4][4];
+  double* X;
+  int64_t row_of[4];  // global row of owned row i
+  if ((int)blockIdx.y < np) {
+    int yi, yj;
+    step_blocks<MODE>(blockIdx.y, r, nb, yi, yj);
+    const double* Dy = Dbuf + (size_t)blockIdx.y * kBS * kBS;
+    X = W;
+    // B0[b + t ld] = X(t, b) = W[IJ_y(t), IJ_x(b)], B1[a + t ld] = D_y(t, a)
+    {
+      double v[16], d[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) acc[k] = 0.0;
+      for (int k = 0; k < 16; ++k) {
+        const int e = tid + 256 * k, t = e % kBS, b = e / kBS;
+        v[k] = W[gidx(t, yi, yj) + (int64_t)gidx(b, xi, xj) * L];
+        d[k] = Dy[e];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = tid + 256 * k, t = e % kBS, b = e / kBS;
+        B0[b + t * kULd] = v[k];
+        B1[b + t * kULd] = d[k];
+      }
+    }
+    __syncthreads();
+    double acc[4][4] = {};
+    for (int t = 0; t < kBS; ++t) {
+      double da[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) da[i] = B1[a1 + 16 * i + t * kULd];
+      const double2 x01 = *reinterpret_cast<const double2*>(B0 + b0 + t * kULd);
+      const double2 x23 = *reinterpret_cast<const double2*>(B0 + b0 + 2 + t * kULd);
+      const double xb[4] = {x01.x, x01.y, x23.x, x23.y};
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fma(da[i], xb[j], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      row_of[i] = gidx(a1 + 16 * i, yi, yj);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yv[i][j] = B0[b0 + j + (a1 + 16 * i) * kULd] + acc[i][j];
+    }
+    __syncthreads();
+    // B0[a + t ld] = Y(a, t), B1[b + t ld] = D_x(t, b)
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) B0[a1 + 16 * i + (b0 + j) * kULd] = yv[i][j];
+    {
+      double d[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) d[k] = Dx[tid + 256 * k];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = tid + 256 * k, t = e % kBS, b = e / kBS;
+        B1[b + t * kULd] = d[k];
+      }
+    }
+    __syncthreads();
+  } else {
+    const int r0 = ((int)blockIdx.y - np) * kBS;
+    X = V;
+    // B0[a + t ld] = V[r0 + a, IJ_x(t)], B1[b + t ld] = D_x(t, b)
+    {
+      double v[16], d[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = tid + 256 * k, a = e % kBS, t = e / kBS;
+        v[k] = V[(r0 + a) + (int64_t)gidx(t, xi, xj) * L];
+        d[k] = Dx[e];
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int e = tid + 256 * k, a = e % kBS, t = e / kBS;
+        B0[a + t * kULd] = v[k];
+        B1[t + a * kULd] = d[k];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      row_of[i] = r0 + a1 + 16 * i;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) yv[i][j] = B0[a1 + 16 * i + (b0 + j) * kULd];
+    }
+  }
+  double acc[4][4] = {};
   for (int t = 0; t < kBS; ++t) {
-    const double xa = T[a + t * kBLd];
+    double ya[4];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) acc[k] = fma(xa, Qs[t + ((tid >> 6) + 4 * k) * kBLd], acc[k]);
+    for (int i = 0; i < 4; ++i) ya[i] = B0[a1 + 16 * i + t * kULd];
+    const double2 d01 = *reinterpret_cast<const double2*>(B1 + b0 + t * kULd);
+    const double2 d23 = *reinterpret_cast<const double2*>(B1 + b0 + 2 + t * kULd);
+    const double db[4] = {d01.x, d01.y, d23.x, d23.y};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(ya[i], db[j], acc[i][j]);
   }
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int b = (tid >> 6) + 4 * k;
-    X[(r0 + a) + (int64_t)gidx(b, bi, bj) * L] = T[a + b * kBLd] + acc[k];
-  }
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) X[row_of[i] + (int64_t)gidx(b0 + j, xi, xj) * L] = yv[i][j] + acc[i][j];
 }
 
 // eigenvalues (diagonal entries of the first l indices), descending with
@@ -338,6 +497,28 @@ size_t jacobi_block_workspace(int l) {
   return c.off + 5 * kAlign;
 }
 
+namespace {
+
+// Enqueue one step (rotations, then the update of W and V) of all pairs.
+template <int MODE>
+int enqueue_step(const rmm_ctx* h, int nb, int r, int L, double* W, double* Vw, double* Db, BlkState* st) {
+  const unsigned np = (unsigned)(nb / 2);
+  hipLaunchKernelGGL(blk_step_kernel<MODE>, dim3(np), dim3(256), 0, h->stream, nb, r, L, W, Db, st);
+  hipLaunchKernelGGL(blk_update_kernel<MODE>, dim3(np, 2 * np), dim3(256), 0, h->stream, nb, r, L, W, Vw, Db,
+                     st);
+  return launch_status();
+}
+
+struct EventPair {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~EventPair() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
+}  // namespace
+
 int jacobi_eig_block(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals, double* V,
                      int32_t* status, Carver& ws) {
   const int nb = ((l + kBB - 1) / kBB + 1) & ~1;
@@ -346,7 +527,7 @@ int jacobi_eig_block(const rmm_ctx* h, int l, const double* G, int64_t ldg, doub
   const size_t mark = ws.off;
   double* W = ws.take<double>((size_t)L * L);
   double* Vw = ws.take<double>((size_t)L * L);
-  double* Qb = ws.take<double>((size_t)np * kBS * kBS);
+  double* Db = ws.take<double>((size_t)np * kBS * kBS);
   BlkState* st = ws.take<BlkState>(1);
   int* perm = ws.take<int>((size_t)l);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
@@ -355,20 +536,33 @@ int jacobi_eig_block(const rmm_ctx* h, int l, const double* G, int64_t ldg, doub
                      G, ldg, W, Vw, st);
   hipLaunchKernelGGL(blk_tol_kernel, dim3(1), dim3(256), 0, h->stream, l, L, W, st);
   RMM_TRY(launch_status());
+  // Sweeps stop on the device once converged (later launches return at
+  // once).  Outside stream capture the host also stops enqueueing them: each
+  // sweep's decision is copied to pinned host memory and read one sweep
+  // later, so the device always has a sweep queued meanwhile.
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  RMM_HIP(hipStreamIsCapturing(h->stream, &cap));
+  EventPair ev;
+  const bool early = h->hflag && cap == hipStreamCaptureStatusNone &&
+                     hipEventCreateWithFlags(&ev.e[0], hipEventDisableTiming) == hipSuccess &&
+                     hipEventCreateWithFlags(&ev.e[1], hipEventDisableTiming) == hipSuccess;
   const unsigned sgroups = (unsigned)(((int64_t)l * l + 255) / 256);
   for (int sweep = 0; sweep <= kBMaxSweeps; ++sweep) {
     hipLaunchKernelGGL(blk_scan_kernel, dim3(sgroups), dim3(256), 0, h->stream, l, L, W, st);
     hipLaunchKernelGGL(blk_decide_kernel, dim3(1), dim3(1), 0, h->stream, st);
     RMM_TRY(launch_status());
     if (sweep == kBMaxSweeps) break;  // the last scan only decides convergence
-    for (int r = 0; r < nb - 1; ++r) {
-      hipLaunchKernelGGL(blk_inner_kernel, dim3((unsigned)np), dim3(256), 0, h->stream, nb, r, L, W, Qb, st);
-      hipLaunchKernelGGL(blk_rows_kernel, dim3((unsigned)np, (unsigned)(L / kBS)), dim3(256), 0, h->stream,
-                         nb, r, L, W, Qb, st);
-      hipLaunchKernelGGL(blk_cols_kernel, dim3((unsigned)np, (unsigned)(L / kBS), 2u), dim3(256), 0,
-                         h->stream, nb, r, L, W, Vw, Qb, st);
+    if (early) {
+      RMM_HIP(hipMemcpyAsync(h->hflag + (sweep & 1), &st->converged, sizeof(int), hipMemcpyDeviceToHost,
+                             h->stream));
+      RMM_HIP(hipEventRecord(ev.e[sweep & 1], h->stream));
+      if (sweep > 0) {
+        RMM_HIP(hipEventSynchronize(ev.e[(sweep - 1) & 1]));
+        if (h->hflag[(sweep - 1) & 1]) break;
+      }
     }
-    RMM_TRY(launch_status());
+    RMM_TRY(enqueue_step<1>(h, nb, 0, L, W, Vw, Db, st));
+    for (int r = 0; r < nb - 1; ++r) RMM_TRY(enqueue_step<0>(h, nb, r, L, W, Vw, Db, st));
   }
   hipLaunchKernelGGL(blk_rank_kernel, dim3((unsigned)((l + 255) / 256)), dim3(256), 0, h->stream, l, L, W,
                      evals, perm, st, status);

@@ -25,9 +25,13 @@ struct rmm_ctx {
   bool ktime = false;
   mutable bool kmarked = false;  // both events recorded since timing was enabled
   hipEvent_t kev[2] = {nullptr, nullptr};
+  // pinned host words through which iterative solvers report convergence
+  // to the host (null if the allocation failed)
+  int* hflag = nullptr;
   ~rmm_ctx() {
     for (hipEvent_t e : kev)
       if (e) (void)hipEventDestroy(e);
+    if (hflag) (void)hipHostFree(hflag);
   }
 };
 
