@@ -9,14 +9,15 @@
 // row index i = i_hi L + i_lo,
 //     H_N[r, i] = H_{N/L}[r_hi, i_hi] * H_L[r_lo, i_lo],
 //     (H_N x)[r] = sum_{i_hi} (-1)^popcount(r_hi & i_hi) (H_L x_{i_hi})[r_lo].
-// A workgroup of 4 waves takes 4 consecutive L-row chunks of one column:
-// each wave loads its chunk (16-byte loads, 4 rows per lane), applies D,
-// runs the 12-stage butterfly network in registers with one LDS transpose
-// and leaves z = H_L x_chunk in its LDS buffer; the workgroup then adds the
-// four chunks' signed contributions to the s sampled rows, whose
-// accumulators are spread over its 256 threads.  N < L is handled by zero
-// padding to L: (H_L [x; 0])[r] equals (H_N x)[r] for r < N.  Per-workgroup
-// partial sums are reduced in a fixed order.
+// A workgroup of WV waves (8 for fp32, 4 for fp64) takes WV consecutive
+// L-row chunks of one column: each wave loads its chunk (16-byte loads, 4
+// rows per lane), applies D (sign bits from a table generated once per call,
+// since they depend on the row only), runs the 12-stage butterfly network in
+// registers with one LDS transpose and leaves z = H_L x_chunk in its LDS
+// buffer; the workgroup then adds the WV chunks' signed contributions to the
+// s sampled rows, whose accumulators are spread over its threads.  N < L is
+// handled by zero padding to L: (H_L [x; 0])[r] equals (H_N x)[r] for r < N.
+// Per-workgroup partial sums are reduced in a fixed order.
 #include "common.hpp"
 #include "rng.hpp"
 
@@ -33,15 +34,16 @@ constexpr int kL = 1 << kLogL;  // 4096 rows per chunk, 64 values per lane
 __device__ __forceinline__ uint32_t swz(uint32_t r) { return r ^ (((r >> 8) & 7u) << 2); }
 
 template <typename T>
-__device__ __forceinline__ T flip(T x, uint32_t bit);
+__device__ __forceinline__ T flip(T x, uint32_t w);
+// toggles the IEEE sign bit of x when bit 0 of w is set (higher bits of w
+// are shifted out)
 template <>
-__device__ __forceinline__ float flip<float>(float x, uint32_t bit) {
-  // adding bit << 31 toggles the IEEE sign bit when bit is 0 or 1
-  return __uint_as_float(__float_as_uint(x) + (bit << 31));
+__device__ __forceinline__ float flip<float>(float x, uint32_t w) {
+  return __uint_as_float(__float_as_uint(x) + (w << 31));
 }
 template <>
-__device__ __forceinline__ double flip<double>(double x, uint32_t bit) {
-  const uint64_t u = (uint64_t)__double_as_longlong(x) + ((uint64_t)bit << 63);
+__device__ __forceinline__ double flip<double>(double x, uint32_t w) {
+  const uint64_t u = (uint64_t)__double_as_longlong(x) + ((uint64_t)w << 63);
   return __longlong_as_double((long long)u);
 }
 
@@ -53,43 +55,67 @@ __device__ __forceinline__ void bfly(T& a, T& b) {
   b = y;
 }
 
-// One workgroup = 4 waves working on 4 consecutive chunks ("a quad") of the
-// same column; unit = (column, quad).  Wave w transforms chunk 4 q + w into
-// its own LDS buffer; then the 256 threads add, for the samples they own
-// (t = tid + 256 k), the quad's contribution
-//   sum_w (-1)^popcount(r_hi & (4 q + w)) z_w[r_lo]
-//   = (-1)^popcount((r_hi >> 2) & q) * [(z0 + a z1) + b (z2 + a z3)],
-// a = (-1)^{bit 0 of r_hi}, b = (-1)^{bit 1 of r_hi}.
-template <typename T, int SPQ, bool VEC>
+// LDS word address of row r of a chunk in the combine layout: after the
+// second butterfly phase lane (a | b' << 2) holds rows a + 4 i + 256 b' in
+// x[i]; x[4 j .. 4 j + 3] go to one 16-byte store at word
+// 4 (lane + 64 j), so the wave's stores cover 1 KiB contiguously.
+__device__ __forceinline__ uint32_t zaddr(uint32_t r) {
+  const uint32_t a = r & 3u, i = (r >> 2) & 63u, bp = r >> 8;
+  return (i & 3u) + 4u * ((a | (bp << 2)) + 64u * (i >> 2));
+}
+
+template <typename T>
+__device__ __forceinline__ T xor_sign(T x, uint32_t mask);
+template <>
+__device__ __forceinline__ float xor_sign<float>(float x, uint32_t mask) {
+  return __uint_as_float(__float_as_uint(x) ^ mask);
+}
+template <>
+__device__ __forceinline__ double xor_sign<double>(double x, uint32_t mask) {
+  return __longlong_as_double(__double_as_longlong(x) ^ ((long long)mask << 32));
+}
+
+// One workgroup = WV waves working on WV consecutive chunks ("a group") of
+// the same column; unit = (column, group).  Wave w transforms chunk WV g + w
+// into its own LDS buffer; then the threads add, for the samples they own
+// (t = tid + 64 WV k), the group's contribution
+//   sum_w (-1)^popcount(r_hi & (WV g + w)) z_w[r_lo]
+//   = (-1)^popcount((r_hi >> LW) & g) * sum_w (-1)^popcount((r_hi mod WV) & w) z_w[r_lo],
+// the inner sum a WV-point Walsh-Hadamard combination whose sign bits are
+// fixed per sample.
+template <typename T, int WV, int SPQ, bool VEC>
 __device__ __forceinline__ void srht_body(const T* __restrict__ A, int64_t lda,
                                           const T* __restrict__ bcol, int n, PanelPlan plan,
-                                          const uint32_t* __restrict__ idx, uint64_t seed,
+                                          const uint32_t* __restrict__ idx,
+                                          const uint32_t* __restrict__ signs,
                                           T* __restrict__ partials) {
+  constexpr int LW = WV == 8 ? 3 : 2;
+  constexpr int NT = 64 * WV;
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   T* buf = reinterpret_cast<T*>(smem) + (size_t)wave * kL;  // this wave's chunk
-  uint32_t* sgn = reinterpret_cast<uint32_t*>(smem + 4 * kL * sizeof(T)) + wave * 128;
+  uint32_t* sgn = reinterpret_cast<uint32_t*>(smem + WV * kL * sizeof(T)) + wave * 128;
   const int64_t blk = blockIdx.x;
   const int64_t u0 = plan_start(plan, blk);
   const int64_t u1 = plan_start(plan, blk + 1);
   const int s = plan.s;
-  const int64_t nquads = plan.nchunks;  // plan chunk = 4 L rows
+  const int64_t ngroups = plan.nchunks;  // plan chunk = WV L rows
 
-  // owned samples: packed byte address of z[r_lo] (bits 0..14) and r_hi >> 2 (bits 16..)
-  // with bits 0 and 1 of r_hi kept in pa (bit 31) and pb (bit 31) form on the fly
+  // owned samples: word address of z[r_lo] in the combine layout times 4
+  // (bits 0..13), r_hi mod WV (bits 14 ..), r_hi >> LW (bits 14 + LW ..)
   uint32_t pk[SPQ];
   T acc[SPQ];
 #pragma unroll
   for (int k = 0; k < SPQ; ++k) {
-    const int t = tid + 256 * k;
+    const int t = tid + NT * k;
     const uint32_t r = t < s ? idx[t] : 0u;
     const uint32_t hi = r >> kLogL;
-    pk[k] = ((hi >> 2) << 16) | ((hi & 3u) << 14) | (swz(r & (kL - 1)) * 4u);
+    pk[k] = ((hi >> LW) << (14 + LW)) | ((hi & (WV - 1u)) << 14) | (zaddr(r & (kL - 1)) * 4u);
     acc[k] = T(0);
   }
-  // lane-constant parts of the swizzled addresses (swz only touches bits 2..4)
+  // lane-constant parts of the swizzled transpose addresses (swz only touches bits 2..4)
   const uint32_t a = lane & 3u, bq = (uint32_t)lane >> 2;
   uint32_t woff[8], roff[8];
 #pragma unroll
@@ -98,10 +124,10 @@ __device__ __forceinline__ void srht_body(const T* __restrict__ A, int64_t lda,
     roff[i] = a + 256u * bq + 4u * ((uint32_t)i ^ (bq & 7u));
   }
 
-  T x[64];
-  auto load_chunk = [&](int64_t u) {
-    const int64_t j = u / nquads;
-    const int64_t c = (u - j * nquads) * 4 + wave;
+  T xa[64];
+  auto load_chunk = [&](int64_t u, T (&x)[64]) {
+    const int64_t j = u / ngroups;
+    const int64_t c = (u - j * ngroups) * WV + wave;
     const int64_t r0 = c * kL;
     const T* col = (j < n) ? A + j * lda : bcol;
     if (VEC && r0 + kL <= plan.m) {
@@ -128,38 +154,46 @@ __device__ __forceinline__ void srht_body(const T* __restrict__ A, int64_t lda,
     }
   };
 
+  // the 128 sign words of unit u's chunk, loaded along with its rows
+  auto load_signs = [&](int64_t u) {
+    const int64_t j = u / ngroups;
+    const int64_t r0 = ((u - j * ngroups) * WV + wave) * kL;
+    return lane < 32 ? reinterpret_cast<const uint4*>(signs + (r0 >> 5))[lane] : make_uint4(0u, 0u, 0u, 0u);
+  };
   int64_t cur = -1;
-  if (u0 < u1) load_chunk(u0);
+  T (&x)[64] = xa;
+  uint4 sw = make_uint4(0u, 0u, 0u, 0u);
+  if (u0 < u1) {
+    sw = load_signs(u0);
+    load_chunk(u0, x);
+  }
   for (int64_t u = u0; u < u1; ++u) {
-    const int64_t j = u / nquads;
-    const int64_t q = u - j * nquads;
+    const int64_t j = u / ngroups;
+    const int64_t g = u - j * ngroups;
     if (j != cur) {
       if (cur >= 0) {
         T* dst = partials + (blk + cur) * plan.slot_elems;
 #pragma unroll
         for (int k = 0; k < SPQ; ++k) {
-          const int t = tid + 256 * k;
+          const int t = tid + NT * k;
           if (t < s) dst[t] = acc[k];
           acc[k] = T(0);
         }
       }
       cur = j;
     }
-    const int64_t r0 = (q * 4 + wave) * kL;
-    // signs: 32 Philox blocks of 128 rows cover the chunk (rows beyond m are zero anyway)
-    if (lane < 32) {
-      const Words4 w = philox_at((uint64_t)(r0 >> 7) + lane, TAG_SRHT_SIGN, 0, seed);
-      *reinterpret_cast<uint4*>(sgn + 4 * lane) = make_uint4(w.w[0], w.w[1], w.w[2], w.w[3]);
-    }
+    if (lane < 32) reinterpret_cast<uint4*>(sgn)[lane] = sw;
     wave_lds_sync();
     {
+      // row 4 lane + e + 256 k: bit 4 (lane mod 8) + e of word 4 (2 k + lane / 32) + (lane mod 32) / 8;
+      // (w >> e) << 31 keeps that bit alone at the sign position
       const int wsel = (lane & 31) >> 3;
       const uint32_t sh = 4u * (lane & 7);
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const uint32_t word = sgn[4 * (2 * k + (lane >> 5)) + wsel] >> sh;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[4 * k + e] = flip<T>(x[4 * k + e], (word >> e) & 1u);
+        for (int e = 0; e < 4; ++e) x[4 * k + e] = flip<T>(x[4 * k + e], word >> e);
       }
     }
     // butterflies on row bits 0,1 (e) and 8..11 (k): register index bits 0..5
@@ -192,24 +226,36 @@ __device__ __forceinline__ void srht_body(const T* __restrict__ A, int64_t lda,
     }
     wave_lds_sync();
 #pragma unroll
-    for (int i = 0; i < 64; ++i) buf[roff[i & 7] + 32 * (i >> 3)] = x[i];
+    for (int jj = 0; jj < 16; ++jj) {
+      T* p = buf + 4 * (lane + 64 * jj);
+      if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) =
+            make_float4(x[4 * jj], x[4 * jj + 1], x[4 * jj + 2], x[4 * jj + 3]);
+      } else {
+        *reinterpret_cast<double2*>(p) = make_double2(x[4 * jj], x[4 * jj + 1]);
+        *reinterpret_cast<double2*>(p + 2) = make_double2(x[4 * jj + 2], x[4 * jj + 3]);
+      }
+    }
     // the registers are free again: the next unit's loads fly during the combine
-    if (u + 1 < u1) load_chunk(u + 1);
+    if (u + 1 < u1) {
+      sw = load_signs(u + 1);
+      load_chunk(u + 1, x);
+    }
     __syncthreads();
-    const uint32_t qmask = (uint32_t)q << 16;
+    const uint32_t gmask = (uint32_t)g << (14 + LW);
 #pragma unroll
     for (int k = 0; k < SPQ; ++k) {
       const unsigned char* zb = smem + (pk[k] & 0x3FFFu) * (sizeof(T) / 4);
-      const T z0 = *reinterpret_cast<const T*>(zb);
-      const T z1 = *reinterpret_cast<const T*>(zb + kL * sizeof(T));
-      const T z2 = *reinterpret_cast<const T*>(zb + 2 * kL * sizeof(T));
-      const T z3 = *reinterpret_cast<const T*>(zb + 3 * kL * sizeof(T));
-      const uint32_t ba = (pk[k] >> 14) & 1u, bb = (pk[k] >> 15) & 1u;
-      const T lo = z0 + flip<T>(z1, ba);
-      const T hi = z2 + flip<T>(z3, ba);
-      const T uq = lo + flip<T>(hi, bb);
-      const uint32_t par = __builtin_popcount(pk[k] & qmask) & 1u;
-      acc[k] += flip<T>(uq, par);
+      T z[WV];
+#pragma unroll
+      for (int w = 0; w < WV; ++w) z[w] = *reinterpret_cast<const T*>(zb + (size_t)w * kL * sizeof(T));
+#pragma unroll
+      for (int e = 0; e < LW; ++e)
+#pragma unroll
+        for (int w = 0; w < WV; w += 2 << e)
+          z[w] = z[w] + xor_sign<T>(z[w + (1 << e)], (pk[k] >> (14 + e)) << 31);
+      const uint32_t par = __builtin_popcount(pk[k] & gmask);
+      acc[k] += flip<T>(z[0], par);
     }
     __syncthreads();
   }
@@ -217,50 +263,63 @@ __device__ __forceinline__ void srht_body(const T* __restrict__ A, int64_t lda,
     T* dst = partials + (blk + cur) * plan.slot_elems;
 #pragma unroll
     for (int k = 0; k < SPQ; ++k) {
-      const int t = tid + 256 * k;
+      const int t = tid + NT * k;
       if (t < s) dst[t] = acc[k];
     }
   }
 }
 
-// two workgroups per CU for fp32 with s <= 4096; otherwise the registers of
-// one wave per SIMD (the fp64 chunk buffers leave room for one workgroup anyway)
-template <typename T, int SPQ, bool VEC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void srht_kernel2(
-    const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
-    const uint32_t* __restrict__ idx, uint64_t seed, T* __restrict__ partials) {
-  srht_body<T, SPQ, VEC>(A, lda, bcol, n, plan, idx, seed, partials);
+// fp32 with s <= 4096: two workgroups per CU (64 KiB of chunk buffers
+// each), so that one workgroup's transforms overlap the other's combine;
+// otherwise the registers of one wave per SIMD
+template <typename T, int SPQ>
+constexpr int srht_wpe() {
+  return sizeof(T) == 4 && SPQ <= 16 ? 2 : 1;
 }
-template <typename T, int SPQ, bool VEC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void srht_kernel1(
+template <typename T, int WV, int SPQ, bool VEC>
+__global__ __launch_bounds__(64 * WV) __attribute__((amdgpu_waves_per_eu(srht_wpe<T, SPQ>(),
+                                                                         srht_wpe<T, SPQ>()))) void srht_kernel(
     const T* __restrict__ A, int64_t lda, const T* __restrict__ bcol, int n, PanelPlan plan,
-    const uint32_t* __restrict__ idx, uint64_t seed, T* __restrict__ partials) {
-  srht_body<T, SPQ, VEC>(A, lda, bcol, n, plan, idx, seed, partials);
+    const uint32_t* __restrict__ idx, const uint32_t* __restrict__ signs, T* __restrict__ partials) {
+  srht_body<T, WV, SPQ, VEC>(A, lda, bcol, n, plan, idx, signs, partials);
+}
+
+// signs[4 b + w] = word w of Philox block (b, TAG_SRHT_SIGN, 0): bit t of
+// word w is the sign bit of row 128 b + 32 w + t
+__global__ void srht_signs_kernel(int64_t blocks, uint64_t seed, uint32_t* __restrict__ signs) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= blocks) return;
+  const Words4 w = philox_at((uint64_t)b, TAG_SRHT_SIGN, 0, seed);
+  reinterpret_cast<uint4*>(signs)[b] = make_uint4(w.w[0], w.w[1], w.w[2], w.w[3]);
+}
+
+template <typename T>
+constexpr int srht_waves() {
+  return 4;
 }
 
 template <typename T>
 size_t srht_lds() {
-  return 4 * (size_t)kL * sizeof(T) + 4 * 512;
+  return (size_t)srht_waves<T>() * ((size_t)kL * sizeof(T) + 512);
 }
 
 PanelPlan srht_plan(const rmm_ctx* h, int64_t m, int ncols, int s, size_t tsize) {
-  const size_t lds = 4 * (size_t)kL * tsize + 4 * 512;
-  int per_cu = (int)(160 * 1024 / lds);
-  if (per_cu > 2) per_cu = 2;
-  if (per_cu < 1) per_cu = 1;
-  return make_plan(m, ncols, 1, s, s, 4 * (int64_t)kL, h->cus * per_cu);
+  return make_plan(m, ncols, 1, s, s, 4 * (int64_t)kL, h->cus * (tsize == 4 ? 2 : 1));
 }
 
+// rows covered by the sign table: whole groups of chunks
+int64_t srht_sign_rows(const PanelPlan& plan) { return plan.nchunks * plan.chunk; }
+
 template <typename T, int SPQ, bool VEC>
-int launch_srht(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n,
-                const PanelPlan& plan, const uint32_t* idx, uint64_t seed, T* partials) {
-  constexpr bool two = sizeof(T) == 4 && SPQ <= 16;
-  auto kern = two ? srht_kernel2<T, SPQ, VEC> : srht_kernel1<T, SPQ, VEC>;
+int launch_srht(const rmm_ctx* h, const T* A, int64_t lda, const T* b, int n, const PanelPlan& plan,
+                const uint32_t* idx, const uint32_t* signs, T* partials) {
+  constexpr int WV = srht_waves<T>();
+  auto kern = srht_kernel<T, WV, SPQ, VEC>;
   const size_t lds = srht_lds<T>();
   RMM_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds));
   ktime_mark(h, 0);
-  hipLaunchKernelGGL(kern, dim3(plan.G), dim3(256), lds, h->stream, A, lda, b, n, plan, idx, seed,
+  hipLaunchKernelGGL(kern, dim3(plan.G), dim3(64 * WV), lds, h->stream, A, lda, b, n, plan, idx, signs,
                      partials);
   ktime_mark(h, 1);
   return launch_status();
@@ -276,6 +335,7 @@ size_t srht_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s) {
   const PanelPlan plan = srht_plan(h, m, ncols, (int)s, sizeof(T));
   Carver c(nullptr, 0);
   c.take<uint32_t>((size_t)s);
+  c.take<uint32_t>((size_t)(srht_sign_rows(plan) / 32));
   c.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
   return c.off;
 }
@@ -291,20 +351,27 @@ int srht_run(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b, 
   if (m == 0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
   const PanelPlan plan = srht_plan(h, m, ncols, (int)s, sizeof(T));
   uint32_t* idx = ws.take<uint32_t>((size_t)s);
+  const int64_t sblocks = srht_sign_rows(plan) / 128;
+  uint32_t* signs = ws.take<uint32_t>((size_t)sblocks * 4);
   T* partials = ws.take<T>((size_t)plan_slots(plan) * plan.slot_elems);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
   RMM_TRY(launch_sample_indices_u32(h, 1ull << k, k, s, TAG_SRHT_SAMPLE, seed, idx));
+  hipLaunchKernelGGL(srht_signs_kernel, dim3((unsigned)((sblocks + 255) / 256)), dim3(256), 0, h->stream,
+                     sblocks, seed, signs);
+  RMM_TRY(launch_status());
   const bool vec = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0) &&
                    (b == nullptr || (uintptr_t)b % 16 == 0);
   int rc;
 #define RMM_SRHT_CASE(SPQ)                                                                 \
-  rc = vec ? launch_srht<T, SPQ, true>(h, A, lda, b, n, plan, idx, seed, partials)         \
-           : launch_srht<T, SPQ, false>(h, A, lda, b, n, plan, idx, seed, partials);
-  if (s <= 256) {
+  rc = vec ? launch_srht<T, SPQ, true>(h, A, lda, b, n, plan, idx, signs, partials)        \
+           : launch_srht<T, SPQ, false>(h, A, lda, b, n, plan, idx, signs, partials);
+  // samples per thread: s over the workgroup's 64 WV threads
+  const int nt = 64 * srht_waves<T>();
+  if (s <= nt) {
     RMM_SRHT_CASE(1)
-  } else if (s <= 1024) {
+  } else if (s <= 4 * nt) {
     RMM_SRHT_CASE(4)
-  } else if (s <= 4096) {
+  } else if (s <= 16 * nt) {
     RMM_SRHT_CASE(16)
   } else {
     RMM_SRHT_CASE(32)
