@@ -129,7 +129,10 @@ int rmm_device_cus(rmm_handle h, int* cus);
  *   GAUSSIAN     S[i, r] = Omega[i, r] / sqrt(s), Omega from stream tag 4
  *   SRHT         S[i, r] = d_i H[i, idx_r] / sqrt(s); H Sylvester-ordered
  *                (H[i, r] = (-1)^popcount(i & r)); idx = sorted sample of s
- *                distinct rows of [0, N); requires s <= N
+ *                distinct rows of [0, N); requires s <= N (else
+ *                RMM_ERR_INVALID_ARG), s <= 8192 (each workgroup keeps one
+ *                accumulator per sampled row in registers; larger s is
+ *                RMM_ERR_UNSUPPORTED) and N <= 2^30
  *   COUNTSKETCH  S[i, h_i] = g_i, zero elsewhere; no scaling
  * m = 0 yields C = 0.  Requires n >= 0, s >= 1. */
 int rmm_sketch_workspace(rmm_handle h, rmm_dtype dt, rmm_sketch_kind kind,

@@ -28,6 +28,7 @@ F32, F64 = 0, 1
 STATUS_RANK_DEFICIENT = 1
 STATUS_QR_FALLBACK = 2
 STATUS_NOT_CONVERGED = 4
+ERR_UNSUPPORTED = -4
 ERR_SCRATCH_LIMIT = -5
 NOALLOC_SCRATCH_BYTES = 128 << 20
 

@@ -238,6 +238,11 @@ def test_invalid_arguments(h):
         h.sketch(A, 17, "srht", 1)        # s > N
     with pytest.raises(rmm.RmmError):
         h.sketch(A, 0, "countsketch", 1)  # s < 1
+    # SRHT keeps one accumulator per sampled row per workgroup: s <= 8192
+    Ab = torch.zeros(16384, 2, dtype=torch.float32, device="cuda")
+    with pytest.raises(rmm.RmmError) as e:
+        h.sketch(Ab, 8193, "srht", 1)
+    assert e.value.code == rmm.ERR_UNSUPPORTED
 
 
 # ---- config-scale sampled parity -------------------------------------------------
