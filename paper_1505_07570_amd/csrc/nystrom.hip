@@ -94,14 +94,16 @@ __global__ void rbf_gram_f64_kernel(int d, const float* __restrict__ X, int64_t 
 }
 
 // F[:, t] = V[:, t] / sqrt(lam_t) for lam_t > c * eps * lam_0, else 0 (t < k).
+// F = U_k Lam_k^{-1/2} formed in FP64 and rounded once to FP32 for the
+// product L = C F (C is FP32 already).
 __global__ void nystrom_scale_kernel(int c, int k, const double* __restrict__ lam,
-                                     const double* __restrict__ V, double* __restrict__ F) {
+                                     const double* __restrict__ V, float* __restrict__ F) {
   const int a = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
   if (a >= c) return;
   const double cut = (double)c * 0x1p-52 * lam[0];
   const double l = lam[t];
-  F[a + (int64_t)t * c] = (l > cut && l > 0.0) ? V[a + (int64_t)t * c] / sqrt(l) : 0.0;
+  F[a + (int64_t)t * c] = (float)((l > cut && l > 0.0) ? V[a + (int64_t)t * c] / sqrt(l) : 0.0);
 }
 
 int launch_rbf(const rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, int c,
@@ -123,17 +125,16 @@ namespace {
 struct NysBufs {
   double* W;
   double* V;
-  double* F;
+  float* F;
 };
 
-// layout shared by the size query and the run
 size_t nystrom_layout(const rmm_ctx* h, int64_t n, int c, int k, Carver& ws, NysBufs* b) {
   double* W = ws.take<double>((size_t)c * c);
   double* V = ws.take<double>((size_t)c * c);
-  double* F = ws.take<double>((size_t)c * k);
+  float* F = ws.take<float>((size_t)c * k);
   if (b) *b = NysBufs{W, V, F};
   size_t scratch = jacobi_workspace(c);
-  const size_t g = gemm_workspace<double>(h, (int)n, k, c);
+  const size_t g = gemm_workspace<float>(h, (int)n, k, c);
   if (g > scratch) scratch = g;
   return ws.off + scratch + 4 * kAlign;
 }
@@ -164,7 +165,7 @@ int nystrom_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, doubl
   hipLaunchKernelGGL(nystrom_scale_kernel, dim3((unsigned)((c + 127) / 128), (unsigned)k), dim3(128), 0,
                      h->stream, c, k, evals, b.V, b.F);
   RMM_TRY(launch_status());
-  return gemm<float, double, double, float>(h, false, false, (int)n, k, c, C, ldc, b.F, c, 1.0, L, ldl,
+  return gemm<float, float, float, float>(h, false, false, (int)n, k, c, C, ldc, b.F, c, 1.0, L, ldl,
                                             ws);
 }
 
@@ -186,12 +187,12 @@ size_t nystrom_gauss_layout(const rmm_ctx* h, int64_t n, int c, int k, Carver& w
   float* kt = ws.take<float>((size_t)br * bc);
   double* W = ws.take<double>((size_t)c * c);
   double* V = ws.take<double>((size_t)c * c);
-  double* F = ws.take<double>((size_t)c * k);
+  float* F = ws.take<float>((size_t)c * k);
   if (Om) *Om = o;
   if (Kt) *Kt = kt;
   if (b) *b = NysBufs{W, V, F};
   size_t scratch = jacobi_workspace(c);
-  scratch = scratch > gemm_workspace<double>(h, (int)n, k, c) ? scratch : gemm_workspace<double>(h, (int)n, k, c);
+  scratch = scratch > gemm_workspace<float>(h, (int)n, k, c) ? scratch : gemm_workspace<float>(h, (int)n, k, c);
   const size_t g1 = gemm_workspace<float>(h, (int)br, c, bc);
   const size_t g2 = gemm_workspace<double>(h, c, c, n);
   scratch = scratch > g1 ? scratch : g1;
@@ -235,7 +236,7 @@ int nystrom_gauss_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx,
   hipLaunchKernelGGL(nystrom_scale_kernel, dim3((unsigned)((c + 127) / 128), (unsigned)k), dim3(128), 0,
                      h->stream, c, k, evals, b.V, b.F);
   RMM_TRY(launch_status());
-  return gemm<float, double, double, float>(h, false, false, (int)n, k, c, C, ldc, b.F, c, 1.0, L, ldl,
+  return gemm<float, float, float, float>(h, false, false, (int)n, k, c, C, ldc, b.F, c, 1.0, L, ldl,
                                             ws);
 }
 

@@ -35,8 +35,11 @@ def _align(L, Lo):
 def _check_L(L, Lo, Co, lam, k, c):
     keep = (lam[:k] > c * 2.0 ** -52 * lam[0]) & (lam[:k] > 0)
     fnorm = 1.0 / np.sqrt(lam[:k][keep].min())
-    # fp32 rounding of C (relative 2^-24 per entry plus the distance error)
-    # times ||F||_2, relative to ||L||_F
+    # L = C F is formed in FP32 from the FP32 C and F rounded once from
+    # FP64: C's rounding (2^-24 per entry plus the distance error) and F's
+    # (2^-24 per entry) each give at most 2^-24 ||C|| ||F||_2, the FP32
+    # accumulation over c terms about sqrt(c) 2^-24 ||C|| ||F||_2 (32 at
+    # c = 1024); 64 covers their sum, relative to ||L||_F
     bound = 64 * 2.0 ** -24 * np.linalg.norm(Co) * fnorm / np.linalg.norm(Lo) + 1e-6
     assert rel(_align(L, Lo), Lo) <= bound
 
