@@ -122,15 +122,22 @@ __device__ __forceinline__ void jacobi_rotation(double gpq, double gpp, double g
   s = rot ? tt * cc : 0.0;
 }
 
-// pending |= an off-diagonal element (a < b < l) passes the rotation test
-__global__ void blk_scan_kernel(int l, int L, const double* __restrict__ W, BlkState* st) {
-  if (st->converged) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)l * l) return;
-  const int a = (int)(e % l), b = (int)(e / l);
-  if (a >= b) return;
-  if (rot_test(W[a + (int64_t)b * L], W[a + (int64_t)a * L], W[b + (int64_t)b * L], st->abs_tol))
-    atomicOr(&st->pending, 1);
+// pending |= an off-diagonal element (a < b < l) passes the rotation test.
+// One atomic per wave that finds one; workgroups starting after pending is
+// set skip their reads (a stale read only costs the scan).
+// Workgroup x scans columns b = x, x + G, ... (G workgroups) with the
+// diagonal in LDS.
+__global__ __launch_bounds__(256) void blk_scan_kernel(int l, int L, const double* __restrict__ W,
+                                                       BlkState* st) {
+  if (st->converged || st->pending) return;
+  __shared__ double dg[1024];
+  for (int i = threadIdx.x; i < l; i += 256) dg[i] = W[i + (int64_t)i * L];
+  __syncthreads();
+  const double tol = st->abs_tol;
+  bool pass = false;
+  for (int b = blockIdx.x; b < l; b += gridDim.x)
+    for (int a = threadIdx.x; a < b; a += 256) pass |= rot_test(W[a + (int64_t)b * L], dg[a], dg[b], tol);
+  if (__any(pass) && (threadIdx.x & 63) == 0) atomicOr(&st->pending, 1);
 }
 
 __global__ void blk_decide_kernel(BlkState* st) {
@@ -218,6 +225,20 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
   const double abs_tol = st->abs_tol;
   const int u = tid & 31, g = tid >> 5;
   constexpr int rounds = MODE == 0 ? kCrossRounds : kIntraRounds;
+  // In cross steps p_u = u and p_v = v in every round, so the block I x I
+  // entries S[u][v] and the entries Q[u][v], Q[u + 32][v] of a thread never
+  // change owner: they stay in registers (only S[u][u], which the rotation
+  // of pair u reads, also goes to LDS each round).
+  double ii[4], qi[4][2];
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int v = g + 8 * m;
+      ii[m] = S[0][u + v * kBLd];
+      qi[m][0] = u == v ? 1.0 : 0.0;
+      qi[m][1] = 0.0;  // row u + 32 >= 32 > v
+    }
+  }
   for (int rr = 0; rr < rounds; ++rr) {
     const double* Sc = S[rr & 1];
     double* Sn = S[(rr & 1) ^ 1];
@@ -231,13 +252,13 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
     double x[4][4], y[4][2][2];
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      x[m][0] = Sc[p + pv[m] * kBLd];
+      x[m][0] = MODE == 0 ? ii[m] : Sc[p + pv[m] * kBLd];
       x[m][1] = Sc[p + qv[m] * kBLd];
       x[m][2] = Sc[q + pv[m] * kBLd];
       x[m][3] = Sc[q + qv[m] * kBLd];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        y[m][h][0] = Q[u + 32 * h + pv[m] * kBLd];
+        y[m][h][0] = MODE == 0 ? qi[m][h] : Q[u + 32 * h + pv[m] * kBLd];
         y[m][h][1] = Q[u + 32 * h + qv[m] * kBLd];
       }
     }
@@ -265,16 +286,30 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
         z01 = rot ? 0.0 : x[m][1];
         z10 = rot ? 0.0 : x[m][2];
       }
-      Sn[p + pv[m] * kBLd] = z00;
+      if constexpr (MODE == 0) {
+        ii[m] = z00;
+        if (g + 8 * m == u) Sn[p + pv[m] * kBLd] = z00;
+      } else {
+        Sn[p + pv[m] * kBLd] = z00;
+      }
       Sn[p + qv[m] * kBLd] = z01;
       Sn[q + pv[m] * kBLd] = z10;
       Sn[q + qv[m] * kBLd] = z11;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        Q[u + 32 * h + pv[m] * kBLd] = cv[m] * y[m][h][0] - sv[m] * y[m][h][1];
+        const double qp = cv[m] * y[m][h][0] - sv[m] * y[m][h][1];
+        if constexpr (MODE == 0) qi[m][h] = qp;
+        else Q[u + 32 * h + pv[m] * kBLd] = qp;
         Q[u + 32 * h + qv[m] * kBLd] = sv[m] * y[m][h][0] + cv[m] * y[m][h][1];
       }
     }
+    __syncthreads();
+  }
+  if constexpr (MODE == 0) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) Q[u + 32 * h + (g + 8 * m) * kBLd] = qi[m][h];
     __syncthreads();
   }
   // Each rotation is orthogonal only to rounding, and so is Q, their product;
@@ -521,6 +556,7 @@ struct EventPair {
 
 int jacobi_eig_block(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* evals, double* V,
                      int32_t* status, Carver& ws) {
+  if (l > 1024) return RMM_ERR_UNSUPPORTED;  // the scan's LDS copy of the diagonal
   const int nb = ((l + kBB - 1) / kBB + 1) & ~1;
   const int L = nb * kBB;
   const int np = nb / 2;
@@ -546,9 +582,9 @@ int jacobi_eig_block(const rmm_ctx* h, int l, const double* G, int64_t ldg, doub
   const bool early = h->hflag && cap == hipStreamCaptureStatusNone &&
                      hipEventCreateWithFlags(&ev.e[0], hipEventDisableTiming) == hipSuccess &&
                      hipEventCreateWithFlags(&ev.e[1], hipEventDisableTiming) == hipSuccess;
-  const unsigned sgroups = (unsigned)(((int64_t)l * l + 255) / 256);
+  const dim3 sgrid((unsigned)(l < 256 ? l : 256));
   for (int sweep = 0; sweep <= kBMaxSweeps; ++sweep) {
-    hipLaunchKernelGGL(blk_scan_kernel, dim3(sgroups), dim3(256), 0, h->stream, l, L, W, st);
+    hipLaunchKernelGGL(blk_scan_kernel, sgrid, dim3(256), 0, h->stream, l, L, W, st);
     hipLaunchKernelGGL(blk_decide_kernel, dim3(1), dim3(1), 0, h->stream, st);
     RMM_TRY(launch_status());
     if (sweep == kBMaxSweeps) break;  // the last scan only decides convergence
