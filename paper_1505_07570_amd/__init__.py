@@ -65,6 +65,7 @@ def lib():
             "rmm_set_autotune": [_vp, _i32],
             "rmm_set_kernel_timing": [_vp, _i32],
             "rmm_kernel_time": [_vp, ctypes.POINTER(ctypes.c_float)],
+            "rmm_stream_read": [_vp, _vp, _i64, _vp],
             "rmm_autotune_count": [_vp, ctypes.POINTER(_i64)],
             "rmm_autotune_save": [_vp, ctypes.c_char_p],
             "rmm_autotune_load": [_vp, ctypes.c_char_p],
@@ -407,6 +408,13 @@ class Handle:
     # ---- timing of the sketches' main kernels (rmm_set_kernel_timing) ------------
     def set_kernel_timing(self, on: bool = True):
         _check(lib().rmm_set_kernel_timing(self._h, 1 if on else 0), "rmm_set_kernel_timing")
+
+    def stream_read(self, x: torch.Tensor, sink: torch.Tensor):
+        """One streaming read of x (the HBM read reference); sink: >= 4096 float32."""
+        assert x.is_cuda and x.is_contiguous() and sink.dtype == torch.float32 and sink.numel() >= 4096
+        self._bind_stream()
+        _check(lib().rmm_stream_read(self._h, _ptr(x), x.numel() * x.element_size(), _ptr(sink)),
+               "rmm_stream_read")
 
     def kernel_time(self) -> float:
         """Milliseconds of the last timed sketch kernel (waits for it)."""

@@ -268,3 +268,12 @@ def test_sketch_config_lsr_sampled_rows(h, lsr_problem, name, kind):
     ref = osk.sketch(D, s, kind, seed, fp64=False, rows=rows)
     for t, r_ in enumerate(rows):
         assert rel(C[r_], ref[t]) < TOL[torch.float32], (name, r_)
+
+
+def test_stream_read_reads_every_element(h):
+    """The HBM read reference touches every 16-byte word of its buffer once."""
+    x = torch.rand((1 << 22) + 12, dtype=torch.float32, device="cuda")
+    sink = torch.zeros(4096, dtype=torch.float32, device="cuda")
+    h.stream_read(x, sink)
+    got, ref = float(sink.double().sum()), float(x.double().sum())
+    assert abs(got - ref) <= 1e-5 * ref
