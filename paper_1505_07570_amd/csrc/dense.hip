@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void gemm_nn_kernel(int M, int N, int64_t K, c
                                                       double alpha, double beta) {
   using F = Mfma<T>;
   using acc_t = typename F::acc;
-  constexpr int BM = 128, BN = 128, BK = kBK;
+  constexpr int BM = 128, BN = 128, BK = sizeof(T) == 4 ? 2 * kBK : kBK;
   constexpr int V = 16 / (int)sizeof(T);        // elements per 16-byte load
   constexpr int AL = BM * BK / V / 256;          // A loads per thread per stage
   constexpr int BL = BN * BK / V / 256;          // B loads per thread per stage

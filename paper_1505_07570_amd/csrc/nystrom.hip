@@ -25,14 +25,17 @@ constexpr int kRbfMaxD = 64;   // point dimension held in registers
 // D + 1 floats: conflict-free per-thread reads) and the workgroup walks over
 // all c columns in stages of kRbfCols sampled points, stored coordinate-major
 // so that one broadcast 16-byte LDS read serves four columns.  Writes are
-// coalesced along i.
+// coalesced along i.  blockIdx.y takes columns [cpg y, cpg (y + 1)) (cpg a
+// multiple of kRbfCols), so that short, wide blocks of K still give many
+// workgroups.
 // Column j is point idx[j] of Y, or point col_base + j when idx is null.
 template <int D>
 __global__ __launch_bounds__(kRbfRows) void rbf_columns_kernel(int64_t n, int d, const float* __restrict__ X,
                                                                int64_t ldx, int c, const int64_t* __restrict__ idx,
                                                                const float* __restrict__ Y, int64_t ldy,
                                                                int64_t col_base,
-                                                               float g, float* __restrict__ C, int64_t ldc) {
+                                                               float g, float* __restrict__ C, int64_t ldc,
+                                                               int cpg) {
   __shared__ __align__(16) float ys[D][kRbfCols];
   __shared__ float xs[kRbfRows][D + 1];
   const int64_t r0 = (int64_t)blockIdx.x * kRbfRows;
@@ -41,16 +44,18 @@ __global__ __launch_bounds__(kRbfRows) void rbf_columns_kernel(int64_t n, int d,
     const int r = e / D, k = e % D;
     xs[r][k] = (r0 + r < n && k < d) ? X[(r0 + r) * ldx + k] : 0.0f;
   }
-  for (int j0 = 0; j0 < c; j0 += kRbfCols) {
+  const int jb = blockIdx.y * cpg;
+  const int je = jb + cpg < c ? jb + cpg : c;
+  for (int j0 = jb; j0 < je; j0 += kRbfCols) {
     __syncthreads();
     for (int e = threadIdx.x; e < kRbfCols * D; e += kRbfRows) {
       const int jj = e / D, k = e % D;
       const int j = j0 + jj;
-      const int64_t pt = idx ? idx[j < c ? j : 0] : col_base + j;  // sampled or contiguous points
-      ys[k][jj] = (j < c && k < d) ? Y[pt * ldy + k] : 0.0f;
+      const int64_t pt = idx ? idx[j < je ? j : jb] : col_base + j;  // sampled or contiguous points
+      ys[k][jj] = (j < je && k < d) ? Y[pt * ldy + k] : 0.0f;
     }
     __syncthreads();
-    const int jn = (c - j0) < kRbfCols ? (c - j0) : kRbfCols;
+    const int jn = (je - j0) < kRbfCols ? (je - j0) : kRbfCols;
     if (i >= n) continue;
     float acc[kRbfCols];
 #pragma unroll
@@ -111,12 +116,20 @@ int launch_rbf(const rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, 
                int64_t ldc) {
   if (n == 0 || c == 0) return RMM_OK;
   const unsigned blocks = (unsigned)((n + kRbfRows - 1) / kRbfRows);
+  // column groups: at least 4 workgroups per CU in all
+  const int stages = (c + kRbfCols - 1) / kRbfCols;
+  int64_t gy = (4 * (int64_t)h->cus + blocks - 1) / blocks;
+  if (gy > stages) gy = stages;
+  if (gy < 1) gy = 1;
+  const int cpg = (int)((stages + gy - 1) / gy) * kRbfCols;
+  gy = (c + cpg - 1) / cpg;
+  const dim3 grid(blocks, (unsigned)gy);
   if (d <= 32)
-    hipLaunchKernelGGL(rbf_columns_kernel<32>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n, d, X,
-                       ldx, c, idx, Y, ldy, col_base, (float)g, C, ldc);
+    hipLaunchKernelGGL(rbf_columns_kernel<32>, grid, dim3(kRbfRows), 0, h->stream, n, d, X, ldx, c, idx, Y,
+                       ldy, col_base, (float)g, C, ldc, cpg);
   else
-    hipLaunchKernelGGL(rbf_columns_kernel<kRbfMaxD>, dim3(blocks), dim3(kRbfRows), 0, h->stream, n,
-                       d, X, ldx, c, idx, Y, ldy, col_base, (float)g, C, ldc);
+    hipLaunchKernelGGL(rbf_columns_kernel<kRbfMaxD>, grid, dim3(kRbfRows), 0, h->stream, n, d, X, ldx, c,
+                       idx, Y, ldy, col_base, (float)g, C, ldc, cpg);
   return launch_status();
 }
 
