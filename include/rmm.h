@@ -344,7 +344,14 @@ int rmm_plain_lsr(rmm_handle h, rmm_dtype dt, int64_t m, int64_t d,
  *   evals (c doubles) eigenvalues of W = K[S, S] (computed in FP64), descending
  *   L (n x k fp32, ldl >= n)  C U_k Lam_k^{-1/2}, so that K ~ L L^T =
  *                     C W_k^+ C^T; eigenvalues <= c * 2^-52 * lambda_max give
- *                     zero columns
+ *                     zero columns; L = C F is an FP32 product with
+ *                     F = U_k Lam_k^{-1/2} formed in FP64 and rounded once
+ * The eigensolver of W is cyclic Jacobi in FP64 (one workgroup for c <= 128,
+ * block Jacobi above).  For c > 128, outside stream capture, the call reads
+ * each sweep's convergence flag on the host one sweep after enqueueing it
+ * (so it returns once the sweeps are decided, with the last work still
+ * queued); under capture it enqueues the maximum number of sweeps, of which
+ * those after convergence return at once.
  * Requires 1 <= k <= c <= n; d <= 64 and c <= 1024 (RMM_ERR_UNSUPPORTED
  * beyond).  status: RMM_STATUS_NOT_CONVERGED from the eigensolver. */
 int rmm_nystrom_workspace(rmm_handle h, int64_t n, int64_t d, int64_t c, int64_t k,
@@ -359,7 +366,8 @@ int rmm_nystrom(rmm_handle h, int64_t n, int64_t d, const float* X, int64_t ldx,
  * (n x c, i.i.d. N(0,1), stream tag 7) regenerated from the seed,
  * W = Omega^T C (FP64), W = U Lam U^T, L = C U_k Lam_k^{-1/2} (n x k fp32,
  * ldl >= n) with the same zero-eigenvalue cut as rmm_nystrom.  K is formed
- * tile by tile only.  Same limits as rmm_nystrom. */
+ * tile by tile only.  Same limits, eigensolver and host behaviour as
+ * rmm_nystrom. */
 int rmm_nystrom_gaussian_workspace(rmm_handle h, int64_t n, int64_t d, int64_t c,
                                    int64_t k, size_t* bytes);
 int rmm_nystrom_gaussian(rmm_handle h, int64_t n, int64_t d, const float* X,
