@@ -17,8 +17,9 @@
 // the whole matrix afterwards by tiles, W[IJ, IJ'] <- Q^T W[IJ, IJ'] Q' and
 // V[:, IJ] <- V[:, IJ] Q (all pairs of a step at once: their index sets are
 // disjoint).  So W <- P^T W P and V <- V P with P block orthogonal.
-// Before each sweep a scan decides convergence exactly as the scalar solver
-// does (no off-diagonal element passes the rotation test).  Then the
+// Before each sweep a scan decides convergence (no off-diagonal element
+// passes the rotation test: the scalar solver's relative test, plus an
+// absolute floor of 2^-52 ||W||_F, the rounding level of the block updates).  Then the
 // eigenvalues (the diagonal, descending, ties by index) and V's columns are
 // sorted out.
 #include <math.h>
@@ -67,18 +68,31 @@ __global__ void blk_init_kernel(int l, int L, const double* __restrict__ G, int6
   if (e == 0) *st = BlkState{0.0, 0, 0, 0};
 }
 
-__global__ __launch_bounds__(256) void blk_tol_kernel(int l, int L, const double* __restrict__ W,
-                                                      BlkState* st) {
-  __shared__ double red[256];
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < l; i += 256) mx = fmax(mx, fabs(W[i + (int64_t)i * L]));
-  red[threadIdx.x] = mx;
+// abs_tol = 2^-52 ||W||_F.  The block updates apply re-orthogonalized
+// products of rotations with full 64 x 64 products, so every step leaves
+// rounding of order eps ||W|| in the entries it touches (the backward error
+// of an orthogonal similarity); off-diagonal entries at that level carry no
+// information and are not rotated.  Without this floor a cluster of
+// numerically zero eigenvalues (repeated points) would be rotated forever:
+// its large-angle rotations smear the rounding of the large eigenvalues back
+// into it.  The relative test of the scalar solver applies on top.  One
+// workgroup, fixed summation order (the threshold is reproducible).
+__global__ __launch_bounds__(1024) void blk_tol_kernel(int l, int L, const double* __restrict__ W,
+                                                       BlkState* st) {
+  __shared__ double red[1024];
+  double ss = 0.0;
+  for (int b = 0; b < l; ++b)
+    for (int a = threadIdx.x; a < l; a += 1024) {
+      const double v = W[a + (int64_t)b * L];
+      ss = fma(v, v, ss);
+    }
+  red[threadIdx.x] = ss;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+  for (int s = 512; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) st->abs_tol = 1e-17 * red[0];
+  if (threadIdx.x == 0) st->abs_tol = 0x1p-52 * sqrt(red[0]);
 }
 
 __device__ __forceinline__ bool rot_test(double gpq, double gpp, double gqq, double abs_tol) {
@@ -570,7 +584,7 @@ int jacobi_eig_block(const rmm_ctx* h, int l, const double* G, int64_t ldg, doub
   const int64_t LL = (int64_t)L * L;
   hipLaunchKernelGGL(blk_init_kernel, dim3((unsigned)((LL + 255) / 256)), dim3(256), 0, h->stream, l, L,
                      G, ldg, W, Vw, st);
-  hipLaunchKernelGGL(blk_tol_kernel, dim3(1), dim3(256), 0, h->stream, l, L, W, st);
+  hipLaunchKernelGGL(blk_tol_kernel, dim3(1), dim3(1024), 0, h->stream, l, L, W, st);
   RMM_TRY(launch_status());
   // Sweeps stop on the device once converged (later launches return at
   // once).  Outside stream capture the host also stops enqueueing them: each

@@ -44,8 +44,11 @@ def _check_L(L, Lo, Co, lam, k, c):
     assert rel(_align(L, Lo), Lo) <= bound
 
 
+# c = 129 (just above the one-workgroup eigensolver; 6 blocks of 32 with 63
+# padded indices), 301 and 700 (padded block counts), 1024 (32 blocks)
 @pytest.mark.parametrize("n,d,c,k", [(3000, 32, 100, None), (777, 3, 37, 37), (5000, 64, 128, 64),
-                                     (129, 7, 129 - 1, None), (3000, 32, 301, None),
+                                     (129, 7, 129 - 1, None), (2000, 16, 129, None),
+                                     (3000, 32, 301, None), (4000, 8, 700, 300),
                                      (6000, 32, 1024, 256)])
 def test_nystrom_parity(h, n, d, c, k):
     X, sigma = synth.gmm_points(seed=n + d, n=n, d=d, pairs=2000)
@@ -58,6 +61,23 @@ def test_nystrom_parity(h, n, d, c, k):
     assert rel(C, Co) < 1e-5
     assert np.abs(host(ev) - lamo).max() <= 1e-12 * lamo[0]
     _check_L(host(L), Lo, Co, lamo, kk, c)
+
+
+def test_nystrom_repeated_points_eigenvalues(h):
+    """150 distinct points each repeated 10 times, c = 300: W has rank at most
+    the number r of distinct points in the sample, so at least 300 - r of its
+    eigenvalues vanish (a cluster at zero for the block Jacobi eigensolver);
+    all of them within 1e-12 lambda_max of the oracle's."""
+    X0, sigma = synth.gmm_points(seed=77, n=150, d=8, pairs=2000)
+    X = np.tile(X0, (10, 1))
+    Lo, So, Co, Wo, lamo = onys.nystrom(X, sigma, 300, seed=5)
+    L, idx, C, ev, st = h.nystrom(torch.from_numpy(X).cuda(), sigma, 300, 5)
+    np.testing.assert_array_equal(idx.cpu().numpy(), So)
+    assert int(st.item()) == 0
+    ev = host(ev)
+    assert np.abs(ev - lamo).max() <= 1e-12 * lamo[0]
+    r = len(np.unique(So % 150))
+    assert (np.abs(ev[r:]) <= 1e-12 * lamo[0]).all()
 
 
 def test_nystrom_full_rows_sampled(h):
