@@ -75,24 +75,35 @@ __global__ void blk_init_kernel(int l, int L, const double* __restrict__ G, int6
 // information and are not rotated.  Without this floor a cluster of
 // numerically zero eigenvalues (repeated points) would be rotated forever:
 // its large-angle rotations smear the rounding of the large eigenvalues back
-// into it.  The relative test of the scalar solver applies on top.  One
-// workgroup, fixed summation order (the threshold is reproducible).
-__global__ __launch_bounds__(1024) void blk_tol_kernel(int l, int L, const double* __restrict__ W,
-                                                       BlkState* st) {
-  __shared__ double red[1024];
+// into it.  The relative test of the scalar solver applies on top.  Partial
+// sums per column group, then one thread adds them in a fixed order (the
+// threshold is reproducible).
+constexpr int kTolGroups = 128;
+
+// part[x] = sum of the squares of columns x, x + kTolGroups, ... of W
+__global__ __launch_bounds__(256) void blk_fro_part_kernel(int l, int L, const double* __restrict__ W,
+                                                           double* __restrict__ part) {
+  __shared__ double red[256];
   double ss = 0.0;
-  for (int b = 0; b < l; ++b)
-    for (int a = threadIdx.x; a < l; a += 1024) {
+  for (int b = blockIdx.x; b < l; b += kTolGroups)
+    for (int a = threadIdx.x; a < l; a += 256) {
       const double v = W[a + (int64_t)b * L];
       ss = fma(v, v, ss);
     }
   red[threadIdx.x] = ss;
   __syncthreads();
-  for (int s = 512; s > 0; s >>= 1) {
+  for (int s = 128; s > 0; s >>= 1) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) st->abs_tol = 0x1p-52 * sqrt(red[0]);
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void blk_tol_kernel(const double* __restrict__ part, BlkState* st) {
+  if (threadIdx.x != 0) return;
+  double ss = 0.0;
+  for (int x = 0; x < kTolGroups; ++x) ss += part[x];  // fixed order: reproducible
+  st->abs_tol = 0x1p-52 * sqrt(ss);
 }
 
 __device__ __forceinline__ bool rot_test(double gpq, double gpp, double gqq, double abs_tol) {
@@ -543,7 +554,8 @@ size_t jacobi_block_workspace(int l) {
   c.take<double>((size_t)(nb / 2) * kBS * kBS);   // Q of each pair
   c.take<BlkState>(1);
   c.take<int>((size_t)l);                         // eigenvalue order
-  return c.off + 5 * kAlign;
+  c.take<double>((size_t)kTolGroups);             // partial sums of ||W||_F^2
+  return c.off + 6 * kAlign;
 }
 
 namespace {
@@ -580,11 +592,13 @@ int jacobi_eig_block(const rmm_ctx* h, int l, const double* G, int64_t ldg, doub
   double* Db = ws.take<double>((size_t)np * kBS * kBS);
   BlkState* st = ws.take<BlkState>(1);
   int* perm = ws.take<int>((size_t)l);
+  double* part = ws.take<double>((size_t)kTolGroups);
   if (!ws.fits()) return RMM_ERR_WORKSPACE_TOO_SMALL;
   const int64_t LL = (int64_t)L * L;
   hipLaunchKernelGGL(blk_init_kernel, dim3((unsigned)((LL + 255) / 256)), dim3(256), 0, h->stream, l, L,
                      G, ldg, W, Vw, st);
-  hipLaunchKernelGGL(blk_tol_kernel, dim3(1), dim3(1024), 0, h->stream, l, L, W, st);
+  hipLaunchKernelGGL(blk_fro_part_kernel, dim3(kTolGroups), dim3(256), 0, h->stream, l, L, W, part);
+  hipLaunchKernelGGL(blk_tol_kernel, dim3(1), dim3(64), 0, h->stream, part, st);
   RMM_TRY(launch_status());
   // Sweeps stop on the device once converged (later launches return at
   // once).  Outside stream capture the host also stops enqueueing them: each
