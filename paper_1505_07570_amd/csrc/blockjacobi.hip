@@ -218,14 +218,22 @@ __device__ __forceinline__ void step_pair(int u, int rr, int& p, int& q) {
 // blockIdx.x; D = Q - I (64 x 64, column-major) to Dbuf[pair].
 //
 // Thread (u = tid mod 32, g = tid / 32) computes rotation u of each round
-// and updates the 2 x 2 blocks (u, v) of the subproblem, v = g, g + 8,
-// g + 16, g + 24 (rows {p_u, q_u}, columns {p_v, q_v}: every element once),
+// and updates the 2 x 2 blocks (u, v) of the subproblem, v = g + kStepG m
+// for m < kStepM (rows {p_u, q_u}, columns {p_v, q_v}: every element once),
 // and rows u and u + 32 of Q at the column pairs v; rotation v comes from
 // lane v of the same wave.  The subproblem is double-buffered in LDS (read
-// one, write the other), so one barrier per round suffices.
+// one, write the other), so one barrier per round suffices.  A round is a
+// short dependent chain (LDS reads, the rotation, the shuffles, the 2 x 2
+// updates), so several waves per SIMD share the blocks to hide its latency.
+constexpr int kStepM = 2;                    // blocks (u, v) per thread
+constexpr int kStepG = kBB / kStepM;         // thread groups of 32
+constexpr int kStepThreads = kBB * kStepG;
+constexpr int kStepLoads = kBS * kBS / kStepThreads;
+constexpr int kStepCols = kBS * kBS / (4 * kStepThreads);  // epilogue: 4 rows x kStepCols columns per thread
+
 template <int MODE>
-__global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, const double* __restrict__ W,
-                                                       double* __restrict__ Dbuf, const BlkState* st) {
+__global__ __launch_bounds__(kStepThreads) void blk_step_kernel(int nb, int r, int L, const double* __restrict__ W,
+                                                                double* __restrict__ Dbuf, const BlkState* st) {
   if (st->converged) return;
   __shared__ double S[2][kBS * kBLd];
   __shared__ double Q[kBS * kBLd];
@@ -233,15 +241,15 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
   int bi, bj;
   step_blocks<MODE>(blockIdx.x, r, nb, bi, bj);
   {
-    double v[16];  // all loads in flight before the LDS stores
+    double v[kStepLoads];  // all loads in flight before the LDS stores
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int e = tid + 256 * k, a = e % kBS, b = e / kBS;
+    for (int k = 0; k < kStepLoads; ++k) {
+      const int e = tid + kStepThreads * k, a = e % kBS, b = e / kBS;
       v[k] = W[gidx(a, bi, bj) + (int64_t)gidx(b, bi, bj) * L];
     }
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int e = tid + 256 * k, a = e % kBS, b = e / kBS;
+    for (int k = 0; k < kStepLoads; ++k) {
+      const int e = tid + kStepThreads * k, a = e % kBS, b = e / kBS;
       S[0][a + b * kBLd] = v[k];
       Q[a + b * kBLd] = a == b ? 1.0 : 0.0;
     }
@@ -254,11 +262,11 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
   // entries S[u][v] and the entries Q[u][v], Q[u + 32][v] of a thread never
   // change owner: they stay in registers (only S[u][u], which the rotation
   // of pair u reads, also goes to LDS each round).
-  double ii[4], qi[4][2];
+  double ii[kStepM], qi[kStepM][2];
   if constexpr (MODE == 0) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int v = g + 8 * m;
+    for (int m = 0; m < kStepM; ++m) {
+      const int v = g + kStepG * m;
       ii[m] = S[0][u + v * kBLd];
       qi[m][0] = u == v ? 1.0 : 0.0;
       qi[m][1] = 0.0;  // row u + 32 >= 32 > v
@@ -267,16 +275,16 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
   for (int rr = 0; rr < rounds; ++rr) {
     const double* Sc = S[rr & 1];
     double* Sn = S[(rr & 1) ^ 1];
-    int p, q, pv[4], qv[4];
+    int p, q, pv[kStepM], qv[kStepM];
     step_pair<MODE>(u, rr, p, q);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) step_pair<MODE>(g + 8 * m, rr, pv[m], qv[m]);
+    for (int m = 0; m < kStepM; ++m) step_pair<MODE>(g + kStepG * m, rr, pv[m], qv[m]);
     // every LDS read of the round first (the compiler cannot tell the stores
     // below from these addresses)
     const double gpq = Sc[p + q * kBLd], gpp = Sc[p + p * kBLd], gqq = Sc[q + q * kBLd];
-    double x[4][4], y[4][2][2];
+    double x[kStepM][4], y[kStepM][2][2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < kStepM; ++m) {
       x[m][0] = MODE == 0 ? ii[m] : Sc[p + pv[m] * kBLd];
       x[m][1] = Sc[p + qv[m] * kBLd];
       x[m][2] = Sc[q + pv[m] * kBLd];
@@ -289,22 +297,22 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
     }
     double c, s, t;
     jacobi_rotation(gpq, gpp, gqq, abs_tol, c, s, t);
-    double cv[4], sv[4];
+    double cv[kStepM], sv[kStepM];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      cv[m] = __shfl(c, g + 8 * m);
-      sv[m] = __shfl(s, g + 8 * m);
+    for (int m = 0; m < kStepM; ++m) {
+      cv[m] = __shfl(c, g + kStepG * m);
+      sv[m] = __shfl(s, g + kStepG * m);
     }
     // blocks (u, v): R_u^T X R_v; the rotated block itself (v = u) takes the
     // scalar solver's update.  A zero rotation (c = 1, s = 0) leaves values
     // unchanged exactly, so nothing branches on it.
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < kStepM; ++m) {
       const double y00 = c * x[m][0] - s * x[m][2], y01 = c * x[m][1] - s * x[m][3];
       const double y10 = s * x[m][0] + c * x[m][2], y11 = s * x[m][1] + c * x[m][3];
       double z00 = cv[m] * y00 - sv[m] * y01, z01 = sv[m] * y00 + cv[m] * y01;
       double z10 = cv[m] * y10 - sv[m] * y11, z11 = sv[m] * y10 + cv[m] * y11;
-      if (g + 8 * m == u) {
+      if (g + kStepG * m == u) {
         const bool rot = s != 0.0;
         z00 = rot ? x[m][0] - t * x[m][1] : x[m][0];
         z11 = rot ? x[m][3] + t * x[m][1] : x[m][3];
@@ -313,7 +321,7 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
       }
       if constexpr (MODE == 0) {
         ii[m] = z00;
-        if (g + 8 * m == u) Sn[p + pv[m] * kBLd] = z00;
+        if (g + kStepG * m == u) Sn[p + pv[m] * kBLd] = z00;
       } else {
         Sn[p + pv[m] * kBLd] = z00;
       }
@@ -332,9 +340,9 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
   }
   if constexpr (MODE == 0) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < kStepM; ++m)
 #pragma unroll
-      for (int h = 0; h < 2; ++h) Q[u + 32 * h + (g + 8 * m) * kBLd] = qi[m][h];
+      for (int h = 0; h < 2; ++h) Q[u + 32 * h + (g + kStepG * m) * kBLd] = qi[m][h];
     __syncthreads();
   }
   // Each rotation is orthogonal only to rounding, and so is Q, their product;
@@ -343,45 +351,43 @@ __global__ __launch_bounds__(256) void blk_step_kernel(int nb, int r, int L, con
   // second order in E), and stored as D = Q - I: the updates then add a
   // small correction D^T W or W D to W, rounding relative to its size.
   double* E = S[0];
-  const int a1 = tid & 15, b0 = (tid >> 4) * 4;  // rows a1 + 16 i, columns b0 + j
-  double acc[4][4] = {};
+  const int a1 = tid & 15, b0 = (tid >> 4) * kStepCols;  // rows a1 + 16 i, columns b0 + j
+  double acc[4][kStepCols] = {};
   for (int t = 0; t < kBS; ++t) {
-    double qa[4], qb[4];
+    double qa[4], qb[kStepCols];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      qa[i] = Q[t + (a1 + 16 * i) * kBLd];
-      qb[i] = Q[t + (b0 + i) * kBLd];
-    }
+    for (int i = 0; i < 4; ++i) qa[i] = Q[t + (a1 + 16 * i) * kBLd];
+#pragma unroll
+    for (int j = 0; j < kStepCols; ++j) qb[j] = Q[t + (b0 + j) * kBLd];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(qa[i], qb[j], acc[i][j]);
+      for (int j = 0; j < kStepCols; ++j) acc[i][j] = fma(qa[i], qb[j], acc[i][j]);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kStepCols; ++j) {
       E[a1 + 16 * i + (b0 + j) * kBLd] = acc[i][j] - (a1 + 16 * i == b0 + j ? 1.0 : 0.0);
       acc[i][j] = 0.0;
     }
   __syncthreads();
   for (int t = 0; t < kBS; ++t) {
-    double qa[4], eb[4];
+    double qa[4], eb[kStepCols];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      qa[i] = Q[a1 + 16 * i + t * kBLd];
-      eb[i] = E[t + (b0 + i) * kBLd];
-    }
+    for (int i = 0; i < 4; ++i) qa[i] = Q[a1 + 16 * i + t * kBLd];
+#pragma unroll
+    for (int j = 0; j < kStepCols; ++j) eb[j] = E[t + (b0 + j) * kBLd];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(qa[i], eb[j], acc[i][j]);
+      for (int j = 0; j < kStepCols; ++j) acc[i][j] = fma(qa[i], eb[j], acc[i][j]);
   }
   double* out = Dbuf + (size_t)blockIdx.x * kBS * kBS;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kStepCols; ++j) {
       const int a = a1 + 16 * i, b = b0 + j;
       out[a + b * kBS] = (Q[a + b * kBLd] - (a == b ? 1.0 : 0.0)) - 0.5 * acc[i][j];
     }
@@ -564,7 +570,7 @@ namespace {
 template <int MODE>
 int enqueue_step(const rmm_ctx* h, int nb, int r, int L, double* W, double* Vw, double* Db, BlkState* st) {
   const unsigned np = (unsigned)(nb / 2);
-  hipLaunchKernelGGL(blk_step_kernel<MODE>, dim3(np), dim3(256), 0, h->stream, nb, r, L, W, Db, st);
+  hipLaunchKernelGGL(blk_step_kernel<MODE>, dim3(np), dim3(kStepThreads), 0, h->stream, nb, r, L, W, Db, st);
   hipLaunchKernelGGL(blk_update_kernel<MODE>, dim3(np, 2 * np), dim3(256), 0, h->stream, nb, r, L, W, Vw, Db,
                      st);
   return launch_status();
