@@ -339,6 +339,54 @@ __global__ void gemm_reduce_kernel(int M, int N, const TC* __restrict__ P, int s
   C[i + j * ldc] = (TO)v;
 }
 
+// The same reduction for many splits (small outputs such as the l x l Gram
+// matrices of tall panels): a workgroup takes 64 consecutive outputs, wave
+// w sums the splits z = w, w + 4, ... with four loads in flight, and the four
+// wave sums are added in a fixed order.
+constexpr int kRedWide = 8;  // splits from which the wide reduction is used
+
+template <typename TC, typename TO>
+__global__ __launch_bounds__(256) void gemm_reduce_wide_kernel(int M, int N, const TC* __restrict__ P,
+                                                               int splits, double alpha, double beta,
+                                                               TO* __restrict__ C, int64_t ldc) {
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t MN = (int64_t)M * N;
+  const int64_t o = (int64_t)blockIdx.x * 64 + lane;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (o < MN) {
+    int z = wave;
+    for (; z + 12 < splits; z += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] += (double)P[(int64_t)(z + 4 * u) * MN + o];
+    }
+    for (; z < splits; z += 4) s[0] += (double)P[(int64_t)z * MN + o];
+  }
+  part[wave][lane] = (s[0] + s[1]) + (s[2] + s[3]);
+  __syncthreads();
+  if (wave == 0 && o < MN) {
+    const double acc = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+    const int64_t i = o % M, j = o / M;
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * (double)C[i + j * ldc];
+    C[i + j * ldc] = (TO)v;
+  }
+}
+
+template <typename TC, typename TO>
+void launch_gemm_reduce(const rmm_ctx* h, int M, int N, const TC* P, int splits, double alpha, double beta,
+                        TO* C, int64_t ldc) {
+  if (splits >= kRedWide) {
+    const int64_t blocks = ((int64_t)M * N + 63) / 64;
+    hipLaunchKernelGGL((gemm_reduce_wide_kernel<TC, TO>), dim3((unsigned)blocks), dim3(256), 0, h->stream,
+                       M, N, P, splits, alpha, beta, C, ldc);
+  } else {
+    dim3 grid((unsigned)((M + 255) / 256), (unsigned)N);
+    hipLaunchKernelGGL((gemm_reduce_kernel<TC, TO>), grid, dim3(256), 0, h->stream, M, N, P, splits, alpha,
+                       beta, C, ldc);
+  }
+}
+
 namespace {
 
 struct GemmShape {
@@ -486,9 +534,7 @@ int gemm_plan(rmm_ctx* h, int plan, bool ta, bool tb, int M, int N, int64_t K, c
     ws.off = mark;
     return RMM_OK;
   }
-  dim3 grid((unsigned)((M + 255) / 256), (unsigned)N);
-  hipLaunchKernelGGL((gemm_reduce_kernel<TC, TO>), grid, dim3(256), 0, h->stream, M, N, P, g.splits,
-                     alpha, beta, C, ldc);
+  launch_gemm_reduce<TC, TO>(h, M, N, P, g.splits, alpha, beta, C, ldc);
   ws.off = mark;  // the partials are dead once the reduction is enqueued
   return launch_status();
 }
