@@ -368,16 +368,6 @@ __device__ __forceinline__ void rr_pair(int i, int r, int L, int& p, int& q) {
 // (levels Q = P, P/2, ..., 1: P + P/2 + ... + 1 = L - 1 rounds) meets
 // every pair exactly once, while a group reads and writes only one column
 // per round.
-__device__ __forceinline__ void hier_pair(int i, int r, int L, int& p, int& q) {
-  int Q = L / 2, u = r;
-  while (u >= Q) {
-    u -= Q;
-    Q >>= 1;
-  }
-  const int b = i / Q, j = i & (Q - 1);
-  p = 2 * Q * b + j;
-  q = 2 * Q * b + Q + ((j + u) & (Q - 1));
-}
 
 __host__ __device__ inline int pow2_ceil(int l) {
   int L = 2;
@@ -551,13 +541,12 @@ __global__ __launch_bounds__(kSmallThreads) void jacobi_kernel(int l, const doub
 // One wave owns kVecRows rows of V in LDS; lane i applies pair i of every
 // round to those rows (the pairs of a round are disjoint, and one wave's LDS
 // accesses are performed in program order, so no barrier is needed).
-template <bool HIER>
 __global__ __launch_bounds__(256) void jacobi_vectors_kernel(int l, const double2* __restrict__ rlog,
                                                              const int* __restrict__ nrounds,
                                                              const int* __restrict__ perm,
                                                              double* __restrict__ Vout) {
   extern __shared__ double vs[];  // 4 waves x kVecRows x L, then the pair tables
-  const int L = HIER ? pow2_ceil(l) : (l + 1) & ~1;
+  const int L = (l + 1) & ~1;
   const int npairs = L / 2;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* V = vs + (size_t)wave * kVecRows * L;
@@ -565,10 +554,7 @@ __global__ __launch_bounds__(256) void jacobi_vectors_kernel(int l, const double
   unsigned char* qtab = ptab + (size_t)(L - 1) * npairs;
   for (int e = threadIdx.x; e < (L - 1) * npairs; e += blockDim.x) {
     int p, q;
-    if (HIER)
-      hier_pair(e % npairs, e / npairs, L, p, q);
-    else
-      rr_pair(e % npairs, e / npairs, L, p, q);
+    rr_pair(e % npairs, e / npairs, L, p, q);
     ptab[e] = (unsigned char)p;
     qtab[e] = (unsigned char)q;
   }
@@ -614,6 +600,108 @@ __global__ __launch_bounds__(256) void jacobi_vectors_kernel(int l, const double
     const int k = row0 + rr;
     if (k >= l) break;
     for (int rank = lane; rank < l; rank += 64) Vout[k + (int64_t)rank * l] = V[rr * L + perm[rank]];
+  }
+}
+
+// J = J_1 J_2 ... from the log of osj_kernel; Jout[:, rank] = J[:, perm[rank]].
+// Rows of J are independent and follow the column movements of the
+// one-sided sweep itself: a wave holds kOsjVecRows rows, lane g the entries
+// of its rows at group g's resident (x) and traveller (y) columns.  A round
+// rotates (x, y) with group g's logged (cs, sn); inside a level the
+// travellers pass to the next lower group of their block by a lane shuffle
+// (no LDS round trip), and at a level's end the row is laid out in column
+// order in the wave's LDS row buffer and read back in the next level's
+// pairing.  The rounds of a sweep are therefore a chain of shuffles and
+// FMAs per wave, and the rows run in parallel over the workgroups.
+constexpr int kOsjVecRows = 2;
+
+__global__ __launch_bounds__(256) void osj_vectors_kernel(int l, const double2* __restrict__ rlog,
+                                                          const int* __restrict__ nrounds,
+                                                          const int* __restrict__ perm,
+                                                          double* __restrict__ Jout) {
+  __shared__ double buf[4][kOsjVecRows][kLdsMaxL];
+  const int L = pow2_ceil(l), P = L / 2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row0 = (blockIdx.x * 4 + wave) * kOsjVecRows;
+  if (row0 >= l) return;  // whole waves
+  const bool act = lane < P;
+  const int g = act ? lane : 0;
+  double x[kOsjVecRows], y[kOsjVecRows];
+#pragma unroll
+  for (int w = 0; w < kOsjVecRows; ++w) {
+    x[w] = row0 + w == g ? 1.0 : 0.0;
+    y[w] = row0 + w == P + g ? 1.0 : 0.0;
+    if (act) {  // column order, for a log without rounds
+      buf[wave][w][g] = x[w];
+      buf[wave][w][P + g] = y[w];
+    }
+  }
+  const int R = *nrounds;  // whole sweeps of L - 1 rounds
+  int Q = P, u = 0;        // level and round within it
+  constexpr int kPre = 16;  // rounds of the log in flight
+  double2 cur[kPre], nxt[kPre];
+#pragma unroll
+  for (int k = 0; k < kPre; ++k) cur[k] = k < R ? rlog[(size_t)k * P + g] : make_double2(1.0, 0.0);
+  for (int t0 = 0; t0 < R; t0 += kPre) {
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      const int t = t0 + kPre + k;
+      nxt[k] = t < R ? rlog[(size_t)t * P + g] : make_double2(1.0, 0.0);
+    }
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) {
+      if (t0 + k < R) {
+        const double c = cur[k].x, sn = cur[k].y;
+        if (sn != 0.0) {
+#pragma unroll
+          for (int w = 0; w < kOsjVecRows; ++w) {
+            const double xv = x[w], yv = y[w];
+            x[w] = c * xv - sn * yv;
+            y[w] = sn * xv + c * yv;
+          }
+        }
+        const int j = g & (Q - 1), b0 = g - j;  // block start b Q
+        if (u + 1 < Q) {
+          const int src = b0 + ((j + 1) & (Q - 1));
+#pragma unroll
+          for (int w = 0; w < kOsjVecRows; ++w) y[w] = __shfl(y[w], src);
+          ++u;
+        } else {
+          const int pc = 2 * b0 + j, qc = 2 * b0 + Q + ((j + Q - 1) & (Q - 1));
+          if (act) {
+#pragma unroll
+            for (int w = 0; w < kOsjVecRows; ++w) {
+              buf[wave][w][pc] = x[w];
+              buf[wave][w][qc] = y[w];
+            }
+          }
+          // one wave's LDS accesses are performed in program order
+          __builtin_amdgcn_wave_barrier();
+          Q = Q > 1 ? Q >> 1 : P;
+          u = 0;
+          const int j1 = g & (Q - 1);
+          const int pn = 2 * (g - j1) + j1, qn = pn + Q;
+          if (act) {
+#pragma unroll
+            for (int w = 0; w < kOsjVecRows; ++w) {
+              x[w] = buf[wave][w][pn];
+              y[w] = buf[wave][w][qn];
+            }
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kPre; ++k) cur[k] = nxt[k];
+  }
+  // R is a whole number of sweeps, so the last level end left every row in
+  // column order
+#pragma unroll
+  for (int w = 0; w < kOsjVecRows; ++w) {
+    const int k = row0 + w;
+    if (k >= l) break;
+    for (int rank = lane; rank < l; rank += 64) Jout[k + (int64_t)rank * l] = buf[wave][w][perm[rank]];
   }
 }
 
@@ -721,10 +809,10 @@ int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* ev
                      perm, rlog, nr, status, kJacobiMaxSweeps);
   RMM_TRY(launch_status());
   const size_t vlds = (size_t)4 * kVecRows * L * sizeof(double) + 2 * (size_t)(L - 1) * npairs;
-  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel<false>,
+  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
   const int groups = (l + 4 * kVecRows - 1) / (4 * kVecRows);
-  hipLaunchKernelGGL(jacobi_vectors_kernel<false>, dim3(groups), dim3(256), vlds, h->stream, l, rlog,
+  hipLaunchKernelGGL(jacobi_vectors_kernel, dim3(groups), dim3(256), vlds, h->stream, l, rlog,
                      nr, perm, V);
   ws.off = mark;
   return launch_status();
@@ -745,7 +833,7 @@ int jacobi_eig(const rmm_ctx* h, int l, const double* G, int64_t ldg, double* ev
 //   cs = 1 / sqrt(1 + t^2),  sn = t cs,
 //   col_p <- cs col_p - sn col_q,  col_q <- sn col_p + cs col_q.
 // The (cs, sn) of every pair of every round go to a log from which
-// jacobi_vectors_kernel accumulates J.  A sweep without a rotation ends the
+// osj_vectors_kernel accumulates J.  A sweep without a rotation ends the
 // iteration (the columns are orthogonal to the test's precision).
 //
 // osj_kernel (l <= 128, one workgroup): the columns are padded with zeros to
@@ -1172,12 +1260,8 @@ static int osj_launch(const rmm_ctx* h, int rows, int l, const TI* M, int64_t ld
     RMM_TRY((osj_launch_r<TI, 4>(h, rows, l, M, ldm, sigma, perm, Ubar, rlog, nr, status)));
   else
     RMM_TRY((osj_launch_r<TI, 8>(h, rows, l, M, ldm, sigma, perm, Ubar, rlog, nr, status)));
-  const size_t vlds = (size_t)4 * kVecRows * L * sizeof(double) + 2 * (size_t)(L - 1) * P;
-  RMM_HIP(hipFuncSetAttribute((const void*)jacobi_vectors_kernel<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
-  const int groups = (l + 4 * kVecRows - 1) / (4 * kVecRows);
-  hipLaunchKernelGGL(jacobi_vectors_kernel<true>, dim3(groups), dim3(256), vlds, h->stream, l, rlog,
-                     nr, perm, J);
+  const int groups = (l + 4 * kOsjVecRows - 1) / (4 * kOsjVecRows);
+  hipLaunchKernelGGL(osj_vectors_kernel, dim3(groups), dim3(256), 0, h->stream, l, rlog, nr, perm, J);
   ws.off = mark;
   return launch_status();
 }
