@@ -43,9 +43,12 @@ struct Fp8Fmt {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-// One MFMA of each format: 16 x 16 outputs, K = 32 per instruction, each lane
-// holding 8 K-consecutive elements of one row of each operand (16 bytes for
-// BF16, gfx950's 16x16x32 BF16 MFMA; 8 bytes for FP8).
+// One MFMA of each format: 16 x 16 outputs; each lane holds K-consecutive
+// elements of one row of each operand, 16 bytes of BF16 (gfx950's 16x16x32
+// BF16 MFMA, K = 32) or 32 bytes of FP8 (gfx950's 16x16x128 f8f6f4 MFMA with
+// unit block scales, K = 128).  Both operands use the same lane-to-K
+// assignment, so the sum over K does not depend on the order in which the
+// instruction pairs them.
 template <typename F>
 struct QOp;
 template <>
@@ -58,11 +61,19 @@ struct QOp<Bf16Fmt> {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, y, c, 0, 0, 0);
   }
 };
+struct alignas(16) U8x32 {
+  uint4 lo, hi;
+};
+typedef int intx8 __attribute__((ext_vector_type(8)));
 template <>
 struct QOp<Fp8Fmt> {
-  using op_t = uint64_t;
-  static __device__ __forceinline__ floatx4 mfma(uint64_t a, uint64_t b, floatx4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8((long)a, (long)b, c, 0, 0, 0);
+  using op_t = U8x32;
+  static __device__ __forceinline__ floatx4 mfma(const U8x32& a, const U8x32& b, floatx4 c) {
+    intx8 x, y;
+    __builtin_memcpy(&x, &a, 32);
+    __builtin_memcpy(&y, &b, 32);
+    // formats e4m3 / e4m3, block scales 2^(127 - 127) = 1
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(x, y, c, 0, 0, 0, 127, 0, 127);
   }
 };
 
