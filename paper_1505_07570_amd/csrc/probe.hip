@@ -1,5 +1,5 @@
-// Streaming-read reference: reads a device buffer once with 16-byte loads,
-// sixteen in flight per lane, one contiguous range per workgroup, and writes
+// Streaming-read reference: reads a device buffer once with 16-byte
+// nontemporal loads, sixteen in flight per lane, one contiguous range per workgroup, and writes
 // one float per workgroup (so the loads cannot be dropped).  It is what every
 // HBM-bound pass of the library does with A, minus all arithmetic: its rate
 // is the practical read ceiling against which those passes are judged, next
@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void stream_read_kernel(const float4* __restri
 #pragma unroll
     for (int u = 0; u < kProbeUnroll; ++u) {
       const int64_t j = i + 256 * u;
-      v[u] = j < b1 ? x[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      v[u] = j < b1 ? ld_stream(x + j) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int u = 0; u < kProbeUnroll; ++u) acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);

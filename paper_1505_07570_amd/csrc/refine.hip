@@ -82,10 +82,10 @@ __global__ __launch_bounds__(kPassThreads) void normal_pass_kernel(
       const T* src = A + i + (int64_t)cc * lda;
       if (full && e < nvec) {
         if constexpr (sizeof(T) == 4) {
-          const float4 q = *reinterpret_cast<const float4*>(src);
+          const float4 q = ld_stream(reinterpret_cast<const float4*>(src));
           v[4 * u] = q.x; v[4 * u + 1] = q.y; v[4 * u + 2] = q.z; v[4 * u + 3] = q.w;
         } else {
-          const double2 q = *reinterpret_cast<const double2*>(src);
+          const double2 q = ld_stream(reinterpret_cast<const double2*>(src));
           v[2 * u] = q.x; v[2 * u + 1] = q.y;
         }
       } else {

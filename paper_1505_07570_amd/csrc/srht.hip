@@ -135,11 +135,11 @@ __device__ __forceinline__ void srht_body(const T* __restrict__ A, int64_t lda,
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         if constexpr (sizeof(T) == 4) {
-          const float4 q = *reinterpret_cast<const float4*>(p + 256 * k);
+          const float4 q = ld_stream(reinterpret_cast<const float4*>(p + 256 * k));
           x[4 * k] = q.x; x[4 * k + 1] = q.y; x[4 * k + 2] = q.z; x[4 * k + 3] = q.w;
         } else {
-          const double2 q0 = *reinterpret_cast<const double2*>(p + 256 * k);
-          const double2 q1 = *reinterpret_cast<const double2*>(p + 256 * k + 2);
+          const double2 q0 = ld_stream(reinterpret_cast<const double2*>(p + 256 * k));
+          const double2 q1 = ld_stream(reinterpret_cast<const double2*>(p + 256 * k + 2));
           x[4 * k] = q0.x; x[4 * k + 1] = q0.y; x[4 * k + 2] = q1.x; x[4 * k + 3] = q1.y;
         }
       }
