@@ -23,6 +23,7 @@
 namespace rmm {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
@@ -65,6 +66,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     int64_t ldq, T* __restrict__ partials) {
   using Cfg = GaussCfg<T>;
   using acc_t = typename Cfg::acc_t;
+  // fp32 with an even number of 16-column tiles: 32 x 32 x 2 MFMAs, each
+  // B operand value serving 32 sketch rows (half the instructions and half
+  // the B reads of the 16 x 16 x 4 form for the same flops)
+  constexpr bool W32 = sizeof(T) == 4 && NT % 2 == 0;
   constexpr int KS = Cfg::KS;
   constexpr int LDT = Cfg::LDT;
   constexpr int NCOL = NT * 16;              // columns of the MFMA tiles
@@ -90,10 +95,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (k1 > m) k1 = m;
 
   acc_t acc[2][NT];
+  floatx16 acc32[NT / 2 > 0 ? NT / 2 : 1];
+  if constexpr (W32) {
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+    for (int q = 0; q < NT / 2; ++q)
 #pragma unroll
-    for (int q = 0; q < NT; ++q) acc[t][q] = acc_t{0, 0, 0, 0};
+      for (int v = 0; v < 16; ++v) acc32[q][v] = 0.f;
+  } else {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int q = 0; q < NT; ++q) acc[t][q] = acc_t{0, 0, 0, 0};
+  }
+  const int lo = lane & 31, hi = lane >> 5;
 
   T stage_v[GPT][4];
   auto load_stage = [&](int64_t r0) {
@@ -243,7 +257,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     }
     // a wave whose 32 sketch rows all lie past s skips the MFMAs
-    if (wave_rows) {
+    if (wave_rows && W32) {
+      if constexpr (W32) {
+#pragma unroll
+        for (int ks = 0; ks < KS / 2; ++ks) {
+          const float a = om[b][(2 * ks + hi) * 128 + 32 * wave + lo];
+          const float* tb = &tile[b][lo * LDT + 2 * ks + hi];
+#pragma unroll
+          for (int q = 0; q < NT / 2; ++q)
+            acc32[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, tb[q * 32 * LDT], acc32[q], 0, 0, 0);
+        }
+      }
+    } else if (wave_rows) {
 #pragma unroll
       for (int ks = 0; ks < KS / 4; ++ks) {
         const T a0 = om[b][(4 * ks + kk) * 128 + arow];
@@ -274,17 +299,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       if (xh == 0 && r < s) dst[(int64_t)(nbase + NCOL) * s + r] = xacc + om[0][xr];
     }
   }
+  if constexpr (W32) {
+    // register v of the 32 x 32 result holds row 8 (v / 4) + 4 hi + v % 4,
+    // column lo
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+    for (int q = 0; q < NT / 2; ++q) {
+      const int64_t j = nbase + q * 32 + lo;
 #pragma unroll
-    for (int q = 0; q < NT; ++q) {
-      const int64_t j = nbase + q * 16 + mi;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = mblk + 32 * wave + 16 * t + mfma_row(T(0), kk, v);
-        if (j < ncols && r < s) dst[j * s + r] = acc[t][q][v];
+      for (int v = 0; v < 16; ++v) {
+        const int r = mblk + 32 * wave + 8 * (v >> 2) + 4 * hi + (v & 3);
+        if (j < ncols && r < s) dst[j * s + r] = acc32[q][v];
       }
     }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int q = 0; q < NT; ++q) {
+        const int64_t j = nbase + q * 16 + mi;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = mblk + 32 * wave + 16 * t + mfma_row(T(0), kk, v);
+          if (j < ncols && r < s) dst[j * s + r] = acc[t][q][v];
+        }
+      }
+  }
 }
 
 // TRANS: write C^T (C[j + r * ldc]) instead of C
