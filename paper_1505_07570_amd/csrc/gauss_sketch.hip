@@ -326,17 +326,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
-// TRANS: write C^T (C[j + r * ldc]) instead of C
+// TRANS: write C^T (C[j + r * ldc]) instead of C; beta != 0 adds beta C
 template <typename T, bool TRANS>
 __global__ void splitk_reduce_kernel(const T* __restrict__ partials, int splits, int64_t plane,
-                                     double scale, int s, T* __restrict__ C, int64_t ldc) {
+                                     double scale, double beta, int s, T* __restrict__ C, int64_t ldc) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t j = blockIdx.y;
   if (r >= s) return;
   double acc = 0.0;
   for (int p = 0; p < splits; ++p) acc += (double)partials[p * plane + j * s + r];
-  if (TRANS) C[j + r * ldc] = (T)(acc * scale);
-  else C[r + j * ldc] = (T)(acc * scale);
+  T* dst = TRANS ? C + j + r * ldc : C + r + j * ldc;
+  double v = acc * scale;
+  if (beta != 0.0) v += beta * (double)*dst;
+  *dst = (T)v;
 }
 
 namespace {
@@ -418,15 +420,18 @@ size_t gauss_sketch_workspace(const rmm_ctx* h, int64_t m, int ncols, int64_t s)
 
 namespace {
 
-// C (s x ncols, or its transpose) = scale * L^T [A | b], L = Qm (m x s) when
-// given, else Omega of stream `tag`.
+// C (s x ncols, or its transpose) = scale * L^T [A | b] + beta C, L = Qm
+// (m x s) when given, else Omega of stream `tag`.
 template <typename T>
 int project_any(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b, int64_t s,
                 uint32_t tag, uint64_t seed, const T* Qm, int64_t ldq, double scale, T* C,
-                int64_t ldc, bool trans, Carver& ws) {
+                int64_t ldc, bool trans, Carver& ws, double beta = 0.0) {
   const int ncols = n + (b ? 1 : 0);
   if (ncols == 0) return RMM_OK;
-  if (m == 0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
+  if (m == 0) {
+    if (beta == 0.0) return launch_fill_zero<T>(C, s, ncols, ldc, h->stream);
+    return beta == 1.0 ? RMM_OK : RMM_ERR_UNSUPPORTED;
+  }
   const GaussShape g = gauss_shape<T>(h, m, ncols, (int)s);
   const size_t mark = ws.off;  // the partials are released on return
   T* partials = ws.take<T>((size_t)g.splits * ncols * s);
@@ -456,10 +461,10 @@ int project_any(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* 
   dim3 grid((unsigned)((s + 255) / 256), (unsigned)ncols);
   if (trans)
     hipLaunchKernelGGL((splitk_reduce_kernel<T, true>), grid, dim3(256), 0, h->stream, partials, g.splits,
-                       (int64_t)ncols * s, scale, (int)s, C, ldc);
+                       (int64_t)ncols * s, scale, beta, (int)s, C, ldc);
   else
     hipLaunchKernelGGL((splitk_reduce_kernel<T, false>), grid, dim3(256), 0, h->stream, partials, g.splits,
-                       (int64_t)ncols * s, scale, (int)s, C, ldc);
+                       (int64_t)ncols * s, scale, beta, (int)s, C, ldc);
   ws.off = mark;
   return launch_status();
 }
@@ -474,12 +479,13 @@ int gauss_project(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T
   return project_any<T>(h, m, n, A, lda, b, s, tag, seed, nullptr, 0, scale, C, ldc, false, ws);
 }
 
-// Z (ncols x s, ld ldz) = A^T Qm for A (m x ncols) and Qm (m x s): the same
-// kernel with the stored matrix as its left operand, written transposed.
+// Z (ncols x s, ld ldz) = A^T Qm + beta Z for A (m x ncols) and Qm (m x s):
+// the same kernel with the stored matrix as its left operand, written
+// transposed.
 template <typename T>
 int project_tn(rmm_ctx* h, int64_t m, int ncols, const T* A, int64_t lda, const T* Qm, int64_t ldq,
-               int64_t s, T* Z, int64_t ldz, Carver& ws) {
-  return project_any<T>(h, m, ncols, A, lda, nullptr, s, 0, 0, Qm, ldq, 1.0, Z, ldz, true, ws);
+               int64_t s, T* Z, int64_t ldz, Carver& ws, double beta) {
+  return project_any<T>(h, m, ncols, A, lda, nullptr, s, 0, 0, Qm, ldq, 1.0, Z, ldz, true, ws, beta);
 }
 
 template <typename T>
@@ -496,9 +502,9 @@ template int gauss_sketch_run<float>(rmm_ctx*, int64_t, int, const float*, int64
 template int gauss_sketch_run<double>(rmm_ctx*, int64_t, int, const double*, int64_t,
                                       const double*, int64_t, uint64_t, double*, int64_t, Carver&);
 template int project_tn<float>(rmm_ctx*, int64_t, int, const float*, int64_t, const float*, int64_t,
-                               int64_t, float*, int64_t, Carver&);
+                               int64_t, float*, int64_t, Carver&, double);
 template int project_tn<double>(rmm_ctx*, int64_t, int, const double*, int64_t, const double*, int64_t,
-                                int64_t, double*, int64_t, Carver&);
+                                int64_t, double*, int64_t, Carver&, double);
 template int gauss_project<float>(rmm_ctx*, int64_t, int, const float*, int64_t, const float*,
                                   int64_t, uint32_t, uint64_t, double, float*, int64_t, Carver&);
 template int gauss_project<double>(rmm_ctx*, int64_t, int, const double*, int64_t, const double*,

@@ -184,10 +184,15 @@ int nystrom_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx, doubl
 
 // ---- Gaussian-projection variant: C = K Omega, W = Omega^T C ----------------------------
 //
-// K (n x n) exists only as tiles of at most kKRows x kKCols entries, written
-// by the RBF kernel into the workspace and multiplied into C by the MFMA
-// GEMM with accumulation (C += K_tile Omega[cols, :]).  Omega (n x c fp32,
-// stream tag 7) is generated once into the workspace.
+// K (n x n) exists only as blocks of at most kKCols x kKRows entries, written
+// by the RBF kernel into the workspace and multiplied into C with
+// accumulation: C[rows, :] += K[rows, cols] Omega[cols, :], computed as the
+// transposed product (K[cols, rows])^T Omega[cols, :] of the sketch kernel
+// with a stored left operand (its 128 x 256 tiles and 32 x 32 MFMAs run
+// closer to the FP32 MFMA rate than the plain GEMM on this shape; K is
+// symmetric, and its block K[cols, rows] holds the same values bit for bit,
+// the squared differences being symmetric).  Omega (n x c fp32, stream tag
+// 7) is generated once into the workspace.
 constexpr int64_t kKRows = 32768;
 constexpr int64_t kKCols = 8192;
 
@@ -206,7 +211,7 @@ size_t nystrom_gauss_layout(const rmm_ctx* h, int64_t n, int c, int k, Carver& w
   if (b) *b = NysBufs{W, V, F};
   size_t scratch = jacobi_workspace(c);
   scratch = scratch > gemm_workspace<float>(h, (int)n, k, c) ? scratch : gemm_workspace<float>(h, (int)n, k, c);
-  const size_t g1 = gemm_workspace<float>(h, (int)br, c, bc);
+  const size_t g1 = gauss_sketch_workspace<float>(h, bc, (int)br, c);
   const size_t g2 = gemm_workspace<double>(h, c, c, n);
   scratch = scratch > g1 ? scratch : g1;
   scratch = scratch > g2 ? scratch : g2;
@@ -236,11 +241,11 @@ int nystrom_gauss_run(rmm_ctx* h, int64_t n, int d, const float* X, int64_t ldx,
     const int64_t rows = (n - i0) < br ? (n - i0) : br;
     for (int64_t l0 = 0; l0 < n; l0 += bc) {
       const int64_t cols = (n - l0) < bc ? (n - l0) : bc;
-      // K[i0:i0+rows, l0:l0+cols] (rows x cols, ld rows)
-      RMM_TRY(launch_rbf(h, rows, d, X + i0 * ldx, ldx, (int)cols, nullptr, X, ldx, l0, g, Kt, rows));
-      // C[i0:, :] (+)= K_tile Omega[l0:l0+cols, :]
-      RMM_TRY((gemm<float, float, float, float>(h, false, false, (int)rows, c, cols, Kt, rows, Om + l0, n,
-                                                1.0, C + i0, ldc, ws, l0 == 0 ? 0.0 : 1.0)));
+      // K[l0:l0+cols, i0:i0+rows] (cols x rows, ld cols)
+      RMM_TRY(launch_rbf(h, cols, d, X + l0 * ldx, ldx, (int)rows, nullptr, X, ldx, i0, g, Kt, cols));
+      // C[i0:, :] (+)= K[l0:, i0:]^T Omega[l0:l0+cols, :]
+      RMM_TRY(project_tn<float>(h, cols, (int)rows, Kt, cols, Om + l0, n, c, C + i0, ldc, ws,
+                                l0 == 0 ? 0.0 : 1.0));
     }
   }
   // W = Omega^T C (c x c, fp64)

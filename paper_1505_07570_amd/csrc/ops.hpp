@@ -45,11 +45,12 @@ template <typename T>
 int gauss_project(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* b,
                   int64_t s, uint32_t tag, uint64_t seed, double scale, T* C, int64_t ldc,
                   Carver& ws);
-// Z (ncols x s, ld ldz) = A^T Qm (A m x ncols, Qm m x s): the same kernel with a
-// stored left operand; workspace gauss_sketch_workspace<T>(h, m, ncols, s).
+// Z (ncols x s, ld ldz) = A^T Qm + beta Z (A m x ncols, Qm m x s): the same
+// kernel with a stored left operand; workspace gauss_sketch_workspace<T>(h, m,
+// ncols, s).
 template <typename T>
 int project_tn(rmm_ctx* h, int64_t m, int ncols, const T* A, int64_t lda, const T* Qm, int64_t ldq,
-               int64_t s, T* Z, int64_t ldz, Carver& ws);
+               int64_t s, T* Z, int64_t ldz, Carver& ws, double beta = 0.0);
 
 // Machine-precision LSR iterations (refine.hip): one fused pass over A giving
 // per-workgroup partials of A^T r and ||r||^2 for r = [b] - A p (G = refine_groups
