@@ -326,7 +326,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
-// TRANS: write C^T (C[j + r * ldc]) instead of C; beta != 0 adds beta C
+// C[r + j * ldc] (TRANS: C[j + r * ldc]) = scale * (sum of the split
+// partials) + beta C
 template <typename T, bool TRANS>
 __global__ void splitk_reduce_kernel(const T* __restrict__ partials, int splits, int64_t plane,
                                      double scale, double beta, int s, T* __restrict__ C, int64_t ldc) {
@@ -339,6 +340,38 @@ __global__ void splitk_reduce_kernel(const T* __restrict__ partials, int splits,
   double v = acc * scale;
   if (beta != 0.0) v += beta * (double)*dst;
   *dst = (T)v;
+}
+
+// The transposed form for wide outputs (s >= 512) through a 64 x 64 LDS
+// tile: the partials are read along r and C is written along j, both
+// contiguous (the kernel above writes C^T with a stride of ldc between
+// neighbouring threads); the splits are summed in the same order.
+template <typename T>
+__global__ __launch_bounds__(256) void splitk_reduce_t_kernel(const T* __restrict__ partials, int splits,
+                                                              int64_t plane, double scale, double beta, int s,
+                                                              int ncols, T* __restrict__ C, int64_t ldc) {
+  __shared__ double tile[64][65];
+  const int r0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+  for (int k = 0; k < 16; ++k) {
+    const int j = j0 + ty + 4 * k, r = r0 + tx;
+    double acc = 0.0;
+    if (r < s && j < ncols)
+      for (int p = 0; p < splits; ++p) acc += (double)partials[p * plane + (int64_t)j * s + r];
+    tile[ty + 4 * k][tx] = acc;
+  }
+  __syncthreads();
+#pragma unroll 4
+  for (int k = 0; k < 16; ++k) {
+    const int r = r0 + ty + 4 * k, j = j0 + tx;
+    if (r < s && j < ncols) {
+      T* dst = C + j + (int64_t)r * ldc;
+      double v = tile[tx][ty + 4 * k] * scale;
+      if (beta != 0.0) v += beta * (double)*dst;
+      *dst = (T)v;
+    }
+  }
 }
 
 namespace {
@@ -459,7 +492,11 @@ int project_any(rmm_ctx* h, int64_t m, int n, const T* A, int64_t lda, const T* 
   }
   RMM_TRY(rc);
   dim3 grid((unsigned)((s + 255) / 256), (unsigned)ncols);
-  if (trans)
+  if (trans && s >= 512)
+    hipLaunchKernelGGL((splitk_reduce_t_kernel<T>), dim3((unsigned)((s + 63) / 64), (unsigned)((ncols + 63) / 64)),
+                       dim3(256), 0, h->stream, partials, g.splits, (int64_t)ncols * s, scale, beta, (int)s,
+                       ncols, C, ldc);
+  else if (trans)
     hipLaunchKernelGGL((splitk_reduce_kernel<T, true>), grid, dim3(256), 0, h->stream, partials, g.splits,
                        (int64_t)ncols * s, scale, beta, (int)s, C, ldc);
   else
