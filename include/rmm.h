@@ -112,8 +112,8 @@ int rmm_autotune_load(rmm_handle h, const char* path);
 int rmm_set_kernel_timing(rmm_handle h, int on);
 int rmm_kernel_time(rmm_handle h, float* ms);
 /* Measurement hook (no section of the paper): reads `bytes` of device memory
- * at x once with 16-byte loads, the access pattern of the library's
- * HBM-bound passes without their arithmetic, and writes 4096 floats (one
+ * at x once with 16-byte nontemporal loads, the access pattern of the
+ * library's HBM-bound passes without their arithmetic, and writes 4096 floats (one
  * partial sum per workgroup) to the device buffer sink.  Its rate is the
  * practical HBM read ceiling that the bench reports beside the rated peak.
  * Requires bytes >= 16, bytes and x multiples of 16.  Asynchronous on the
