@@ -530,7 +530,7 @@ def main():
     h.set_kernel_timing(False)
 
     # practical HBM read ceiling: one streaming read of [A | b]'s bytes
-    # (rmm_stream_read: the sketches' 16-byte load pattern, no arithmetic)
+    # (rmm_stream_read: the sketches' 16-byte nontemporal load pattern, no arithmetic)
     probe = torch.empty(ab_bytes // 16 * 4, dtype=torch.float32, device="cuda")
     sink = torch.empty(4096, dtype=torch.float32, device="cuda")
     h.stream_read(probe, sink)
@@ -579,8 +579,8 @@ def main():
         "kernel_ms": kernel_ms,
         "sketch_gbs": {k: ab_bytes / (sketch_ms[k] * 1e-3) / 1e9 for k in kinds},
         "hbm_read_reference": {"GB/s": read_gbs, "frac_of_peak": read_gbs / HBM_PEAK_GBS,
-                               "what": "rmm_stream_read of the bytes of [A | b]: 16-byte loads, "
-                                       "no arithmetic"},
+                               "what": "rmm_stream_read of the bytes of [A | b]: 16-byte "
+                                       "nontemporal loads, no arithmetic"},
         "data_gen_s": gen_s,
     }
 
