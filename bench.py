@@ -275,6 +275,7 @@ def serving_leg(count, factors=(1.0,)):
 
     _, _, wall_sat = serve.run_plain(reqs, np.zeros(count), make, on_done=drop)
     rate = count / wall_sat
+    print(f"serving: plain saturation {rate:.1f} solves/s", file=sys.stderr, flush=True)
     budget = int(200e9 * count / 10000)
     req_bytes = sum(4 * q["m"] * q["n"] for q in reqs)
 
@@ -288,8 +289,10 @@ def serving_leg(count, factors=(1.0,)):
     for f in factors:
         arrivals = synth.poisson_arrivals(count, f * rate)
         _, lat_p, wall_p = serve.run_plain(reqs, arrivals, make, on_done=drop)
+        print(f"serving: {f:g}x plain done ({wall_p:.1f} s)", file=sys.stderr, flush=True)
         srv = serve.Server(budget, streams=4)
         _, lat_s, wall_s = srv.run(reqs, arrivals, make, on_done=drop)
+        print(f"serving: {f:g}x served done ({wall_s:.1f} s)", file=sys.stderr, flush=True)
         out["by_arrival_rate"][f"{f:g}x"] = {
             "arrival_rate_per_s": f * rate, "plain_one_at_a_time": summary(lat_p, wall_p),
             "served": summary(lat_s, wall_s), "peak_admitted_bytes": srv.peak_bytes,
