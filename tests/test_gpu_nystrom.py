@@ -123,7 +123,8 @@ def test_nystrom_invalid(h):
         h.nystrom(Xw, 1.0, 10, 1)          # d > 64
 
 
-@pytest.mark.parametrize("n,d,c,k", [(3000, 32, 64, 8), (9000, 8, 32, 6), (2500, 16, 200, 12)])
+@pytest.mark.parametrize("n,d,c,k", [(3000, 32, 64, 8), (9000, 8, 32, 6), (2500, 16, 200, 12),
+                                     (9000, 8, 600, 6)])
 def test_nystrom_gaussian_parity(h, n, d, c, k):
     """C = K Omega and W = Omega^T C against the oracle (fp32 Omega on both
     sides); W is formed from the fp32 C, so its eigenvalues carry C's
