@@ -854,8 +854,8 @@ constexpr int kDppRowMirror = 0x140;
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -874,17 +874,26 @@ __device__ __forceinline__ double group_sum(double v, int gl2) {
 // rotation of the pair with squared norms a, b and inner product c; false
 // when the pair already passes the orthogonality test
 __device__ __forceinline__ bool osj_rotation(double a, double b, double c, double tol2, double& cs,
-                                             double& sn) {
+                                             double& sn, double& tc) {
   cs = 1.0;
   sn = 0.0;
+  tc = 0.0;
   if (!(fabs(c) > 1e-300) || !(c * c > tol2 * a * b)) return false;
-  const double zeta = (b - a) * recip_f64(2.0 * c);
-  const double az = fabs(zeta);
-  const double w = az * az + 1.0;
-  const double den = az > 0x1p26 ? 2.0 * az : az + w * rsqrt_f64(w);
-  const double t = (zeta >= 0 ? 1.0 : -1.0) * recip_f64(den);
-  cs = rsqrt_f64(t * t + 1.0);
-  sn = t * cs;
+  // with d = b - a, e = 2c, h = sqrt(d^2 + e^2) and g = |d| + h the tangent
+  // is t = sign(d) e / g, so cs = g / sqrt(2 h g) and sn = sign(d) e / sqrt(2 h g);
+  // d and e are first scaled by a power of two to keep d^2 + e^2 in range
+  const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(b - a), fabs(2.0 * c)));
+  const double d = __builtin_amdgcn_ldexp(b - a, -ex);
+  const double e = __builtin_amdgcn_ldexp(2.0 * c, -ex);
+  const double h2 = fma(d, d, e * e);
+  const double h = h2 * rsqrt_f64(h2);
+  const double g = fabs(d) + h;
+  const double r = rsqrt_f64((h + h) * g);
+  cs = g * r;
+  sn = (d >= 0 ? e : -e) * r;
+  // t c with t = sn / cs = sign(d) e / g = sign(d) e 2 h r^2: the rotated
+  // squared norms are a - t c and b + t c
+  tc = sn * (h + h) * r * c;
   return true;
 }
 
@@ -906,6 +915,24 @@ __device__ __forceinline__ void row16_sum3(double& a, double& b, double& c) {
   c += dpp_f64<kDppRowMirror>(c);
 }
 
+__device__ __forceinline__ void row16_sum2(double& a, double& b) {
+  a += dpp_f64<kDppQuad1032>(a);
+  b += dpp_f64<kDppQuad1032>(b);
+  a += dpp_f64<kDppQuad2301>(a);
+  b += dpp_f64<kDppQuad2301>(b);
+  a += dpp_f64<kDppRowHalfMirror>(a);
+  b += dpp_f64<kDppRowHalfMirror>(b);
+  a += dpp_f64<kDppRowMirror>(a);
+  b += dpp_f64<kDppRowMirror>(b);
+}
+
+__device__ __forceinline__ double row16_sum1(double c) {
+  c += dpp_f64<kDppQuad1032>(c);
+  c += dpp_f64<kDppQuad2301>(c);
+  c += dpp_f64<kDppRowHalfMirror>(c);
+  return c + dpp_f64<kDppRowMirror>(c);
+}
+
 // One group of 16 lanes per pair; lane t holds rows t, t + 16, ...,
 // t + 16 (R - 1) of its two columns.  In LDS every column has 16 R entries
 // (rows past `rows` are zero and stay zero under rotations), so the round
@@ -925,6 +952,7 @@ __global__ __launch_bounds__(kSmallThreads) void osj_kernel(int rows, int l, con
   constexpr int LD = R == 1 ? 16 : 16 * R + 16;
   extern __shared__ double S[];
   __shared__ double nrm[kLdsMaxL];
+  __shared__ double cn[kLdsMaxL];  // squared column norms, moved like the columns
   __shared__ int sperm[kLdsMaxL];
   __shared__ int rotated[2];
   const int L = pow2_ceil(l);
@@ -942,38 +970,69 @@ __global__ __launch_bounds__(kSmallThreads) void osj_kernel(int rows, int l, con
   const double tol2 = (double)l * 0x1p-104;
   int rounds = 0, sweep = 0;
   bool conv = false;
+  // squared norms of the resident (na) and the traveller (nb) column: exact
+  // at the start of every sweep, then carried through the rotations (a - t c
+  // and b + t c) and summed again when one of them drops below an eighth of
+  // its value before the rotation, where the difference would cancel; only
+  // the inner product is summed every round
+  double na = 0.0, nb = 0.0;
   for (; sweep < max_sweeps && !conv; ++sweep) {
     const int fl = sweep & 1;
+    na = 0.0;
+    nb = 0.0;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      na = fma(x[k], x[k], na);
+      nb = fma(y[k], y[k], nb);
+    }
+    row16_sum2(na, nb);
     for (int Q = P; Q >= 1; Q >>= 1) {
       const int b = grp / Q, j = grp & (Q - 1);
       for (int u = 0; u < Q; ++u, ++rounds) {
-        double a = 0.0, bb = 0.0, c = 0.0;
+        double c = 0.0;
 #pragma unroll
-        for (int k = 0; k < R; ++k) {
-          a = fma(x[k], x[k], a);
-          bb = fma(y[k], y[k], bb);
-          c = fma(x[k], y[k], c);
-        }
-        row16_sum3(a, bb, c);
-        double cs, sn;
-        if (osj_rotation(a, bb, c, tol2, cs, sn)) {
+        for (int k = 0; k < R; ++k) c = fma(x[k], y[k], c);
+        c = row16_sum1(c);
+        double cs, sn, tc;
+        const bool rot = osj_rotation(na, nb, c, tol2, cs, sn, tc);
+        // a pair that does not rotate has (cs, sn) = (1, 0), whose update
+        // reproduces its columns exactly; the wave skips the update only when
+        // none of its pairs rotates
+        if (__any(rot)) {
 #pragma unroll
           for (int k = 0; k < R; ++k) {
             const double xv = x[k], yv = y[k];
-            x[k] = cs * xv - sn * yv;
-            y[k] = sn * xv + cs * yv;
+            x[k] = fma(cs, xv, -sn * yv);
+            y[k] = fma(sn, xv, cs * yv);
           }
-          if (t == 0) rotated[fl] = 1;
+          const double na1 = na - tc, nb1 = nb + tc;
+          if (__any(na1 < 0.125 * na || nb1 < 0.125 * nb)) {
+            na = 0.0;
+            nb = 0.0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+              na = fma(x[k], x[k], na);
+              nb = fma(y[k], y[k], nb);
+            }
+            row16_sum2(na, nb);
+          } else {
+            na = na1;
+            nb = nb1;
+          }
         }
+        if (rot && t == 0) rotated[fl] = 1;
         if (t == 0) rlog[(size_t)rounds * P + grp] = make_double2(cs, sn);
         if (u + 1 < Q) {
           double* buf = S + (size_t)(rounds & 1) * P * LD;
+          double* nbuf = cn + (rounds & 1) * P;
           const int dst = b * Q + ((j + Q - 1) & (Q - 1));
 #pragma unroll
           for (int k = 0; k < R; ++k) buf[dst * LD + t + 16 * k] = y[k];
+          if (t == 0) nbuf[dst] = nb;
           lds_barrier();
 #pragma unroll
           for (int k = 0; k < R; ++k) y[k] = buf[grp * LD + t + 16 * k];
+          nb = nbuf[grp];
         }
       }
       // end of the level: every column to its place (after the last
@@ -984,6 +1043,10 @@ __global__ __launch_bounds__(kSmallThreads) void osj_kernel(int rows, int l, con
       for (int k = 0; k < R; ++k) {
         S[pc * LD + t + 16 * k] = x[k];
         S[qc * LD + t + 16 * k] = y[k];
+      }
+      if (t == 0) {
+        cn[pc] = na;
+        cn[qc] = nb;
       }
       lds_barrier();
       if (Q == 1) conv = rotated[fl] == 0;  // every flag of the sweep is set by now
@@ -996,6 +1059,8 @@ __global__ __launch_bounds__(kSmallThreads) void osj_kernel(int rows, int l, con
         x[k] = S[pn * LD + t + 16 * k];
         y[k] = S[qn * LD + t + 16 * k];
       }
+      na = cn[pn];
+      nb = cn[qn];
       lds_barrier();
       if (Q == 1 && tid == 0) rotated[fl] = 0;  // read by all before the barrier above
     }
@@ -1100,8 +1165,8 @@ __global__ __launch_bounds__(256) void osj_big_round_kernel(int l, int L, int r,
   a = group_sum(a, 6);
   b = group_sum(b, 6);
   c = group_sum(c, 6);
-  double cs, sn;
-  if (osj_rotation(a, b, c, (double)l * 0x1p-104, cs, sn)) {
+  double cs, sn, tc;
+  if (osj_rotation(a, b, c, (double)l * 0x1p-104, cs, sn, tc)) {
 #pragma unroll
     for (int k = 0; k < kOsjBigRows; ++k) {
       const int i = lane + 64 * k;
